@@ -1,0 +1,603 @@
+"""Pins of the CPU FP64 oracle against facts fixed outside the oracle itself.
+
+Each test checks one part of the oracle against a published value, a closed
+form, a brute-force enumeration, an independent library implementation or an
+invariant that the paper's definitions imply, so that a dropped term, a wrong
+sign or index, or a transposed operand in the oracle fails here.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.special import logsumexp
+
+import oracle as O
+from paper_2312_08684_amd import scenarios as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold_rows(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# Counter-based RNG (only used for the predictive initial particles)
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    for row in _gold_rows("philox4x32_10_kat.txt"):
+        v = [int(x, 16) for x in row]
+        out = O.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_box_muller_normals_moments():
+    zs = np.array([O.normals(1234, 0, 1, i, 8) for i in range(4000)]).reshape(-1)
+    n = zs.size
+    assert abs(zs.mean()) < 5 / math.sqrt(n)
+    assert abs(zs.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    # Kolmogorov-Smirnov against the standard normal
+    assert stats.kstest(zs, "norm").pvalue > 1e-4
+    # distinct counters give distinct streams; the key separates seeds
+    assert not np.allclose(O.normals(1, 0, 1, 0, 4), O.normals(1, 0, 1, 1, 4))
+    assert not np.allclose(O.normals(1, 0, 1, 0, 4), O.normals(2, 0, 1, 0, 4))
+    assert not np.allclose(O.normals(1, 0, 1, 0, 4), O.normals(1, 1, 1, 0, 4))
+
+
+# ---------------------------------------------------------------------------
+# Models (eq. SSM and the scenario models)
+# ---------------------------------------------------------------------------
+
+def _all_models():
+    return {name: S._model_for(name, 0) for name in ("growth1d", "range2d", "cv4d", "arm7", "lingauss")}
+
+
+def _independent_loglik(desc, z, mask, x):
+    """Observation log-likelihoods assembled from scipy's densities."""
+    p = desc.params
+    on = (lambda o: True) if mask is None else (lambda o: bool(mask[o]))
+    if desc.kind == S.GROWTH1D:
+        return stats.norm.logpdf(z[0], p[5] * x[0] ** 2, math.sqrt(p[6])) if on(0) else 0.0
+    if desc.kind == S.RANGE2D:
+        nb = int(p[1])
+        bc = p[2:2 + 2 * nb].reshape(nb, 2)
+        r = np.linalg.norm(x[None, :] - bc, axis=1)
+        return sum(stats.norm.logpdf(z[b], r[b], math.sqrt(p[0])) for b in range(nb) if on(b))
+    if desc.kind == S.CV4D:
+        rv, pd, V = p[1], p[2], p[3]
+        dets = [z[2 * k:2 * k + 2] for k in range(desc.n_obs) if on(k)]
+        M = len(dets)
+        if M == 0:
+            return math.log(1 - pd)
+        dens = sum(stats.multivariate_normal.pdf(zz, x[:2], rv * np.eye(2)) for zz in dets)
+        return -(M - 1) * math.log(V) + math.log((1 - pd) / V + pd / M * dens)
+    if desc.kind == S.ARM7:
+        pos = S.dh_forward_kinematics(x, p[1:8], p[8:15], p[15:22])
+        return stats.multivariate_normal.logpdf(z, pos, p[0] * np.eye(3)) if on(0) else 0.0
+    if desc.kind == S.LINGAUSS:
+        d, o = desc.d, desc.obs_dim
+        Cm = p[16:16 + o * d].reshape(o, d)
+        return float(np.sum(stats.norm.logpdf(z, Cm @ x, np.sqrt(p[32:32 + o])))) if on(0) else 0.0
+    raise ValueError
+
+
+def _random_state(desc, rng):
+    if desc.kind == S.RANGE2D:
+        return rng.uniform(0, 20, size=2)
+    if desc.kind == S.ARM7:
+        return rng.uniform(-1, 1, size=7)
+    return rng.normal(0, 2, size=desc.d)
+
+
+def _random_obs(desc, rng, x):
+    if desc.kind == S.CV4D:
+        z = rng.normal(0, 3, size=desc.obs_dim)
+        z[:2] = x[:2] + rng.normal(0, 0.3, size=2)
+        return z
+    if desc.kind == S.ARM7:
+        return S.dh_forward_kinematics(x, desc.params[1:8], desc.params[8:15], desc.params[15:22]) \
+            + rng.normal(0, 0.02, size=3)
+    return rng.normal(0, 5, size=desc.obs_dim) + (10 if desc.kind == S.RANGE2D else 0)
+
+
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+def test_loglik_matches_scipy_densities(name):
+    desc = _all_models()[name]
+    rng = np.random.default_rng(1)
+    for trial in range(20):
+        x = _random_state(desc, rng)
+        z = _random_obs(desc, rng, x)
+        mask = None
+        if trial % 2 and desc.n_obs > 1:
+            mask = (rng.random(desc.n_obs) < 0.6).astype(np.uint8)
+        got = O.loglik(desc, z, mask, x)
+        want = _independent_loglik(desc, z, mask, x)
+        assert got == pytest.approx(want, rel=1e-10, abs=1e-9)
+
+
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+def test_grad_loglik_matches_finite_differences(name):
+    desc = _all_models()[name]
+    rng = np.random.default_rng(2)
+    for trial in range(10):
+        x = _random_state(desc, rng)
+        z = _random_obs(desc, rng, x)
+        mask = None
+        if trial % 2 and desc.n_obs > 1:
+            mask = (rng.random(desc.n_obs) < 0.6).astype(np.uint8)
+        g = O.grad_loglik(desc, z, mask, x)
+        fd = np.zeros(desc.d)
+        for a in range(desc.d):
+            e = np.zeros(desc.d)
+            hstep = 1e-6 * max(1.0, abs(x[a]))
+            e[a] = hstep
+            fd[a] = (O.loglik(desc, z, mask, x + e) - O.loglik(desc, z, mask, x - e)) / (2 * hstep)
+        scale = max(1.0, np.abs(fd).max())
+        assert np.abs(g - fd).max() <= 2e-6 * scale
+
+
+def test_transition_means_match_model_definitions():
+    rng = np.random.default_rng(3)
+    m = _all_models()
+    x = rng.normal(size=1)
+    for t in (1, 2, 17):
+        want = 0.5 * x[0] + 25 * x[0] / (1 + x[0] ** 2) + 8 * math.cos(1.2 * t)
+        assert O.transition_mean(m["growth1d"], t, x)[0] == pytest.approx(want, rel=1e-14)
+    x4 = rng.normal(size=4)
+    assert np.allclose(O.transition_mean(m["cv4d"], 3, x4),
+                       [x4[0] + 0.1 * x4[2], x4[1] + 0.1 * x4[3], x4[2], x4[3]], rtol=1e-14)
+    for name in ("range2d", "arm7"):
+        xv = rng.normal(size=m[name].d)
+        assert np.array_equal(O.transition_mean(m[name], 5, xv), xv)
+    lg = m["lingauss"]
+    x2 = rng.normal(size=2)
+    assert np.allclose(O.transition_mean(lg, 1, x2), np.array([[1.0, 0.1], [0.0, 0.95]]) @ x2)
+
+
+def test_log_transition_matches_scipy():
+    rng = np.random.default_rng(4)
+    for name, desc in _all_models().items():
+        x = rng.normal(size=desc.d)
+        mean = rng.normal(size=desc.d)
+        want = stats.multivariate_normal.logpdf(x, mean, np.diag(desc.q_var[:desc.d]))
+        assert O.log_transition(desc, x, mean) == pytest.approx(want, rel=1e-12)
+
+
+def test_arm_fk_planar_chain_closed_form():
+    # With every twist alpha = 0 the standard-DH chain is a planar arm:
+    # p = (sum a_i cos(q_1+..+q_i), sum a_i sin(q_1+..+q_i), 0).
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0.1, 0.4, size=7)
+    desc = S.arm7_model(a, alpha=np.zeros(7))
+    for _ in range(10):
+        q = rng.uniform(-1, 1, size=7)
+        cum = np.cumsum(q)
+        want = [np.sum(a * np.cos(cum)), np.sum(a * np.sin(cum)), 0.0]
+        assert np.allclose(O.arm_fk(desc, q), want, atol=1e-13)
+
+
+def test_arm_fk_two_independent_codes_agree():
+    rng = np.random.default_rng(6)
+    desc = S._model_for("arm7", 3)
+    p = desc.params
+    for _ in range(20):
+        q = rng.uniform(-2, 2, size=7)
+        assert np.allclose(O.arm_fk(desc, q), S.dh_forward_kinematics(q, p[1:8], p[8:15], p[15:22]),
+                           atol=1e-13)
+    # Reach: never further from the base than the sum of link lengths.
+    for _ in range(20):
+        q = rng.uniform(-3, 3, size=7)
+        assert np.linalg.norm(O.arm_fk(desc, q)) <= p[1:8].sum() + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Bandwidth (median heuristic)
+# ---------------------------------------------------------------------------
+
+def test_median_bandwidth_hand_examples():
+    for row in _gold_rows("median_bandwidth.txt"):
+        xs = np.array([float(v) for v in row[0].split(";")])[:, None]
+        h, med = O.bandwidth(xs, float(row[1]))
+        assert med == float(row[2])
+        assert h == pytest.approx(float(row[3]), rel=1e-15)
+
+
+def test_lower_median_against_partition():
+    rng = np.random.default_rng(7)
+    for M in (1, 2, 3, 10, 11, 1000, 1001):
+        v = rng.normal(size=M)
+        assert O.lower_median(v) == np.partition(v, (M - 1) // 2)[(M - 1) // 2]
+    # duplicates
+    assert O.lower_median(np.array([2.0, 1.0, 2.0, 1.0])) == 1.0
+
+
+def test_bandwidth_guards():
+    h, med = O.bandwidth(np.array([[1.0, 2.0]]))
+    assert h == 1.0 and math.isnan(med)
+    h, med = O.bandwidth(np.zeros((5, 3)))      # all distances zero
+    assert h == 1.0 and med == 0.0
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=(40, 3))
+    D = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)[np.triu_indices(40, 1)]
+    h, med = O.bandwidth(x, 0.5)
+    assert med == np.sort(D)[(D.size - 1) // 2]
+    assert h == pytest.approx(0.5 * med / math.log(40), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Stein direction (eq. SVGD_newupdate / svgd_iterate)
+# ---------------------------------------------------------------------------
+
+def test_stein_two_particles_zero_score_closed_form():
+    rng = np.random.default_rng(9)
+    for d in (1, 2, 7):
+        x = rng.normal(size=(2, d))
+        h, med = O.bandwidth(x)
+        D = float(((x[0] - x[1]) ** 2).sum())
+        assert med == D and h == pytest.approx(D / math.log(2), rel=1e-15)
+        phi = O.stein_phi(x, np.zeros_like(x), h)
+        # kappa_12 = exp(-ln 2) = 1/2 -> phi_1 = (ln 2 / (2 D)) (x_1 - x_2): repulsion
+        want = math.log(2) / (2 * D) * (x[0] - x[1])
+        assert np.allclose(phi[0], want, rtol=1e-12)
+        assert np.allclose(phi[1], -want, rtol=1e-12)
+
+
+def test_stein_repulsion_conserves_mean_and_is_equivariant():
+    rng = np.random.default_rng(10)
+    x = rng.normal(size=(30, 2))
+    h = 0.7
+    phi = O.stein_phi(x, np.zeros_like(x), h)
+    assert np.abs(phi.sum(0)).max() < 1e-12
+    # translation invariance
+    assert np.allclose(O.stein_phi(x + np.array([3.0, -1.0]), np.zeros_like(x), h), phi, atol=1e-13)
+    # rotation equivariance
+    th = 0.37
+    R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    assert np.allclose(O.stein_phi(x @ R.T, np.zeros_like(x), h), phi @ R.T, atol=1e-13)
+
+
+def test_stein_kernel_weighted_score_term():
+    # With all particles at one point kappa = 1 and the repulsion vanishes:
+    # phi_i = mean_k s_k.
+    rng = np.random.default_rng(11)
+    x = np.ones((6, 3))
+    s = rng.normal(size=(6, 3))
+    phi = O.stein_phi(x, s, 2.0)
+    assert np.allclose(phi, np.broadcast_to(s.mean(0), s.shape), rtol=1e-14)
+    # Two far-apart clusters do not interact (kappa ~ 0 across them).
+    x = np.concatenate([np.zeros((3, 1)), 1e3 * np.ones((3, 1))])
+    s = rng.normal(size=(6, 1))
+    phi = O.stein_phi(x, s, 1.0)
+    assert np.allclose(phi[:3], s[:3].sum() / 6)
+    assert np.allclose(phi[3:], s[3:].sum() / 6)
+
+
+# ---------------------------------------------------------------------------
+# Scores: observation gradient + transition-mixture gradient
+# ---------------------------------------------------------------------------
+
+def _log_target_independent(desc, means, log_w, z, mask, x):
+    """log p(z|x) + log sum_j w_j N(x; m_j, Q) from scipy pieces."""
+    q = desc.q_var[:desc.d]
+    comps = [lw + np.sum(stats.norm.logpdf(x, m, np.sqrt(q))) for lw, m in zip(log_w, means)]
+    return _independent_loglik(desc, z, mask, x) + logsumexp(comps)
+
+
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+def test_lse_scores_match_finite_differences_of_log_target(name):
+    desc = _all_models()[name]
+    rng = np.random.default_rng(12)
+    n_prev = 5
+    x_prev = np.stack([_random_state(desc, rng) for _ in range(n_prev)])
+    means = np.stack([O.transition_mean(desc, 2, xp) for xp in x_prev])
+    log_w = np.log(rng.dirichlet(np.ones(n_prev)))
+    xk = means[0] + 0.3 * rng.normal(size=desc.d) * np.sqrt(desc.q_var[:desc.d])
+    z = _random_obs(desc, rng, xk)
+    s = O.scores_from_means(desc, means, log_w, z, None, xk[None, :])[0]
+    fd = np.zeros(desc.d)
+    for a in range(desc.d):
+        e = np.zeros(desc.d)
+        hs = 1e-6 * max(1.0, abs(xk[a]))
+        e[a] = hs
+        fd[a] = (_log_target_independent(desc, means, log_w, z, None, xk + e)
+                 - _log_target_independent(desc, means, log_w, z, None, xk - e)) / (2 * hs)
+    assert np.abs(s - fd).max() <= 1e-5 * max(1.0, np.abs(fd).max())
+
+
+def test_scores_special_cases():
+    desc = _all_models()["lingauss"]
+    rng = np.random.default_rng(13)
+    x = rng.normal(size=(4, 2))
+    z = np.array([0.3])
+    m1 = rng.normal(size=(1, 2))
+    q = desc.q_var[:2]
+    # one previous particle: a single Gaussian transition gradient
+    s = O.scores_from_means(desc, m1, None, z, None, x)
+    g = np.stack([O.grad_loglik(desc, z, None, xx) for xx in x])
+    assert np.allclose(s, g - (x - m1) / q, rtol=1e-13)
+    # all components equal: same as a single one, for any weights
+    mm = np.repeat(m1, 6, axis=0)
+    lw = np.log(rng.dirichlet(np.ones(6)))
+    assert np.allclose(O.scores_from_means(desc, mm, lw, z, None, x), s, rtol=1e-12)
+    # adding a constant to every log-weight changes nothing
+    means = rng.normal(size=(6, 2))
+    a = O.scores_from_means(desc, means, lw, z, None, x)
+    b = O.scores_from_means(desc, means, lw + 123.0, z, None, x)
+    assert np.allclose(a, b, rtol=1e-12)
+    # uniform default equals explicit uniform weights
+    c = O.scores_from_means(desc, means, None, z, None, x)
+    d = O.scores_from_means(desc, means, np.full(6, -math.log(6)), z, None, x)
+    assert np.allclose(c, d, rtol=1e-13)
+    # the mean-of-gradients reading uses the plain average of the means
+    e = O.scores_from_means(desc, means, None, z, None, x, trans_mode=1)
+    assert np.allclose(e, g - (x - means.mean(0)) / q, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# SVGD step: one particle is plain gradient ascent
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+def test_single_particle_svgd_is_gradient_ascent(name):
+    desc = _all_models()[name]
+    rng = np.random.default_rng(14)
+    n_prev = 3
+    x_prev = np.stack([_random_state(desc, rng) for _ in range(n_prev)])
+    t = 4
+    means = np.stack([O.transition_mean(desc, t, xp) for xp in x_prev])
+    log_w = np.full(n_prev, -math.log(n_prev))
+    x = means[1] + 0.5 * np.sqrt(desc.q_var[:desc.d]) * rng.normal(size=desc.d)
+    z = _random_obs(desc, rng, x)
+    step = {"growth1d": 0.05, "range2d": 0.01, "cv4d": 0.01, "arm7": 1e-5, "lingauss": 0.01}[name]
+    L = 15
+    got, hs, st = O.svgd_step(desc, t, x_prev, None, z, None, x[None, :], L, step)
+    assert st == O.OK and np.all(hs == 1.0)
+    # gradient ascent with a finite-difference gradient of the independent log target
+    y = x.copy()
+    for _ in range(L):
+        g = np.zeros(desc.d)
+        for a in range(desc.d):
+            e = np.zeros(desc.d)
+            hh = 1e-6 * max(1.0, abs(y[a]))
+            e[a] = hh
+            g[a] = (_log_target_independent(desc, means, log_w, z, None, y + e)
+                    - _log_target_independent(desc, means, log_w, z, None, y - e)) / (2 * hh)
+        y = y + step * g
+    assert np.abs(got[0] - y).max() <= 1e-6 * max(1.0, np.abs(y).max())
+
+
+def test_svgd_step_reads_iteration_state_synchronously():
+    # Two iterations of the step equal two hand-chained applications of
+    # bandwidth -> scores -> Stein direction, all from the same particle state.
+    desc = _all_models()["range2d"]
+    rng = np.random.default_rng(15)
+    x_prev = rng.uniform(5, 15, size=(7, 2))
+    x = rng.uniform(5, 15, size=(9, 2))
+    z = np.array([5.0, 7.0, 9.0])
+    got, hs, st = O.svgd_step(desc, 3, x_prev, None, z, None, x, 2, 0.01, 1.5)
+    y = x.copy()
+    for l in range(2):
+        h, _ = O.bandwidth(y, 1.5)
+        assert hs[l] == h
+        s = O.scores(desc, 3, x_prev, None, z, None, y)
+        y = y + 0.01 * O.stein_phi(y, s, h)
+    assert np.array_equal(got, y)
+    # bandwidth computed once per step
+    got2, hs2, _ = O.svgd_step(desc, 3, x_prev, None, z, None, x, 3, 0.01, 1.5, bw_mode=1)
+    assert hs2[0] == hs2[1] == hs2[2]
+
+
+# ---------------------------------------------------------------------------
+# Forward recursion + backtracking against brute force
+# ---------------------------------------------------------------------------
+
+def _viterbi_chain_lattice(As, ells):
+    phi = np.zeros(1)
+    psis = []
+    for A, ell in zip(As, ells):
+        phi, psi, fl, st = O.viterbi_lattice(A, ell, phi)
+        assert st == O.OK
+        psis.append(psi)
+    n = len(phi)
+    psi_tab = np.zeros((len(As), n), dtype=np.int32)
+    for t, p in enumerate(psis):
+        psi_tab[t, :len(p)] = p
+    idx, J, st = O.backtrack(psi_tab, phi)
+    return idx, J
+
+
+@pytest.mark.parametrize("n,T", [(1, 3), (2, 5), (3, 6), (4, 6), (4, 7)])
+def test_viterbi_lattice_equals_brute_force(n, T):
+    rng = np.random.default_rng(100 + 10 * n + T)
+    for trial in range(5):
+        As = [rng.normal(size=(n, 1 if t == 0 else n)) * 3 for t in range(T)]
+        ells = [rng.normal(size=n) * 3 for _ in range(T)]
+        best, second, arg = -np.inf, -np.inf, None
+        for path in itertools.product(range(n), repeat=T):
+            J = 0.0
+            prev = 0
+            for t, i in enumerate(path):
+                J += As[t][i, prev] + ells[t][i]
+                prev = i
+            if J > best:
+                best, second, arg = J, best, path
+            elif J > second:
+                second = J
+        idx, J = _viterbi_chain_lattice(As, ells)
+        assert J == pytest.approx(best, abs=1e-12)
+        if best - second > 1e-9:
+            assert tuple(idx) == arg
+
+
+def test_viterbi_particle_equals_brute_force_over_paths():
+    desc = _all_models()["growth1d"]
+    rng = np.random.default_rng(21)
+    T, n = 5, 3
+    x0 = np.array([0.7])
+    z = rng.normal(2, 2, size=(T, 1))
+    parts = [rng.normal(0, 4, size=(n, 1)) for _ in range(T)]
+    phi = np.zeros(1)
+    prev = x0[None, :]
+    psi_tab = np.zeros((T, n), dtype=np.int32)
+    for t in range(1, T + 1):
+        phi, psi, fl, st = O.viterbi_particle(desc, t, prev, phi, z[t - 1], None, parts[t - 1])
+        psi_tab[t - 1] = psi
+        prev = parts[t - 1]
+    idx, J, st = O.backtrack(psi_tab, phi)
+    best, arg = -np.inf, None
+    for path in itertools.product(range(n), repeat=T):
+        xp = np.concatenate([x0[None, :]] + [parts[t][[i]] for t, i in enumerate(path)])
+        Jp = O.path_score(desc, xp, z)
+        if Jp > best:
+            best, arg = Jp, path
+    assert tuple(idx) == arg
+    assert J == pytest.approx(best, abs=1e-10)
+    # J bookkeeping: the forward recursion accumulates in path-score order
+    xp = np.concatenate([x0[None, :]] + [parts[t][[i]] for t, i in enumerate(idx)])
+    assert O.path_score(desc, xp, z) == J
+
+
+def test_viterbi_ties_lowest_index_and_flags():
+    A = np.array([[1.0, 3.0, 3.0, 0.0],
+                  [2.0, 2.0 - 1e-12, -5.0, 1.0],
+                  [-np.inf, -np.inf, -np.inf, -np.inf]])
+    ell = np.array([0.5, 0.0, 1.0])
+    phi, psi, fl, st = O.viterbi_lattice(A, ell, np.zeros(4), tie_tol=1e-9)
+    assert list(psi) == [1, 0, 0]
+    assert list(fl) == [1, 1, 1]
+    assert phi[0] == 3.5 and phi[1] == 2.0 and phi[2] == -np.inf
+    phi, psi, fl, st = O.viterbi_lattice(A[:2], ell[:2], np.zeros(4), tie_tol=1e-15)
+    assert list(fl) == [1, 0]
+    A[0, 0] = np.nan
+    _, _, _, st = O.viterbi_lattice(A, ell, np.zeros(4))
+    assert st == O.NONFINITE
+
+
+# ---------------------------------------------------------------------------
+# Linear-Gaussian: MAP trajectory = Rauch-Tung-Striebel smoother mean
+# ---------------------------------------------------------------------------
+
+def rts_smoother(A, Cm, Q, R, x0, z):
+    """Kalman filter + RTS smoother with x_0 known exactly (zero prior covariance)."""
+    T = z.shape[0]
+    d = A.shape[0]
+    m, P = x0.copy(), np.zeros((d, d))
+    mf, Pf, mp, Pp = [], [], [], []
+    for t in range(T):
+        m_pred = A @ m
+        P_pred = A @ P @ A.T + Q
+        Sm = Cm @ P_pred @ Cm.T + R
+        K = P_pred @ Cm.T @ np.linalg.inv(Sm)
+        m = m_pred + K @ (z[t] - Cm @ m_pred)
+        P = (np.eye(d) - K @ Cm) @ P_pred
+        mp.append(m_pred); Pp.append(P_pred); mf.append(m); Pf.append(P)
+    mu = [None] * T
+    mu[-1] = mf[-1]
+    for t in range(T - 2, -1, -1):
+        G = Pf[t] @ A.T @ np.linalg.inv(Pp[t + 1])
+        mu[t] = mf[t] + G @ (mu[t + 1] - mp[t + 1])
+    return np.array(mu)
+
+
+def test_rts_smoother_two_step_hand_solution():
+    for row in _gold_rows("rts_two_step.txt"):
+        q, r, z1, z2, x1, x2 = map(float, row)
+        mu = rts_smoother(np.eye(1), np.eye(1), q * np.eye(1), r * np.eye(1), np.zeros(1),
+                          np.array([[z1], [z2]]))
+        assert np.allclose(mu[:, 0], [x1, x2], rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_viterbi_recovers_rts_mean_on_linear_gaussian(seed):
+    wl = S.make_workload("lingauss", B=1, seed=seed, T=12)
+    desc = wl.model
+    d, o = desc.d, desc.obs_dim
+    A = desc.params[:d * d].reshape(d, d)
+    Cm = desc.params[16:16 + o * d].reshape(o, d)
+    Q = np.diag(desc.q_var[:d])
+    R = np.diag(desc.params[32:32 + o])
+    z = wl.z[0]
+    x0 = wl.x0[0]
+    mu = rts_smoother(A, Cm, Q, R, x0, z)
+    rng = np.random.default_rng(seed + 50)
+    n = 9
+    T = wl.T
+    parts, where = [], []
+    for t in range(T):
+        p = mu[t][None, :] + 0.3 * rng.normal(size=(n, d))
+        k = int(rng.integers(n))
+        p[k] = mu[t]
+        parts.append(p)
+        where.append(k)
+    phi = np.zeros(1)
+    prev = x0[None, :]
+    psi_tab = np.zeros((T, n), dtype=np.int32)
+    for t in range(1, T + 1):
+        phi, psi, fl, st = O.viterbi_particle(desc, t, prev, phi, z[t - 1], None, parts[t - 1])
+        psi_tab[t - 1] = psi
+        prev = parts[t - 1]
+    idx, J, st = O.backtrack(psi_tab, phi)
+    assert list(idx) == where
+    path = np.concatenate([x0[None, :], mu])
+    assert J == O.path_score(desc, path, z)
+    # the smoother mean is the continuous maximiser: J's gradient vanishes there
+    base = O.path_score(desc, path, z)
+    for t in range(1, T + 1):
+        for a in range(d):
+            pp = path.copy(); pp[t, a] += 1e-4
+            pm = path.copy(); pm[t, a] -= 1e-4
+            g = (O.path_score(desc, pp, z) - O.path_score(desc, pm, z)) / 2e-4
+            assert abs(g) < 1e-5 * max(1.0, abs(base))
+
+
+def test_run_sequence_map_score_below_rts_optimum():
+    wl = S.make_workload("lingauss", B=1, seed=3, T=10, n=48, n_iter=60)
+    desc = wl.model
+    d, o = desc.d, desc.obs_dim
+    A = desc.params[:d * d].reshape(d, d)
+    Cm = desc.params[16:16 + o * d].reshape(o, d)
+    mu = rts_smoother(A, Cm, np.diag(desc.q_var[:d]), np.diag(desc.params[32:32 + o]),
+                      wl.x0[0], wl.z[0])
+    res = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 7, 0, wl.opts.n_iter,
+                         wl.opts.step)
+    assert res["status"] == O.OK
+    J_mu = O.path_score(desc, np.concatenate([wl.x0[0][None, :], mu]), wl.z[0])
+    assert res["J"] <= J_mu
+    # near-optimal: the particle lattice recovers the MAP score closely
+    assert (J_mu - res["J"]) / max(abs(J_mu), wl.T) < 0.05
+    assert np.abs(res["xmap"][1:] - mu).max() < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 bookkeeping
+# ---------------------------------------------------------------------------
+
+def test_run_sequence_bookkeeping_and_determinism():
+    wl = S.make_workload("growth1d", B=1, seed=4, T=8, n=12, n_iter=20)
+    desc = wl.model
+    r1 = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 99, 0, 20, 0.05,
+                        want_tables=True)
+    r2 = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 99, 0, 20, 0.05)
+    assert np.array_equal(r1["xmap"], r2["xmap"]) and r1["J"] == r2["J"]
+    # J is the path score of the returned trajectory (same accumulation order)
+    assert O.path_score(desc, r1["xmap"], wl.z[0]) == r1["J"]
+    assert np.array_equal(r1["xmap"][0], wl.x0[0])
+    for t in range(1, wl.T + 1):
+        assert np.array_equal(r1["xmap"][t], r1["particles"][t - 1, r1["idx"][t - 1]])
+    # step 1 starts from the predictive particles around f_1(x_0)
+    x_init = O.predictive_init(desc, 1, wl.x0[0][None, :], wl.n, 99, 0)
+    x1, _, _ = O.svgd_step(desc, 1, wl.x0[0][None, :], None, wl.z[0][0], None, x_init, 20, 0.05)
+    assert np.array_equal(x1, r1["particles"][0])
+    mean1 = O.transition_mean(desc, 1, wl.x0[0])
+    want0 = mean1 + math.sqrt(desc.q_var[0]) * O.normals(99, 0, 1, 0, 1)
+    assert np.array_equal(x_init[0], want0)

@@ -1,0 +1,201 @@
+"""Throughput benchmark of the Stein-MAP-Seq hot path on one MI355X.
+
+One benchmark step = Algorithm 2 end to end (predictive initial particles,
+L SVGD iterations and the forward recursion at every time step, then the
+backtrack) over a batch of independent synthetic sequences already resident
+in HBM.  The default workload is the 7-joint arm (N = 1024 particles, d = 7,
+L = 100 iterations, T = 100 steps) with a batch of Monte-Carlo sequences.
+
+Printed as one JSON line: SVGD particle-iterations per second (value), the
+whole-job Viterbi edge rate, the roofline of the dominant kernel (the fused
+step kernel, timed per launch with HIP events on the launch stream), a
+lattice-mode forward-recursion bandwidth figure, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector peak (FLOP/s)
+PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12      # B/s
+
+# Counted flops of the observation-gradient evaluation per particle (FMA = 2),
+# per model family; used in F_iter = N^2 (6d+6) + N N_p (4d+6) + N (c_obs + 6d).
+C_OBS = {"growth1d": 10, "range2d": 60, "cv4d": 150, "arm7": 1100, "lingauss": 16}
+
+
+def flops_per_iteration(n: int, n_prev: int, d: int, name: str) -> float:
+    return n * n * (6 * d + 6) + n * n_prev * (4 * d + 6) + n * (C_OBS[name] + 6 * d)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="arm7")
+    p.add_argument("--batch", type=int, default=256)
+    p.add_argument("--T", type=int, default=None)
+    p.add_argument("--cpu-baseline", type=int, default=1)
+    p.add_argument("--lattice-n", type=int, default=4096)
+    p.add_argument("--lattice-batch", type=int, default=16)
+    return p.parse_args()
+
+
+def cpu_baseline(name: str):
+    """The FP64 oracle, single thread, on one time step of one sequence."""
+    import oracle as O
+    from paper_2312_08684_amd import scenarios as S
+    wl = S.make_workload(name, B=1, seed=0, T=2)
+    desc, o, n = wl.model, wl.opts, wl.n
+    rng = np.random.default_rng(0)
+    sd = np.sqrt(desc.q_var[:desc.d])
+    xprev = wl.truth[0, 1][None, :] + sd * rng.normal(size=(n, desc.d))
+    x_init = O.predictive_init(desc, 2, xprev, n, 1, 0)
+    t0 = time.perf_counter()
+    x, _, _ = O.svgd_step(desc, 2, xprev, None, wl.z[0, 1], None, x_init, o.n_iter, o.step)
+    O.viterbi_particle(desc, 2, xprev, np.zeros(n), wl.z[0, 1], None, x)
+    dt = time.perf_counter() - t0
+    return {"value": n * o.n_iter / dt, "unit": "particle-iters/s", "cores": 1, "kind": "oracle",
+            "sample": "one time step (t=2) of one %s sequence: N=%d, d=%d, %d SVGD iterations + "
+                      "forward recursion, FP64 oracle, single thread, %.1f s" % (name, n, desc.d, o.n_iter, dt),
+            "host_cpus": os.cpu_count(), "cpu_model": platform.processor() or platform.machine()}
+
+
+def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
+    """Lattice-mode forward recursion on `batch` independent FP32 n x n lattices
+    (larger together than the 256 MB last-level cache): edges/s and GB/s."""
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    A = [torch.randn((n, n), generator=gen, device="cuda") for _ in range(batch)]
+    ell = torch.randn(n, device="cuda")
+    phi_prev = torch.randn(n, device="cuda")
+    ws = smsq.workspace()
+    for a in A[:2]:
+        smsq.viterbi_step(None, "f32", 2, phi_prev, lattice=a, loglik=ell, want_flags=False, ws=ws)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        for a in A:
+            smsq.viterbi_step(None, "f32", 2, phi_prev, lattice=a, loglik=ell, want_flags=False, ws=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / (reps * batch)
+    nbytes = n * n * 4 + 3 * n * 4 + n * 4
+    return {"n": n, "lattices": batch, "edges_per_s": n * n / sec, "us_per_launch": sec * 1e6,
+            "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM,
+            "bytes_per_launch": nbytes}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sequences shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2312_08684_amd import scenarios as S
+    from paper_2312_08684_amd import smsq
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    smsq.load()
+    name = args.workload
+    wl = S.make_workload(name, B=args.batch, seed=0, T=args.T)
+    desc, o = wl.model, wl.opts
+    B, T, n, d, L = wl.batch, wl.T, wl.n, desc.d, o.n_iter
+    dt = wl.dtype
+    td = smsq.torch_dtype(dt)
+    model = smsq.Model(desc)
+    x0 = torch.tensor(wl.x0, dtype=td, device="cuda")
+    z = torch.tensor(wl.z, dtype=td, device="cuda")
+    mask = torch.tensor(wl.mask, dtype=torch.uint8, device="cuda") if wl.mask is not None else None
+    parts = torch.empty((B, T, n, d), dtype=td, device="cuda")
+    psi = torch.empty((B, T, n), dtype=torch.int32, device="cuda")
+    phis = torch.empty((B, T, n), dtype=td, device="cuda")
+    ws = smsq.workspace()
+    so = smsq.opts_from(o)
+    stream = torch.cuda.current_stream()
+    x0v = x0.view(B, 1, d)
+
+    def one_pass(events=None):
+        for t in range(1, T + 1):
+            xp = x0v if t == 1 else parts[:, t - 2]
+            php = None if t == 1 else phis[:, t - 2]
+            if events is not None:
+                events[t - 1][0].record(stream)
+            smsq.batch_step(model, dt, t, xp, php, z[:, t - 1], None if mask is None else mask[:, t - 1],
+                            parts[:, t - 1], so, seed=1, phi=phis[:, t - 1], psi=psi[:, t - 1], ws=ws)
+            if events is not None:
+                events[t - 1][1].record(stream)
+        return smsq.backtrack(dt, psi, phis[:, T - 1].contiguous(), parts, x0, ws=ws)
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    assert smsq.device_status(ws) == smsq.OK, "non-finite values in warm-up"
+
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(T)]
+    step_ms = []
+    kernel_ms = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one_pass(events)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        kernel_ms.append([e0.elapsed_time(e1) for e0, e1 in events])
+    ms = float(np.mean(step_ms))
+    particle_iters = B * T * n * L
+    edges = B * (n * 1 + (T - 1) * n * n)
+    flops_total = B * L * (flops_per_iteration(n, 1, d, name) + (T - 1) * flops_per_iteration(n, n, d, name))
+    kern = np.array(kernel_ms)                     # [steps, T] ms per launch
+    k_avg_ms = float(kern[:, 1:].mean())           # steady-state launches (n_prev = n)
+    flops_launch = B * L * flops_per_iteration(n, n, d, name)
+    achieved = flops_launch / (k_avg_ms / 1e3)
+    peak = PEAK_FP64 if dt == "f64" else PEAK_FP32
+    lat = lattice_bandwidth(torch, smsq, args.lattice_n, args.lattice_batch)
+    out = {
+        "metric": "SVGD particle-iters/s",
+        "value": particle_iters / (ms / 1e3),
+        "unit": "particle-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic",
+        "config": {"workload": "%s N=%d d=%d L=%d T=%d eps=%g, batch of %d sequences" % (
+            name, n, d, L, T, o.step, B), "batch": B, "N": n, "d": d, "L": L, "T": T},
+        "viterbi_edges_per_s": edges / (ms / 1e3),
+        "sequences_per_s": B / (ms / 1e3),
+        "counted_tflops": flops_total / (ms / 1e3) / 1e12,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_step (fused SVGD iterations + forward recursion), steady-state launch",
+                     "kernel_avg_ms": k_avg_ms, "flops_per_launch": flops_launch},
+        "viterbi_lattice": lat,
+    }
+    if args.cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(name)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

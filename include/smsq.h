@@ -1,0 +1,242 @@
+/*
+ * smsq.h -- C ABI of the MI355X (gfx950) Stein-MAP-Seq hot path.
+ *
+ * Stein-MAP-Seq (Seo & Kia, arXiv 2312.08684) estimates the MAP state
+ * trajectory of a state-space model x_t ~ p(x_t | x_{t-1}),
+ * z_t ~ p(z_t | x_t) (Sec. II, eq. SSM) from observations z_{1:T} and a known
+ * initial state x_0.  At every step it moves N particles with Stein
+ * variational gradient descent toward p(z_t, x_t | x_{t-1}) (Lemma IV.3, eq.
+ * SVGD_newupdate), then runs one step of a Viterbi max-plus recursion over the
+ * particle lattice (eq. forward_recursion); a final backtrack returns the MAP
+ * sequence (Sec. IV-B, Algorithm 2).
+ *
+ * Conventions for every entry point below:
+ *  - Array arguments are DEVICE pointers owned by the caller, row-major and
+ *    C-contiguous, in the element type named by the smsq_dtype_t argument
+ *    (float for SMSQ_F32, double for SMSQ_F64); index arrays are int32_t,
+ *    masks and flags uint8_t.  Host-side arguments are marked (host).
+ *  - Calls enqueue work on `stream` and return without waiting.  Argument
+ *    errors are returned synchronously and enqueue nothing.  Results of the
+ *    enqueued work (including non-finite detection) are read after the
+ *    stream is synchronised.
+ *  - The library never frees caller memory and never allocates device
+ *    memory inside a step call.  Scratch memory is the caller's workspace
+ *    `ws` of `ws_bytes` bytes (query its size with smsq_workspace_size and
+ *    zero it once after allocation).  The first 256 bytes of a workspace
+ *    hold a device status word (see smsq_get_device_status); a workspace may
+ *    not be used by two calls that run at the same time.
+ *  - Model handles are immutable after creation and may be shared across
+ *    streams.
+ *  - No exception crosses the ABI.
+ */
+#ifndef SMSQ_H
+#define SMSQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMSQ_OK = 0,
+    SMSQ_ERR_INVALID = 1,      /* bad argument: null pointer, size <= 0, mismatched d, ... */
+    SMSQ_ERR_UNSUPPORTED = 2,  /* shape outside what the kernels handle (e.g. LDS capacity) */
+    SMSQ_ERR_HIP = 3,          /* a HIP runtime call failed */
+    SMSQ_ERR_NONFINITE = 4,    /* device saw NaN/Inf in particles, scores or path scores */
+    SMSQ_ERR_WORKSPACE = 5     /* workspace missing or smaller than smsq_workspace_size */
+} smsq_status_t;
+
+typedef enum { SMSQ_F32 = 0, SMSQ_F64 = 1 } smsq_dtype_t;
+
+/* Model families (the paper's scenario shapes, Sec. V, plus a
+ * linear-Gaussian model).  Every family has a Gaussian transition
+ * x_t ~ N(f_t(x_{t-1}), diag(q_var)); `params` layout per family:
+ *   GROWTH1D  d=1, obs_dim=n_obs=1.  f_t(x)=p0 x + p1 x/(1+x^2) + p2 cos(p3 t + p4);
+ *             z = p5 x^2 + N(0, p6).
+ *   RANGE2D   d=2, obs_dim=n_obs=nb<=16.  f(x)=x; z_b = |x - beacon_b| + N(0, p0);
+ *             p1 = nb, beacon b at (p[2+2b], p[3+2b]); mask[b]=0 hides beacon b.
+ *   CV4D      d=4 (px,py,vx,vy), n_obs=M<=16 detections, obs_dim=2M.
+ *             f(x)=(px+p0 vx, py+p0 vy, vx, vy); p(Z|x) = V^-(M-1) [(1-P_D)/V
+ *             + (P_D/M) sum_m N(z_m; (px,py), p1 I)], P_D=p2, V=p3; mask[m]=0
+ *             drops detection m.
+ *   ARM7      d=7 joint angles, obs_dim=3, n_obs=1.  f(x)=x; z = end-effector
+ *             position of the standard-DH chain A_i = Rz(q_i) Tz(d_i) Tx(a_i)
+ *             Rx(alpha_i) + N(0, p0 I); a_i = p[1+i], alpha_i = p[8+i], d_i = p[15+i].
+ *   LINGAUSS  d<=4, obs_dim<=4, n_obs=1.  f(x) = A x with A = p[0..d*d) row-major;
+ *             z = C x + N(0, diag r), C = p[16..16+obs_dim*d), r = p[32..32+obs_dim).
+ */
+typedef enum {
+    SMSQ_MODEL_GROWTH1D = 0,
+    SMSQ_MODEL_RANGE2D = 1,
+    SMSQ_MODEL_CV4D = 2,
+    SMSQ_MODEL_ARM7 = 3,
+    SMSQ_MODEL_LINGAUSS = 4
+} smsq_model_kind_t;
+
+typedef struct {
+    int kind;           /* smsq_model_kind_t */
+    int d;              /* state dimension */
+    int obs_dim;        /* length of one observation vector z_t */
+    int n_obs;          /* length of one mask row (beacons / detections / 1) */
+    double q_var[8];    /* diagonal transition variances, first d used, > 0 */
+    double params[64];  /* family constants, layout above */
+} smsq_model_desc_t;
+
+typedef struct smsq_model_s *smsq_model_t;
+
+/* SVGD options (Sec. V set-up: fixed iteration count and step size).
+ *  n_iter      iterations per time step (>= 0)
+ *  step        step size epsilon of x <- x + epsilon phi (finite)
+ *  bw_scale    multiplier s of the median-heuristic bandwidth h = s med / ln N
+ *              (> 0; the paper's ablation uses 0.5, 1 and 3)
+ *  bw_mode     0: h recomputed from the particles of every iteration;
+ *              1: h computed once from the initial particles of the step
+ *  trans_mode  0: transition term of the score is grad_x log sum_j w_j
+ *              p(x | x_{t-1}^j) (log-sum-exp over the previous particles);
+ *              1: the equation's literal average of the per-j gradients. */
+typedef struct {
+    int n_iter;
+    double step;
+    double bw_scale;
+    int bw_mode;
+    int trans_mode;
+} smsq_svgd_opts_t;
+
+/* Validates a model description and copies it into an immutable handle.
+ * Returns SMSQ_ERR_INVALID for an unknown kind, a d or observation size that
+ * does not match the family, or a non-positive variance. (host only) */
+smsq_status_t smsq_model_create(const smsq_model_desc_t *desc, smsq_model_t *out);
+smsq_status_t smsq_model_destroy(smsq_model_t model);
+
+/* Bytes of workspace needed by smsq_run_batch for `batch` sequences of T
+ * steps with n particles (also enough for smsq_run_sequence with batch = 1
+ * and for the single-step calls, which need only the 256-byte header). */
+smsq_status_t smsq_workspace_size(smsq_model_t model, smsq_dtype_t dtype, int batch, int T,
+                                  int n, size_t *bytes);
+
+/* One time step of SVGD (Algorithm 2, steps 1 and 2; eq. SVGD_newupdate, and
+ * eq. SVGD_initial_newupdate when n_prev = 1 and x_prev = x_0).
+ *  t           step index (>= 1), the time argument of f_t
+ *  x_prev      [n_prev, d] particles of step t-1 (x_0 for t = 1)
+ *  log_w_prev  [n_prev] log-weights of those particles, or NULL for uniform
+ *  z_t         [obs_dim] observation; z_mask [n_obs] or NULL (all present)
+ *  x           [n, d] in: initial particles, out: particles after n_iter
+ *              iterations; all particles move together from the state of
+ *              the previous iteration
+ *  h_out       [n_iter] bandwidth used by each iteration, or NULL
+ * Requires n >= 1, n_prev >= 1; SMSQ_ERR_UNSUPPORTED when the particle sets
+ * do not fit one compute unit's LDS. */
+smsq_status_t smsq_svgd_step(smsq_model_t model, smsq_dtype_t dtype, int t,
+                             int n_prev, const void *x_prev, const void *log_w_prev,
+                             const void *z_t, const uint8_t *z_mask,
+                             int n, void *x, const smsq_svgd_opts_t *opts /* host */,
+                             void *h_out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* One forward-recursion step (eq. forward_recursion):
+ *   c_ij = A_ij + phi_prev(j),  psi(i) = lowest j attaining max_j c_ij,
+ *   phi(i) = c_{i psi(i)} + loglik_i,
+ * with A_ij = log p(x_t^i | x_{t-1}^j) and loglik_i = log p(z_t | x_t^i),
+ * both with their normalising constants.
+ * Lattice mode (lattice != NULL): A is the given [n, n_prev] matrix and
+ * loglik the given [n] vector; model, t, x_prev, z_t, z_mask and x are
+ * ignored (may be NULL).  Particle mode (lattice == NULL): A and loglik are
+ * computed from x_prev [n_prev, d], x [n, d] and z_t.
+ *  phi_prev    [n_prev] accumulated scores of step t-1 (zeros for t = 1)
+ *  phi, psi    [n] outputs; tie_flags [n] output or NULL: 1 where the best
+ *              c_ij over j != psi(i) is >= best - tie_tol * max(1, |best|)
+ * NaN in any c_ij or loglik_i sets SMSQ_ERR_NONFINITE in the workspace
+ * status; -inf is a valid score (a row of -inf gives psi = 0). */
+smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t,
+                                int n_prev, const void *x_prev, const void *phi_prev,
+                                const void *z_t, const uint8_t *z_mask, int n, const void *x,
+                                const void *lattice, const void *loglik,
+                                void *phi, int32_t *psi, uint8_t *tie_flags, double tie_tol,
+                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backtracking (Sec. IV-B; Algorithm 2, step 4) over `batch` independent
+ * sequences.  psi [batch, T, n]: row t-1 holds psi_t (entries of row 0 are
+ * ignored).  phi_T [batch, n].  Outputs idx_out [batch, T] (entry t-1 is
+ * i_t; i_T = lowest argmax of phi_T) and logpost_out [batch] = phi_T(i_T).
+ * If particles [batch, T, n, d], x0 [batch, d] and xmap_out [batch, T+1, d]
+ * are all non-NULL, the MAP states are gathered: xmap[0] = x0,
+ * xmap[t] = particles[t-1][i_t]. */
+smsq_status_t smsq_backtrack(smsq_dtype_t dtype, int batch, int T, int n, int d,
+                             const int32_t *psi, const void *phi_T, int32_t *idx_out,
+                             void *logpost_out, const void *particles, const void *x0,
+                             void *xmap_out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* One step of Algorithm 2 for `batch` independent sequences that share a
+ * model and sizes, in one launch: initial particles, n_iter SVGD iterations
+ * and the forward recursion.
+ *  t              step (>= 1).  For t = 1, n_prev must be 1, x_prev is x_0
+ *                 [batch, d] and phi_prev may be NULL (zeros).
+ *  x_prev         [batch, n_prev, d] (element stride between sequences is
+ *                 x_prev_stride)
+ *  phi_prev       n_prev accumulated scores of step t-1 per sequence, element
+ *                 stride out_stride between sequences (NULL: zeros)
+ *  z, z_mask      observation of step t of each sequence: element
+ *                 b * z_stride (mask: b * mask_stride) starts sequence b's row
+ *  x              [batch, n, d] (stride x_stride): the step's particles; if
+ *                 init_given != 0 it holds the initial particles on entry,
+ *                 else they are drawn as f_t(x_prev[i mod n_prev]) +
+ *                 sqrt(q) * xi with xi standard normals from Philox4x32-10
+ *                 keyed by `seed`, counter (i, t, seq_offset + b, block)
+ *  phi, psi       outputs of the forward recursion, n per sequence with
+ *                 element stride out_stride between sequences; tie_flags
+ *                 likewise, or NULL.  Keeping phi and psi of every step in
+ *                 [batch, T, n] buffers gives out_stride = T n. */
+smsq_status_t smsq_batch_step(smsq_model_t model, smsq_dtype_t dtype, int batch, int t,
+                              int n_prev, const void *x_prev, long x_prev_stride,
+                              const void *phi_prev, const void *z, long z_stride,
+                              const uint8_t *z_mask, long mask_stride,
+                              int n, void *x, long x_stride, int init_given,
+                              uint64_t seed, uint32_t seq_offset,
+                              const smsq_svgd_opts_t *opts /* host */,
+                              void *phi, int32_t *psi, uint8_t *tie_flags, long out_stride,
+                              double tie_tol, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Algorithm 2 end to end for `batch` independent sequences (Monte-Carlo
+ * runs) sharing a model and sizes.
+ *  x0 [batch, d], z [batch, T, obs_dim], z_mask [batch, T, n_obs] or NULL
+ *  seed           Philox key of the predictive initial particles (sequence b
+ *                 uses counter word 2 = b)
+ *  xmap_out       [batch, T+1, d] MAP trajectories (x_0 first)
+ *  logpost_out    [batch] J = sum_t log p(z_t, x_t | x_{t-1}) along the MAP
+ *                 path (Theorem IV.1's score without the constant log p(x_0))
+ *  particles_out  [batch, T, n, d] every step's particles, or NULL (then
+ *                 they are kept in the workspace)
+ * The workspace must hold smsq_workspace_size(model, dtype, batch, T, n). */
+smsq_status_t smsq_run_batch(smsq_model_t model, smsq_dtype_t dtype, int batch, int T, int n,
+                             const void *x0, const void *z, const uint8_t *z_mask, uint64_t seed,
+                             const smsq_svgd_opts_t *opts /* host */, void *xmap_out,
+                             void *logpost_out, void *particles_out, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* smsq_run_batch with batch = 1. */
+smsq_status_t smsq_run_sequence(smsq_model_t model, smsq_dtype_t dtype, int T, int n,
+                                const void *x0, const void *z, const uint8_t *z_mask,
+                                uint64_t seed, const smsq_svgd_opts_t *opts /* host */,
+                                void *xmap_out, void *logpost_out, void *particles_out,
+                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Reads the workspace status word (synchronous device-to-host copy; call
+ * after the work has been synchronised).  *out is SMSQ_OK or
+ * SMSQ_ERR_NONFINITE. */
+smsq_status_t smsq_get_device_status(const void *ws, smsq_status_t *out);
+/* Enqueues a reset of the workspace status word to SMSQ_OK. */
+smsq_status_t smsq_clear_device_status(void *ws, hipStream_t stream);
+
+/* Static text for a status code. (host) */
+const char *smsq_status_string(smsq_status_t status);
+
+/* Maximum particles per step the single-compute-unit kernels accept for a
+ * model and dtype (limited by LDS capacity), for n_prev = n. (host) */
+int smsq_max_particles(smsq_model_t model, smsq_dtype_t dtype);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMSQ_H */

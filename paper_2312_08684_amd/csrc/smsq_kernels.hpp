@@ -1,0 +1,507 @@
+// Stein-MAP-Seq step kernels for gfx950.
+//
+// One workgroup owns one sequence and keeps its whole particle state in LDS
+// for a time step: the previous particles' transition means, the current
+// particles and their scores.  Every SVGD iteration (eq. SVGD_newupdate) is
+//   (1) exact lower median of the pairwise squared distances by radix
+//       selection on their bit patterns (bandwidth h = s med / ln N),
+//   (2) per-particle score: observation gradient plus the log-sum-exp
+//       transition-mixture gradient, with an online (running-max) softmax
+//       over the previous particles,
+//   (3) Stein direction phi_i = (1/N) sum_k kappa_ik [s_k + (2/h)(x_i - x_k)],
+//       then x_i += eps phi_i for all i at once,
+// and after the iterations the forward-recursion row of every particle
+// (eq. forward_recursion) is a max-plus reduction over the previous step.
+#pragma once
+
+#include "smsq_models.hpp"
+
+namespace smsq {
+
+constexpr int kBins = 2048;          // radix-select histogram (11-bit digits)
+constexpr int kMaxRowsPerThread = 2; // particles owned by one thread in the Stein pass
+constexpr int kMaxObs = 32;
+
+enum : uint32_t { STATUS_NONFINITE = 4u };
+
+template <typename T> struct StepArgs {
+    DevModel<T> m;
+    // previous particles [batch][n_prev][d] (sequence stride x_prev_stride)
+    const T *x_prev; long x_prev_stride;
+    const T *log_w; long log_w_stride;      // may be null (uniform)
+    const T *phi_prev; long phi_prev_stride; // may be null (zeros)
+    const T *z; long z_stride;
+    const uint8_t *mask; long mask_stride;  // may be null
+    T *x; long x_stride;                    // [batch][n][d] in/out
+    T *phi; long phi_stride;                // forward recursion outputs (may be null: no Viterbi)
+    int32_t *psi; long psi_stride;
+    uint8_t *flags; long flags_stride;      // may be null
+    T *h_out; long h_stride;                // may be null
+    uint32_t *status;
+    int n_prev, n, t, n_iter, bw_mode, trans_mode, init_given, do_svgd, do_viterbi;
+    T step, bw_scale, tie_tol;
+    uint64_t seed; uint32_t seq_offset;
+};
+
+__host__ __device__ constexpr long align16(long b) { return (b + 15) & ~15L; }
+
+// LDS byte layout of a step workgroup.
+template <typename T> struct StepLds {
+    long off_x, off_s, off_m, off_c, off_hist, off_z, off_mask, off_red, total;
+    __host__ __device__ StepLds(int n, int n_prev, int dp)
+    {
+        long o = 0;
+        off_x = o; o += align16((long)n * dp * sizeof(T));
+        off_s = o; o += align16((long)n * dp * sizeof(T));
+        off_m = o; o += align16((long)n_prev * dp * sizeof(T));
+        off_c = o; o += align16((long)n_prev * sizeof(T));
+        off_hist = o; o += (long)kBins * sizeof(uint32_t);
+        off_z = o; o += align16((long)kMaxObs * sizeof(T));
+        off_mask = o; o += 64;
+        off_red = o; o += 256;
+        total = o;
+    }
+};
+
+template <typename T, int DP> struct Vec { T v[DP]; };
+
+template <typename T, int DP>
+__device__ __forceinline__ void lds_load(const T *p, T (&r)[DP])
+{
+#pragma unroll
+    for (int a = 0; a < DP; ++a) r[a] = p[a];
+}
+
+// ---------------------------------------------------------------------------
+// (1) exact lower median of {|x_i - x_k|^2 : i < k} by radix selection.
+// Pairs are visited as 64x64 tiles of the upper triangle; lane l of a wave
+// takes row i = 64 ib + l and walks the tile's columns.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int DP>
+__device__ T block_median_sqdist(const T *sx, int n, uint32_t *hist, uint32_t *red)
+{
+    using KO = KeyOf<T>;
+    using K = typename KO::K;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nt / kWave;
+    const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
+    if (M == 0) return __builtin_nan("");
+    uint32_t rank = (M - 1) / 2;
+    K prefix = 0, pmask = 0;
+    const int nb = (n + kWave - 1) / kWave;
+    const int ntiles = nb * (nb + 1) / 2;
+    for (int pass = 0; pass < KO::kPasses; ++pass) {
+        const int shift = KO::shift(pass);
+        const K dmask = ((K)1 << KO::width(pass)) - 1;
+        for (int b = tid; b < kBins; b += nt) hist[b] = 0;
+        __syncthreads();
+        for (int tile = wave; tile < ntiles; tile += nwaves) {
+            int ib = 0, rem = tile;
+            while (rem >= nb - ib) { rem -= nb - ib; ++ib; }
+            const int kb = ib + rem;
+            const int i = ib * kWave + lane;
+            T xi[DP];
+            if (i < n) lds_load<T, DP>(sx + (long)i * DP, xi);
+            const int k0 = kb * kWave;
+            const int k1 = min(k0 + kWave, n);
+            for (int k = k0; k < k1; ++k) {
+                if (i < k && i < n) {
+                    T xk[DP];
+                    lds_load<T, DP>(sx + (long)k * DP, xk);
+                    T dd = 0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) { const T r = xi[a] - xk[a]; dd += r * r; }
+                    const K key = KO::key(dd);
+                    if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)((key >> shift) & dmask)], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            constexpr int per = kBins / kWave;
+            uint32_t cnt = 0;
+            for (int q = 0; q < per; ++q) cnt += hist[lane * per + q];
+            const uint32_t incl = wave_incl_scan(cnt, lane);
+            const uint32_t excl = incl - cnt;
+            if (lane == 0) { red[0] = 0; red[1] = 0; }
+            __builtin_amdgcn_wave_barrier();
+            if (rank >= excl && rank < incl) {
+                uint32_t r = rank - excl;
+                for (int q = 0; q < per; ++q) {
+                    const uint32_t h = hist[lane * per + q];
+                    if (r < h) { red[0] = (uint32_t)(lane * per + q); red[1] = r; break; }
+                    r -= h;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t digit = red[0];
+        rank = red[1];
+        prefix |= (K)digit << shift;
+        pmask |= dmask << shift;
+        __syncthreads();
+    }
+    return KO::val(prefix);
+}
+
+template <typename T> __device__ __forceinline__ T bandwidth_from_median(T med, int n, T bw_scale)
+{
+    T h = (n > 1) ? bw_scale * med / RealOps<T>::log_((T)n) : (T)0;
+    if (!(h > (T)0) || !RealOps<T>::finite(h)) h = (T)1;
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel: initial particles, SVGD iterations, forward recursion.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, int D>
+__global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
+{
+    using F = Family<T, KIND, D>;
+    using R = RealOps<T>;
+    constexpr int DP = dpad(D);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, np = a.n_prev;
+    const StepLds<T> L(n, np, DP);
+    T *sx = (T *)(smem + L.off_x);
+    T *ss = (T *)(smem + L.off_s);
+    T *sm = (T *)(smem + L.off_m);
+    T *sc = (T *)(smem + L.off_c);
+    uint32_t *hist = (uint32_t *)(smem + L.off_hist);
+    T *sz = (T *)(smem + L.off_z);
+    uint8_t *smask = smem + L.off_mask;
+    uint32_t *red = (uint32_t *)(smem + L.off_red);
+    T *redT = (T *)(smem + L.off_red + 64);
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const DevModel<T> &m = a.m;
+    const T *xprev = a.x_prev + (long)b * a.x_prev_stride;
+    T *xg = a.x + (long)b * a.x_stride;
+
+    // observation of this step
+    for (int o = tid; o < m.obs_dim; o += nt) sz[o] = a.z[(long)b * a.z_stride + o];
+    const uint8_t *mk = nullptr;
+    if (a.mask) {
+        for (int o = tid; o < m.n_obs; o += nt) smask[o] = a.mask[(long)b * a.mask_stride + o];
+        mk = smask;
+    }
+    // transition means of the previous particles, scaled to log2 units, and
+    // their log-weights (log2 units)
+    T rs[DP];
+#pragma unroll
+    for (int c = 0; c < DP; ++c) rs[c] = c < D ? m.rs[c] : (T)0;
+    for (int j = tid; j < np; j += nt) {
+        T xp[D], mu[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) xp[c] = xprev[(long)j * D + c];
+        F::mean(m, a.t, xp, mu);
+#pragma unroll
+        for (int c = 0; c < DP; ++c) sm[(long)j * DP + c] = c < D ? mu[c] * rs[c] : (T)0;
+        const T lw = a.log_w ? a.log_w[(long)b * a.log_w_stride + j] : -R::log_((T)np);
+        sc[j] = lw * (T)kLog2e;
+    }
+    // initial particles
+    for (int i = tid; i < n; i += nt) {
+        T xi[D];
+        if (a.init_given) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) xi[c] = xg[(long)i * D + c];
+        } else {
+            T xp[D], mu[D];
+            const int j = i % np;
+#pragma unroll
+            for (int c = 0; c < D; ++c) xp[c] = xprev[(long)j * D + c];
+            F::mean(m, a.t, xp, mu);
+            double nz[8];
+            normals8(a.seed, a.seq_offset + (uint32_t)b, (uint32_t)a.t, (uint32_t)i, D, nz);
+#pragma unroll
+            for (int c = 0; c < D; ++c) xi[c] = mu[c] + m.sqrt_q[c] * (T)nz[c];
+        }
+#pragma unroll
+        for (int c = 0; c < DP; ++c) sx[(long)i * DP + c] = c < D ? xi[c] : (T)0;
+    }
+    __syncthreads();
+
+    // mean of the transition means (paper-literal score reading)
+    T mbar_all[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) mbar_all[c] = 0;
+    if (a.do_svgd && a.trans_mode == 1) {
+        for (int c = 0; c < D; ++c) {
+            T part = 0;
+            for (int j = tid; j < np; j += nt) part += sm[(long)j * DP + c] / rs[c];
+            part = wave_sum(part);
+            if ((tid & (kWave - 1)) == 0) redT[tid / kWave] = part;
+            __syncthreads();
+            T tot = 0;
+            for (int w = 0; w < nt / kWave; ++w) tot += redT[w];
+            mbar_all[c] = tot / (T)np;
+            __syncthreads();
+        }
+    }
+
+    const T inv_n = (T)1 / (T)n;
+    T h = (T)1;
+    for (int it = 0; a.do_svgd && it < a.n_iter; ++it) {
+        // (1) bandwidth
+        if (a.bw_mode == 0 || it == 0) {
+            const T med = block_median_sqdist<T, D, DP>(sx, n, hist, red);
+            h = bandwidth_from_median(med, n, a.bw_scale);
+        }
+        if (a.h_out && tid == 0) a.h_out[(long)b * a.h_stride + it] = h;
+
+        // (2) scores
+        for (int k = tid; k < n; k += nt) {
+            T xk[DP];
+            lds_load<T, DP>(sx + (long)k * DP, xk);
+            T g[D];
+            F::grad(m, sz, mk, xk, g);
+            T mb[D];
+            if (a.trans_mode == 0) {
+                T xs[DP];
+#pragma unroll
+                for (int c = 0; c < DP; ++c) xs[c] = xk[c] * rs[c];
+                T mx = -R::inf(), sum = 0, acc[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) acc[c] = 0;
+                constexpr int CH = DP >= 8 ? 4 : 8;
+                int j0 = 0;
+                for (; j0 + CH <= np; j0 += CH) {
+                    T av[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        T mj[DP];
+                        lds_load<T, DP>(sm + (long)(j0 + u) * DP, mj);
+                        T q2 = 0;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) { const T r = xs[c] - mj[c]; q2 += r * r; }
+                        av[u] = sc[j0 + u] - q2;
+                    }
+                    T cm = av[0];
+#pragma unroll
+                    for (int u = 1; u < CH; ++u) cm = av[u] > cm ? av[u] : cm;
+                    const T nm = cm > mx ? cm : mx;
+                    const T sf = R::exp2_(mx - nm);
+                    sum *= sf;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) acc[c] *= sf;
+                    mx = nm;
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const T e = R::exp2_(av[u] - mx);
+                        sum += e;
+                        T mj[DP];
+                        lds_load<T, DP>(sm + (long)(j0 + u) * DP, mj);
+#pragma unroll
+                        for (int c = 0; c < D; ++c) acc[c] += e * mj[c];
+                    }
+                }
+                for (; j0 < np; ++j0) {
+                    T mj[DP];
+                    lds_load<T, DP>(sm + (long)j0 * DP, mj);
+                    T q2 = 0;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) { const T r = xs[c] - mj[c]; q2 += r * r; }
+                    const T av = sc[j0] - q2;
+                    const T nm = av > mx ? av : mx;
+                    const T sf = R::exp2_(mx - nm);
+                    const T e = R::exp2_(av - nm);
+                    sum = sum * sf + e;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) acc[c] = acc[c] * sf + e * mj[c];
+                    mx = nm;
+                }
+                const T isum = (T)1 / sum;
+#pragma unroll
+                for (int c = 0; c < D; ++c) mb[c] = acc[c] * isum / rs[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < D; ++c) mb[c] = mbar_all[c];
+            }
+#pragma unroll
+            for (int c = 0; c < DP; ++c)
+                ss[(long)k * DP + c] = c < D ? g[c] - (xk[c] - mb[c]) * m.inv_q[c] : (T)0;
+        }
+        __syncthreads();
+
+        // (3) Stein direction and synchronous update
+        const T beta = (T)kLog2e / h;
+        const T c2 = (T)2 / h;
+        T phi[kMaxRowsPerThread][D];
+#pragma unroll
+        for (int r = 0; r < kMaxRowsPerThread; ++r) {
+            const int i = tid + r * nt;
+            if (i >= n) break;
+            T xi[DP];
+            lds_load<T, DP>(sx + (long)i * DP, xi);
+            T as[D], ar[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) { as[c] = 0; ar[c] = 0; }
+            for (int k = 0; k < n; ++k) {
+                T xk[DP], sk[DP];
+                lds_load<T, DP>(sx + (long)k * DP, xk);
+                lds_load<T, DP>(ss + (long)k * DP, sk);
+                T df[D], dd = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) { df[c] = xi[c] - xk[c]; dd += df[c] * df[c]; }
+                const T kap = R::exp2_(-beta * dd);
+#pragma unroll
+                for (int c = 0; c < D; ++c) { as[c] += kap * sk[c]; ar[c] += kap * df[c]; }
+            }
+#pragma unroll
+            for (int c = 0; c < D; ++c) phi[r][c] = (as[c] + c2 * ar[c]) * inv_n;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kMaxRowsPerThread; ++r) {
+            const int i = tid + r * nt;
+            if (i >= n) break;
+#pragma unroll
+            for (int c = 0; c < D; ++c) sx[(long)i * DP + c] += a.step * phi[r][c];
+        }
+        __syncthreads();
+    }
+
+    // write particles back; flag non-finite values
+    bool bad = false;
+    for (int i = tid; a.do_svgd && i < n; i += nt) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const T v = sx[(long)i * DP + c];
+            bad |= !R::finite(v);
+            xg[(long)i * D + c] = v;
+        }
+    }
+
+    if (a.do_viterbi) {
+        // forward recursion: c_ij = A_ij + phi_prev(j), A_ij = log_z - ln2 * |xs_i - ms_j|^2
+        for (int j = tid; j < np; j += nt)
+            sc[j] = a.phi_prev ? a.phi_prev[(long)b * a.phi_prev_stride + j] : (T)0;
+        __syncthreads();
+        for (int i = tid; i < n; i += nt) {
+            T xi[DP], xs[DP];
+            lds_load<T, DP>(sx + (long)i * DP, xi);
+#pragma unroll
+            for (int c = 0; c < DP; ++c) xs[c] = xi[c] * rs[c];
+            ArgBest<T> ab{-R::inf(), -R::inf(), 0};
+            bool nan_seen = false;
+            for (int j = 0; j < np; ++j) {
+                T mj[DP];
+                lds_load<T, DP>(sm + (long)j * DP, mj);
+                T q2 = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) { const T r = xs[c] - mj[c]; q2 += r * r; }
+                const T A = m.log_z - (T)kLn2 * q2;
+                const T cij = A + sc[j];
+                nan_seen |= (cij != cij);
+                if (j == 0) { ab.best = cij; ab.arg = 0; }
+                else argbest_push(ab, cij, j);
+            }
+            const T ell = F::loglik(m, sz, mk, xi);
+            const T ph = ab.best + ell;
+            nan_seen |= (ph != ph);
+            bad |= nan_seen;
+            a.phi[(long)b * a.phi_stride + i] = ph;
+            a.psi[(long)b * a.psi_stride + i] = ab.arg;
+            if (a.flags) {
+                const T sc_ = ab.best > (T)1 || ab.best < (T)-1 ? (ab.best < 0 ? -ab.best : ab.best) : (T)1;
+                a.flags[(long)b * a.flags_stride + i] = (np > 1 && ab.second >= ab.best - a.tie_tol * sc_) ? 1 : 0;
+            }
+        }
+    }
+    if (bad) atomicOr(a.status, STATUS_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// Lattice-mode forward recursion: one wave per row i, coalesced over j.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, const T *__restrict__ A,
+                                                         const T *__restrict__ ell,
+                                                         const T *__restrict__ phi_prev, T *phi,
+                                                         int32_t *psi, uint8_t *flags, T tie_tol,
+                                                         uint32_t *status)
+{
+    using R = RealOps<T>;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const T *row = A + (long)i * n_prev;
+    ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};
+    bool nan_seen = false;
+    for (int j = lane; j < n_prev; j += kWave) {
+        const T c = row[j] + phi_prev[j];
+        nan_seen |= (c != c);
+        if (j == lane) { ab.best = c; ab.arg = j; }
+        else argbest_push(ab, c, j);
+    }
+    ab = wave_argbest(ab);
+    if (lane == 0) {
+        const T e = ell[i];
+        const T ph = ab.best + e;
+        phi[i] = ph;
+        psi[i] = ab.arg;
+        if (flags) {
+            const T mag = ab.best < 0 ? -ab.best : ab.best;
+            const T sc = mag > (T)1 ? mag : (T)1;
+            flags[i] = (n_prev > 1 && ab.second >= ab.best - tie_tol * sc) ? 1 : 0;
+        }
+        nan_seen |= (e != e) || (ph != ph);
+    }
+    if (__any(nan_seen) && lane == 0) atomicOr(status, STATUS_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// Backtracking: one workgroup (one wave) per sequence.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_backtrack(int T_, int n, int d, const int32_t *__restrict__ psi,
+                                                  long psi_bstride, const T *__restrict__ phi_T,
+                                                  long phi_bstride, int32_t *idx_out, T *logpost,
+                                                  const T *__restrict__ parts, long parts_bstride,
+                                                  const T *__restrict__ x0, T *xmap, uint32_t *status)
+{
+    using R = RealOps<T>;
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const T *ph = phi_T + (long)b * phi_bstride;
+    ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};
+    for (int i = lane; i < n; i += kWave) {
+        const T v = ph[i];
+        if (i == lane) { ab.best = v; ab.arg = i; }
+        else argbest_push(ab, v, i);
+    }
+    ab = wave_argbest(ab);
+    int32_t *idx = idx_out + (long)b * T_;
+    if (lane == 0) {
+        int cur = ab.arg;
+        idx[T_ - 1] = cur;
+        const int32_t *ps = psi + (long)b * psi_bstride;
+        for (int t = T_; t >= 2; --t) {
+            int prev = ps[(long)(t - 1) * n + cur];
+            if (prev < 0 || prev >= n) { atomicOr(status, STATUS_NONFINITE); prev = 0; }
+            idx[t - 2] = prev;
+            cur = prev;
+        }
+        logpost[b] = ab.best;
+        if (!R::finite(ab.best)) atomicOr(status, STATUS_NONFINITE);
+    }
+    if (xmap == nullptr) return;
+    __syncthreads();
+    T *xm = xmap + (long)b * (T_ + 1) * d;
+    for (int c = lane; c < d; c += kWave) xm[c] = x0[(long)b * d + c];
+    const T *pb = parts + (long)b * parts_bstride;
+    for (int q = lane; q < T_ * d; q += kWave) {
+        const int t = q / d, c = q % d;
+        xm[(long)(t + 1) * d + c] = pb[((long)t * n + idx[t]) * d + c];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+} // namespace smsq

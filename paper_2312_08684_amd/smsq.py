@@ -1,0 +1,353 @@
+"""Python binding of libsmsq.so (the C ABI in include/smsq.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI.  PyTorch supplies device memory (tensors on ``cuda``) and
+the current HIP stream.  There is no CPU fallback: if the library is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmsq.so")
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE, ERR_WORKSPACE = range(6)
+F32, F64 = 0, 1
+
+SYMBOLS = [
+    "smsq_model_create", "smsq_model_destroy", "smsq_workspace_size", "smsq_svgd_step",
+    "smsq_viterbi_step", "smsq_backtrack", "smsq_batch_step", "smsq_run_batch",
+    "smsq_run_sequence", "smsq_get_device_status", "smsq_clear_device_status",
+    "smsq_status_string", "smsq_max_particles",
+]
+
+
+class SmsqError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, status_string(status), status))
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("d", C.c_int), ("obs_dim", C.c_int), ("n_obs", C.c_int),
+                ("q_var", C.c_double * 8), ("params", C.c_double * 64)]
+
+
+class SvgdOpts(C.Structure):
+    _fields_ = [("n_iter", C.c_int), ("step", C.c_double), ("bw_scale", C.c_double),
+                ("bw_mode", C.c_int), ("trans_mode", C.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libsmsq.so; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libsmsq.so is not built (%s); run __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    vp, i32, i64, u64, u32, dbl = C.c_void_p, C.c_int, C.c_long, C.c_uint64, C.c_uint32, C.c_double
+    L.smsq_model_create.argtypes = [C.POINTER(ModelDesc), C.POINTER(vp)]
+    L.smsq_model_destroy.argtypes = [vp]
+    L.smsq_workspace_size.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_size_t)]
+    L.smsq_svgd_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, i32, vp, C.POINTER(SvgdOpts),
+                                 vp, vp, C.c_size_t, vp]
+    L.smsq_viterbi_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                    dbl, vp, C.c_size_t, vp]
+    L.smsq_backtrack.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                 C.c_size_t, vp]
+    L.smsq_batch_step.argtypes = [vp, i32, i32, i32, i32, vp, i64, vp, vp, i64, vp, i64, i32, vp,
+                                  i64, i32, u64, u32, C.POINTER(SvgdOpts), vp, vp, vp, i64, dbl, vp,
+                                  C.c_size_t, vp]
+    L.smsq_run_batch.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, u64, C.POINTER(SvgdOpts), vp,
+                                 vp, vp, vp, C.c_size_t, vp]
+    L.smsq_run_sequence.argtypes = [vp, i32, i32, i32, vp, vp, vp, u64, C.POINTER(SvgdOpts), vp,
+                                    vp, vp, vp, C.c_size_t, vp]
+    L.smsq_get_device_status.argtypes = [vp, C.POINTER(C.c_int)]
+    L.smsq_clear_device_status.argtypes = [vp, vp]
+    L.smsq_status_string.argtypes = [C.c_int]
+    L.smsq_status_string.restype = C.c_char_p
+    L.smsq_max_particles.argtypes = [vp, i32]
+    for name in SYMBOLS:
+        fn = getattr(L, name)
+        if fn.restype is None or fn.restype is C.c_int:
+            fn.restype = C.c_int
+    L.smsq_status_string.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    return load().smsq_status_string(st).decode()
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise SmsqError(st, where)
+
+
+def _dt(dtype) -> int:
+    if dtype in (torch.float32, "f32", F32):
+        return F32
+    if dtype in (torch.float64, "f64", F64):
+        return F64
+    raise ValueError("dtype must be float32 or float64")
+
+
+def torch_dtype(dtype) -> torch.dtype:
+    return torch.float64 if _dt(dtype) == F64 else torch.float32
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: Optional[torch.dtype] = None, name: str = "") -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def opts(n_iter: int, step: float, bw_scale: float = 1.0, bw_mode: int = 0,
+         trans_mode: int = 0) -> SvgdOpts:
+    return SvgdOpts(int(n_iter), float(step), float(bw_scale), int(bw_mode), int(trans_mode))
+
+
+def opts_from(o) -> SvgdOpts:
+    return opts(o.n_iter, o.step, o.bw_scale, o.bw_mode, o.trans_mode)
+
+
+class Model:
+    """Owns a model handle (smsq_model_create / smsq_model_destroy)."""
+
+    def __init__(self, desc):
+        L = load()
+        md = ModelDesc()
+        md.kind, md.d, md.obs_dim, md.n_obs = int(desc.kind), int(desc.d), int(desc.obs_dim), int(desc.n_obs)
+        q = np.zeros(8)
+        q[:len(desc.q_var)] = desc.q_var
+        p = np.zeros(64)
+        p[:len(desc.params)] = desc.params
+        md.q_var[:] = list(q)
+        md.params[:] = list(p)
+        h = C.c_void_p()
+        _check(L.smsq_model_create(C.byref(md), C.byref(h)), "smsq_model_create")
+        self.handle = h
+        self.d = md.d
+        self.obs_dim = md.obs_dim
+        self.n_obs = md.n_obs
+
+    def close(self):
+        if self.handle:
+            load().smsq_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def max_particles(self, dtype) -> int:
+        return load().smsq_max_particles(self.handle, _dt(dtype))
+
+    def workspace_size(self, dtype, batch: int, T: int, n: int) -> int:
+        b = C.c_size_t(0)
+        _check(load().smsq_workspace_size(self.handle, _dt(dtype), batch, T, n, C.byref(b)),
+               "smsq_workspace_size")
+        return b.value
+
+
+HEADER_BYTES = 256
+
+
+def workspace(nbytes: int = HEADER_BYTES, device="cuda") -> torch.Tensor:
+    """Zeroed device workspace of nbytes bytes."""
+    return torch.zeros(max(int(nbytes), HEADER_BYTES), dtype=torch.uint8, device=device)
+
+
+def device_status(ws: torch.Tensor) -> int:
+    torch.cuda.synchronize()
+    out = C.c_int(0)
+    _check(load().smsq_get_device_status(_ptr(ws, torch.uint8, "ws"), C.byref(out)),
+           "smsq_get_device_status")
+    return out.value
+
+
+def clear_device_status(ws: torch.Tensor, stream=None):
+    _check(load().smsq_clear_device_status(_ptr(ws, torch.uint8, "ws"), _stream(stream)),
+           "smsq_clear_device_status")
+
+
+def svgd_step(model: Model, dtype, t: int, x_prev: torch.Tensor, log_w_prev: Optional[torch.Tensor],
+              z_t: torch.Tensor, z_mask: Optional[torch.Tensor], x: torch.Tensor, o: SvgdOpts,
+              h_out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    """In-place SVGD step on x [n, d] (smsq_svgd_step)."""
+    td = torch_dtype(dtype)
+    ws = workspace() if ws is None else ws
+    st = load().smsq_svgd_step(model.handle, _dt(dtype), t, x_prev.shape[0], _ptr(x_prev, td, "x_prev"),
+                               _ptr(log_w_prev, td, "log_w_prev"), _ptr(z_t, td, "z_t"),
+                               _ptr(z_mask, torch.uint8, "z_mask"), x.shape[0], _ptr(x, td, "x"),
+                               C.byref(o), _ptr(h_out, td, "h_out"), _ptr(ws, torch.uint8, "ws"),
+                               ws.numel(), _stream(stream))
+    _check(st, "smsq_svgd_step")
+    return x
+
+
+def viterbi_step(model: Optional[Model], dtype, t: int, phi_prev: torch.Tensor, *, x_prev=None,
+                 z_t=None, z_mask=None, x=None, lattice=None, loglik=None, tie_tol: float = 0.0,
+                 want_flags: bool = True, ws: Optional[torch.Tensor] = None, stream=None):
+    """Forward-recursion step (smsq_viterbi_step).  Returns (phi, psi, flags)."""
+    td = torch_dtype(dtype)
+    n_prev = phi_prev.shape[0]
+    n = lattice.shape[0] if lattice is not None else x.shape[0]
+    dev = phi_prev.device
+    phi = torch.empty(n, dtype=td, device=dev)
+    psi = torch.empty(n, dtype=torch.int32, device=dev)
+    flags = torch.empty(n, dtype=torch.uint8, device=dev) if want_flags else None
+    ws = workspace(device=dev) if ws is None else ws
+    st = load().smsq_viterbi_step(model.handle if model is not None else None, _dt(dtype), t, n_prev,
+                                  _ptr(x_prev, td, "x_prev"), _ptr(phi_prev, td, "phi_prev"),
+                                  _ptr(z_t, td, "z_t"), _ptr(z_mask, torch.uint8, "z_mask"), n,
+                                  _ptr(x, td, "x"), _ptr(lattice, td, "lattice"),
+                                  _ptr(loglik, td, "loglik"), _ptr(phi, td), _ptr(psi), _ptr(flags),
+                                  float(tie_tol), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+                                  _stream(stream))
+    _check(st, "smsq_viterbi_step")
+    return phi, psi, flags
+
+
+def backtrack(dtype, psi: torch.Tensor, phi_T: torch.Tensor, particles=None, x0=None,
+              ws: Optional[torch.Tensor] = None, stream=None):
+    """Backtracking over [batch, T, n] back-pointers.  Returns (idx, J, xmap or None)."""
+    td = torch_dtype(dtype)
+    if psi.dim() == 2:
+        psi = psi.unsqueeze(0)
+        phi_T = phi_T.unsqueeze(0)
+        if particles is not None:
+            particles = particles.unsqueeze(0)
+            x0 = x0.unsqueeze(0)
+    B, T, n = psi.shape
+    d = particles.shape[-1] if particles is not None else 0
+    dev = psi.device
+    idx = torch.empty((B, T), dtype=torch.int32, device=dev)
+    J = torch.empty(B, dtype=td, device=dev)
+    xmap = torch.empty((B, T + 1, d), dtype=td, device=dev) if particles is not None else None
+    ws = workspace(device=dev) if ws is None else ws
+    st = load().smsq_backtrack(_dt(dtype), B, T, n, d, _ptr(psi, torch.int32, "psi"),
+                               _ptr(phi_T, td, "phi_T"), _ptr(idx), _ptr(J), _ptr(particles, td, "particles"),
+                               _ptr(x0, td, "x0"), _ptr(xmap), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+                               _stream(stream))
+    _check(st, "smsq_backtrack")
+    return idx, J, xmap
+
+
+def _batched(t: Optional[torch.Tensor], dtype: Optional[torch.dtype], name: str):
+    """(pointer, element stride between sequences) of a [B, ...] view whose
+    per-sequence block is contiguous."""
+    if t is None:
+        return None, 0
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    inner = t[0] if t.shape[0] > 0 else t
+    if not inner.is_contiguous():
+        raise ValueError("%s: each sequence's block must be contiguous" % name)
+    return t.data_ptr(), (t.stride(0) if t.shape[0] > 1 else inner.numel())
+
+
+def batch_step(model: Model, dtype, t: int, x_prev: torch.Tensor, phi_prev: Optional[torch.Tensor],
+               z_t: torch.Tensor, z_mask: Optional[torch.Tensor], x: torch.Tensor, o: SvgdOpts, *,
+               init_given: bool = False, seed: int = 0, seq_offset: int = 0, phi=None, psi=None,
+               flags=None, tie_tol: float = 0.0, ws: Optional[torch.Tensor] = None, stream=None):
+    """One step of Algorithm 2 for a batch (smsq_batch_step).
+
+    x_prev [B, n_prev, d], phi_prev [B, n_prev] or None (t = 1), z_t [B, obs_dim],
+    z_mask [B, n_obs] or None, x [B, n, d]; phi / psi / flags [B, n].  Each may be
+    a strided view (e.g. one step of a [B, T, ...] buffer) as long as every
+    sequence's block is contiguous.  phi_prev, phi, psi and flags share one
+    stride.
+    Returns (phi, psi, flags).
+    """
+    td = torch_dtype(dtype)
+    B, n, _ = x.shape
+    dev = x.device
+    phi = torch.empty((B, n), dtype=td, device=dev) if phi is None else phi
+    psi = torch.empty((B, n), dtype=torch.int32, device=dev) if psi is None else psi
+    ws = workspace(device=dev) if ws is None else ws
+    xp_ptr, xp_s = _batched(x_prev, td, "x_prev")
+    ph_ptr, ph_s = _batched(phi_prev, td, "phi_prev")
+    z_ptr, z_s = _batched(z_t, td, "z_t")
+    m_ptr, m_s = _batched(z_mask, torch.uint8, "z_mask")
+    x_ptr, x_s = _batched(x, td, "x")
+    phi_ptr, o_s = _batched(phi, td, "phi")
+    psi_ptr, o_s2 = _batched(psi, torch.int32, "psi")
+    fl_ptr, o_s3 = _batched(flags, torch.uint8, "flags")
+    if o_s2 != o_s or (flags is not None and o_s3 != o_s) or (phi_prev is not None and B > 1 and ph_s != o_s):
+        raise ValueError("phi_prev, phi, psi and flags must share one sequence stride")
+    st = load().smsq_batch_step(model.handle, _dt(dtype), B, t, x_prev.shape[1], xp_ptr, xp_s, ph_ptr,
+                                z_ptr, z_s, m_ptr, m_s, n, x_ptr, x_s, 1 if init_given else 0, int(seed),
+                                int(seq_offset), C.byref(o), phi_ptr, psi_ptr, fl_ptr, o_s,
+                                float(tie_tol), _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream(stream))
+    _check(st, "smsq_batch_step")
+    return phi, psi, flags
+
+
+def run_batch(model: Model, dtype, x0: torch.Tensor, z: torch.Tensor, z_mask: Optional[torch.Tensor],
+              n: int, o: SvgdOpts, seed: int, *, particles: Optional[torch.Tensor] = None,
+              ws: Optional[torch.Tensor] = None, stream=None):
+    """Algorithm 2 for B sequences (smsq_run_batch).  x0 [B, d], z [B, T, obs_dim].
+
+    Returns (xmap [B, T+1, d], J [B]).
+    """
+    td = torch_dtype(dtype)
+    B, T, _ = z.shape
+    d = x0.shape[1]
+    dev = x0.device
+    if ws is None:
+        ws = workspace(model.workspace_size(dtype, B, T, n), device=dev)
+    xmap = torch.empty((B, T + 1, d), dtype=td, device=dev)
+    J = torch.empty(B, dtype=td, device=dev)
+    st = load().smsq_run_batch(model.handle, _dt(dtype), B, T, n, _ptr(x0, td, "x0"), _ptr(z, td, "z"),
+                               _ptr(z_mask, torch.uint8, "z_mask"), int(seed), C.byref(o), _ptr(xmap),
+                               _ptr(J), _ptr(particles, td, "particles"), _ptr(ws, torch.uint8, "ws"),
+                               ws.numel(), _stream(stream))
+    _check(st, "smsq_run_batch")
+    return xmap, J
+
+
+def run_sequence(model: Model, dtype, x0: torch.Tensor, z: torch.Tensor, z_mask: Optional[torch.Tensor],
+                 n: int, o: SvgdOpts, seed: int, *, particles: Optional[torch.Tensor] = None,
+                 ws: Optional[torch.Tensor] = None, stream=None):
+    """Algorithm 2 for one sequence (smsq_run_sequence).  x0 [d], z [T, obs_dim]."""
+    td = torch_dtype(dtype)
+    T = z.shape[0]
+    d = x0.shape[0]
+    dev = x0.device
+    if ws is None:
+        ws = workspace(model.workspace_size(dtype, 1, T, n), device=dev)
+    xmap = torch.empty((T + 1, d), dtype=td, device=dev)
+    J = torch.empty(1, dtype=td, device=dev)
+    st = load().smsq_run_sequence(model.handle, _dt(dtype), T, n, _ptr(x0, td, "x0"), _ptr(z, td, "z"),
+                                  _ptr(z_mask, torch.uint8, "z_mask"), int(seed), C.byref(o), _ptr(xmap),
+                                  _ptr(J), _ptr(particles, td, "particles"), _ptr(ws, torch.uint8, "ws"),
+                                  ws.numel(), _stream(stream))
+    _check(st, "smsq_run_sequence")
+    return xmap, J

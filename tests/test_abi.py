@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every symbol include/smsq.h declares;
+host-only entry points validate their arguments (no device work)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+from paper_2312_08684_amd import scenarios as S
+from paper_2312_08684_amd import smsq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "smsq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(smsq_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = smsq.load()
+    names = declared_symbols()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(names) == sorted(smsq.SYMBOLS)
+
+
+def test_status_strings():
+    for st in range(6):
+        assert smsq.status_string(st)
+    assert smsq.status_string(99) == "unknown status"
+
+
+def test_model_validation_host_only():
+    for name in ("growth1d", "range2d", "cv4d", "arm7", "lingauss"):
+        m = smsq.Model(S._model_for(name, 0))
+        assert m.max_particles("f32") >= (1024 if name != "arm7" else 1024)
+        assert m.workspace_size("f32", 2, 10, 64) > 256
+        m.close()
+    bad = S._model_for("arm7", 0)
+    bad.q_var[2] = 0.0
+    try:
+        smsq.Model(bad)
+        raise AssertionError("zero variance accepted")
+    except smsq.SmsqError as e:
+        assert e.status == smsq.ERR_INVALID
+    bad = S._model_for("cv4d", 0)
+    bad.obs_dim = 7
+    try:
+        smsq.Model(bad)
+        raise AssertionError("odd detection layout accepted")
+    except smsq.SmsqError as e:
+        assert e.status == smsq.ERR_INVALID
+
+
+def test_workspace_size_grows_with_batch():
+    m = smsq.Model(S._model_for("range2d", 0))
+    a = m.workspace_size("f32", 1, 50, 256)
+    b = m.workspace_size("f32", 8, 50, 256)
+    c = m.workspace_size("f64", 8, 50, 256)
+    assert a < b < c
+    assert b >= 8 * 50 * 256 * 2 * 4

@@ -1,0 +1,400 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances (stated per result):
+  * forward recursion fed the oracle's FP64 lattice: bit-exact phi, psi, flags;
+  * backtracking: bit-exact indices and score;
+  * SVGD step, teacher-forced (same previous and initial particles on both
+    sides): ||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-4 in FP32 and
+    <= 1e-10 in FP64, after the full iteration count;
+  * trajectory log-posterior J: |dJ| <= 1e-3 max(|J|, T).
+The FP32-vs-FP64 errors measured here are printed with each case.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2312_08684_amd import scenarios as S
+from paper_2312_08684_amd import smsq
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+TOL_X = {"f32": 1e-4, "f64": 1e-10}
+TOL_H = {"f32": 1e-5, "f64": 1e-12}
+TOL_J = 1e-3
+TIE_F32 = 2.0 ** -20
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def tdt(dt):
+    return torch.float64 if dt == "f64" else torch.float32
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def announce(*what):
+    print("CASE", *what, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Forward recursion
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,n_prev", [(1, 1), (7, 1), (64, 64), (100, 37), (130, 257), (1024, 1024),
+                                      (1500, 700)])
+def test_viterbi_lattice_f64_bit_exact(n, n_prev):
+    announce("viterbi lattice f64", n, n_prev)
+    rng = np.random.default_rng(n * 1000 + n_prev)
+    A = rng.normal(size=(n, n_prev)) * 5
+    ell = rng.normal(size=n)
+    phi_prev = rng.normal(size=n_prev) * 10
+    # plant exact ties and -inf rows
+    if n_prev > 3:
+        A[0, 2] = A[0, 1] = A[0].max() + 1.0
+        phi_prev[1] = phi_prev[2]
+    if n > 2:
+        A[2, :] = -np.inf
+    phi_o, psi_o, fl_o, st_o = O.viterbi_lattice(A, ell, phi_prev, tie_tol=1e-9)
+    ws = smsq.workspace()
+    phi, psi, fl = smsq.viterbi_step(None, "f64", 1, dev(phi_prev, torch.float64),
+                                     lattice=dev(A, torch.float64), loglik=dev(ell, torch.float64),
+                                     tie_tol=1e-9, ws=ws)
+    assert np.array_equal(host(psi), psi_o)
+    assert np.array_equal(host(phi), phi_o)
+    assert np.array_equal(host(fl), fl_o)
+    assert smsq.device_status(ws) == smsq.OK
+
+
+def test_viterbi_lattice_nan_sets_status():
+    announce("viterbi lattice nan")
+    A = np.zeros((3, 5))
+    A[1, 3] = np.nan
+    ws = smsq.workspace()
+    smsq.viterbi_step(None, "f64", 1, dev(np.zeros(5), torch.float64), lattice=dev(A, torch.float64),
+                      loglik=dev(np.zeros(3), torch.float64), ws=ws)
+    assert smsq.device_status(ws) == smsq.ERR_NONFINITE
+
+
+@pytest.mark.parametrize("n,n_prev", [(33, 65), (512, 512)])
+def test_viterbi_lattice_f32(n, n_prev):
+    announce("viterbi lattice f32", n, n_prev)
+    rng = np.random.default_rng(7 + n)
+    A = (rng.normal(size=(n, n_prev)) * 5).astype(np.float32)
+    ell = rng.normal(size=n).astype(np.float32)
+    phi_prev = (rng.normal(size=n_prev) * 10).astype(np.float32)
+    phi_o, psi_o, fl_o, _ = O.viterbi_lattice(A.astype(np.float64), ell.astype(np.float64),
+                                              phi_prev.astype(np.float64), tie_tol=TIE_F32)
+    phi, psi, fl = smsq.viterbi_step(None, "f32", 1, dev(phi_prev, torch.float32),
+                                     lattice=dev(A, torch.float32), loglik=dev(ell, torch.float32),
+                                     tie_tol=TIE_F32)
+    psi, phi = host(psi), host(phi).astype(np.float64)
+    sure = fl_o == 0
+    assert np.array_equal(psi[sure], psi_o[sure])
+    c = A.astype(np.float64) + phi_prev[None, :]
+    best = c.max(1)
+    chosen = c[np.arange(n), psi]
+    assert np.all(chosen >= best - 4 * TIE_F32 * np.maximum(1, np.abs(best)))
+    assert np.allclose(phi, phi_o, rtol=1e-6, atol=1e-5)
+
+
+def _particle_case(name, n, n_prev, seed):
+    wl = S.make_workload(name, B=1, seed=seed, T=3)
+    desc = wl.model
+    rng = np.random.default_rng(seed + 17)
+    sd = np.sqrt(desc.q_var[:desc.d])
+    xp = wl.truth[0, 1][None, :] + 2 * sd * rng.normal(size=(n_prev, desc.d))
+    means = np.stack([O.transition_mean(desc, 2, v) for v in xp])
+    x = means[rng.integers(n_prev, size=n)] + sd * rng.normal(size=(n, desc.d))
+    return wl, desc, xp, x
+
+
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_viterbi_particle_mode(name, dt):
+    announce("viterbi particle", name, dt)
+    n, n_prev = 150, 77
+    wl, desc, xp, x = _particle_case(name, n, n_prev, 3)
+    z = wl.z[0, 1]
+    mask = None if wl.mask is None else wl.mask[0, 1]
+    rng = np.random.default_rng(5)
+    phi_prev = rng.normal(size=n_prev) * 3
+    td = tdt(dt)
+    if dt == "f32":
+        xp = xp.astype(np.float32).astype(np.float64)
+        x = x.astype(np.float32).astype(np.float64)
+        phi_prev = phi_prev.astype(np.float32).astype(np.float64)
+        z = z.astype(np.float32).astype(np.float64)
+    tol = 1e-5 if dt == "f32" else 1e-9
+    phi_o, psi_o, fl_o, st = O.viterbi_particle(desc, 2, xp, phi_prev, z, mask, x, tie_tol=tol)
+    assert st == O.OK
+    model = smsq.Model(desc)
+    phi, psi, fl = smsq.viterbi_step(model, dt, 2, dev(phi_prev, td), x_prev=dev(xp, td), z_t=dev(z, td),
+                                     z_mask=None if mask is None else dev(mask, torch.uint8),
+                                     x=dev(x, td), tie_tol=tol)
+    psi, phi = host(psi), host(phi).astype(np.float64)
+    sure = fl_o == 0
+    assert sure.mean() > 0.5
+    assert np.array_equal(psi[sure], psi_o[sure])
+    A, ell = O.particle_lattice(desc, 2, xp, z, mask, x)
+    c = A + phi_prev[None, :]
+    best = c.max(1)
+    assert np.all(c[np.arange(n), psi] >= best - 4 * tol * np.maximum(1, np.abs(best)))
+    err = np.abs(phi - phi_o) / np.maximum(1, np.abs(phi_o))
+    print("phi rel err", err.max())
+    # FP32 evaluation of the log-densities (e.g. the arm's forward kinematics,
+    # d ell / d p ~ |z - p| / r ~ 500 times a ~1e-7 position rounding) bounds
+    # the FP32 error near 1e-4 relative
+    assert err.max() <= (1e-4 if dt == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_backtrack_bit_exact(dt):
+    announce("backtrack", dt)
+    rng = np.random.default_rng(11)
+    B, T, n = 5, 40, 70
+    psi = rng.integers(0, n, size=(B, T, n)).astype(np.int32)
+    phi_T = rng.normal(size=(B, n))
+    phi_T[0, 3] = phi_T[0, 9] = phi_T[0].max() + 1   # tie -> lowest index
+    if dt == "f32":
+        phi_T = phi_T.astype(np.float32).astype(np.float64)
+    parts = rng.normal(size=(B, T, n, 3))
+    x0 = rng.normal(size=(B, 3))
+    td = tdt(dt)
+    idx, J, xmap = smsq.backtrack(dt, dev(psi, torch.int32), dev(phi_T, td), dev(parts, td), dev(x0, td))
+    idx, J, xmap = host(idx), host(J), host(xmap)
+    for b in range(B):
+        ii, jj, st = O.backtrack(psi[b], phi_T[b])
+        assert np.array_equal(idx[b], ii)
+        assert J[b] == (np.float32(jj) if dt == "f32" else jj)
+        assert np.array_equal(xmap[b, 0], x0[b].astype(np.float32) if dt == "f32" else x0[b])
+        want = parts[b, np.arange(T), ii]
+        assert np.array_equal(xmap[b, 1:], want.astype(np.float32) if dt == "f32" else want)
+
+
+# ---------------------------------------------------------------------------
+# SVGD step, teacher-forced
+# ---------------------------------------------------------------------------
+
+def _svgd_case(name, n, n_prev, seed, dt):
+    wl, desc, xp, x = _particle_case(name, n, n_prev, seed)
+    z = wl.z[0, 1]
+    mask = None if wl.mask is None else wl.mask[0, 1]
+    if dt == "f32":
+        xp = xp.astype(np.float32).astype(np.float64)
+        x = x.astype(np.float32).astype(np.float64)
+        z = z.astype(np.float32).astype(np.float64)
+    return wl, desc, xp, x, z, mask
+
+
+def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mode=0, trans_mode=0):
+    td = tdt(dt)
+    xo, ho, st = O.svgd_step(desc, 2, xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode)
+    assert st == O.OK
+    model = smsq.Model(desc)
+    xg = dev(x, td)
+    hg = torch.zeros(max(L, 1), dtype=td, device=DEV)
+    ws = smsq.workspace()
+    smsq.svgd_step(model, dt, 2, dev(xp, td), None if log_w is None else dev(log_w, td), dev(z, td),
+                   None if mask is None else dev(mask, torch.uint8), xg,
+                   smsq.opts(L, step, bw_scale, bw_mode, trans_mode), h_out=hg, ws=ws)
+    assert smsq.device_status(ws) == smsq.OK
+    xg, hg = host(xg).astype(np.float64), host(hg).astype(np.float64)[:L]
+    rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    disp = np.linalg.norm(xo - x)
+    rel_disp = np.linalg.norm(xg - xo) / max(disp, 1e-300)
+    herr = np.abs(hg - ho).max() / np.abs(ho).max() if L else 0.0
+    print("rel X err %.3e  rel displacement err %.3e  rel h err %.3e" % (rel, rel_disp, herr))
+    assert rel <= TOL_X[dt]
+    assert herr <= TOL_H[dt]
+    return xo, xg
+
+
+SVGD_CASES = [
+    ("growth1d", 32, 32, 100, 0.05),
+    ("growth1d", 100, 33, 40, 0.05),
+    ("range2d", 257, 200, 20, 0.005),
+    ("cv4d", 130, 64, 20, 0.005),
+    ("arm7", 200, 129, 20, 1e-5),
+    ("lingauss", 70, 70, 30, 0.01),
+]
+
+
+@pytest.mark.parametrize("name,n,n_prev,L,step", SVGD_CASES)
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_svgd_step_teacher_forced(name, n, n_prev, L, step, dt):
+    announce("svgd step", name, n, n_prev, L, dt)
+    wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 21, dt)
+    _compare_svgd(desc, dt, xp, None, z, mask, x, L, step)
+
+
+@pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "one_particle",
+                                     "two_particles", "ragged_1025"])
+def test_svgd_step_variants(variant):
+    announce("svgd variant", variant)
+    name, n, n_prev, L, step = "range2d", 96, 50, 15, 0.005
+    log_w, bw_scale, bw_mode, trans_mode = None, 1.0, 0, 0
+    if variant == "one_particle":
+        n = 1
+    if variant == "two_particles":
+        n = 2
+    if variant == "ragged_1025":
+        name, n, n_prev, L, step = "cv4d", 1025, 300, 3, 0.005
+    wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 4, "f32")
+    if variant == "weights":
+        rng = np.random.default_rng(3)
+        log_w = np.log(rng.dirichlet(np.ones(n_prev))).astype(np.float32).astype(np.float64)
+    if variant == "mean_reading":
+        trans_mode = 1
+    if variant == "per_step_bw":
+        bw_mode = 1
+    if variant == "bw3":
+        bw_scale = 3.0
+    _compare_svgd(desc, "f32", xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode)
+
+
+def test_svgd_step_full_arm7_shape():
+    """N = 1024, d = 7, 100 iterations: the arm workload's step at full size."""
+    announce("svgd step full arm7 1024x7 L=100")
+    wl, desc, xp, x, z, mask = _svgd_case("arm7", 1024, 1024, 8, "f32")
+    _compare_svgd(desc, "f32", xp, None, z, mask, x, 100, 1e-5)
+
+
+def test_svgd_nonfinite_observation_sets_status():
+    announce("svgd nan observation")
+    wl, desc, xp, x, z, mask = _svgd_case("range2d", 64, 64, 5, "f32")
+    z = z.copy()
+    z[0] = np.nan
+    model = smsq.Model(desc)
+    ws = smsq.workspace()
+    smsq.svgd_step(model, "f32", 2, dev(xp, torch.float32), None, dev(z, torch.float32), None,
+                   dev(x, torch.float32), smsq.opts(3, 0.005), ws=ws)
+    assert smsq.device_status(ws) == smsq.ERR_NONFINITE
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 end to end
+# ---------------------------------------------------------------------------
+
+def test_run_sequence_growth1d_full_f64():
+    """The 1-D growth workload at full size (N=32, T=50, L=100, eps=0.05), FP64."""
+    announce("run_sequence growth1d full f64")
+    wl = S.make_workload("growth1d", B=1, seed=1000)
+    desc = wl.model
+    o = wl.opts
+    res = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 77, 0, o.n_iter, o.step)
+    model = smsq.Model(desc)
+    xmap, J = smsq.run_sequence(model, "f64", dev(wl.x0[0], torch.float64), dev(wl.z[0], torch.float64),
+                                None, wl.n, smsq.opts_from(o), 77)
+    xmap, J = host(xmap), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), wl.T)
+    print("J gpu %.10f oracle %.10f rel %.3e  max|dx| %.3e" % (J, res["J"], dJ, np.abs(xmap - res["xmap"]).max()))
+    assert dJ <= TOL_J
+    assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("name,n,T,L", [("range2d", 64, 12, 10), ("cv4d", 80, 8, 10), ("arm7", 96, 6, 10),
+                                        ("lingauss", 48, 10, 20)])
+def test_run_sequence_f32_free_running(name, n, T, L):
+    announce("run_sequence f32", name, n, T, L)
+    wl = S.make_workload(name, B=1, seed=1001, T=T, n=n, n_iter=L)
+    desc = wl.model
+    o = wl.opts
+    mask = None if wl.mask is None else wl.mask[0]
+    res = O.run_sequence(desc, T, n, wl.x0[0], wl.z[0], mask, 5, 0, o.n_iter, o.step)
+    model = smsq.Model(desc)
+    parts = torch.zeros((T, n, desc.d), dtype=torch.float32, device=DEV)
+    xmap, J = smsq.run_sequence(model, "f32", dev(wl.x0[0], torch.float32), dev(wl.z[0], torch.float32),
+                                None if mask is None else dev(mask, torch.uint8), n, smsq.opts_from(o), 5,
+                                particles=parts)
+    xmap, J = host(xmap).astype(np.float64), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), T)
+    print("J gpu %.6f oracle %.6f rel %.3e" % (J, res["J"], dJ))
+    assert dJ <= TOL_J
+    # J is the path score of the returned trajectory (evaluated by the oracle in FP64)
+    Jpath = O.path_score(desc, xmap, wl.z[0], mask)
+    assert abs(Jpath - J) <= TOL_J * max(abs(J), T)
+
+
+def test_run_batch_matches_single_runs_and_is_deterministic():
+    announce("run_batch determinism")
+    wl = S.make_workload("range2d", B=3, seed=1002, T=10, n=48, n_iter=8)
+    desc = wl.model
+    model = smsq.Model(desc)
+    o = smsq.opts_from(wl.opts)
+    x0 = dev(wl.x0, torch.float32)
+    z = dev(wl.z, torch.float32)
+    mk = dev(wl.mask, torch.uint8)
+    xm1, J1 = smsq.run_batch(model, "f32", x0, z, mk, wl.n, o, 9)
+    xm2, J2 = smsq.run_batch(model, "f32", x0, z, mk, wl.n, o, 9)
+    assert torch.equal(xm1, xm2) and torch.equal(J1, J2)
+    # sequence b of a batch uses Philox counter word 2 = b; a single run uses 0
+    xs, Js = smsq.run_sequence(model, "f32", x0[0].contiguous(), z[0].contiguous(), mk[0].contiguous(),
+                               wl.n, o, 9)
+    assert torch.equal(xs, xm1[0]) and torch.equal(Js, J1[:1])
+
+
+def test_run_batch_full_arm7_sampled_step():
+    """Full arm workload (N=1024, d=7, L=100, T=100) in the benchmark's launch
+    configuration; the oracle recomputes a sampled step from the GPU's previous
+    particles (predictive initial particles from the same Philox counters) and
+    the score J along the returned path."""
+    announce("run_batch full arm7 sampled step")
+    wl = S.make_workload("arm7", B=2, seed=1003)
+    desc = wl.model
+    o = wl.opts
+    model = smsq.Model(desc)
+    B, T, n, d = wl.batch, wl.T, wl.n, desc.d
+    parts = torch.zeros((B, T, n, d), dtype=torch.float32, device=DEV)
+    xmap, J = smsq.run_batch(model, "f32", dev(wl.x0, torch.float32), dev(wl.z, torch.float32), None, n,
+                             smsq.opts_from(o), 31, particles=parts)
+    parts, xmap, J = host(parts).astype(np.float64), host(xmap).astype(np.float64), host(J).astype(np.float64)
+    assert np.all(np.isfinite(parts))
+    for b in range(B):
+        Jpath = O.path_score(desc, xmap[b], wl.z[b])
+        print("seq %d J %.4f path score %.4f" % (b, J[b], Jpath))
+        assert abs(Jpath - J[b]) <= TOL_J * max(abs(J[b]), T)
+    t = 57
+    b = 1
+    xprev = parts[b, t - 2]
+    x_init = O.predictive_init(desc, t, xprev, n, 31, b)
+    xo, _, st = O.svgd_step(desc, t, xprev, None, wl.z[b, t - 1], None, x_init, o.n_iter, o.step)
+    rel = np.linalg.norm(parts[b, t - 1] - xo) / np.linalg.norm(xo)
+    print("sampled step t=%d rel X err %.3e" % (t, rel))
+    assert rel <= TOL_X["f32"]
+
+
+# ---------------------------------------------------------------------------
+# Argument errors (no device work is enqueued)
+# ---------------------------------------------------------------------------
+
+def test_argument_errors():
+    announce("argument errors")
+    desc = S._model_for("range2d", 0)
+    model = smsq.Model(desc)
+    x = torch.zeros((4, 2), device=DEV)
+    z = torch.zeros(3, device=DEV)
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None, x,
+                       smsq.opts(-1, 0.1))
+    assert e.value.status == smsq.ERR_INVALID
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None, x,
+                       smsq.opts(2, 0.1), ws=torch.zeros(16, dtype=torch.uint8, device=DEV))
+    assert e.value.status == smsq.ERR_WORKSPACE
+    big = model.max_particles("f32") + 1
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None,
+                       torch.zeros((big, 2), device=DEV), smsq.opts(2, 0.1))
+    assert e.value.status == smsq.ERR_UNSUPPORTED
+    bad = desc.copy()
+    bad.d = 3
+    with pytest.raises(smsq.SmsqError):
+        smsq.Model(bad)

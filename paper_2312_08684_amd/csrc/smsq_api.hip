@@ -11,6 +11,9 @@
 
 #include "smsq.h"
 #include "smsq_kernels.hpp"
+#include "smsq_mfma.hpp"
+
+#include <cstdlib>
 
 using namespace smsq;
 
@@ -142,20 +145,81 @@ smsq_status_t launch_step_kd(const StepArgs<T> &a, int batch, hipStream_t s)
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
 
-template <typename T>
-smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int batch, hipStream_t s)
+// The FP32 matrix-core kernel takes sequences of up to 1024 particles whose
+// state fits LDS; SMSQ_STEP_KERNEL=valu selects the vector-ALU kernel instead.
+bool use_mfma(int n, int n_prev)
 {
+    const char *e = std::getenv("SMSQ_STEP_KERNEL");
+    if (e && std::strcmp(e, "valu") == 0) return false;
+    const MfmaLds L(n, n_prev);
+    return L.npad <= 1024 && L.total <= kLdsLimit;
+}
+
+template <int KIND, int D>
+smsq_status_t launch_mfma_kd(const StepArgs<float> &a, int batch, hipStream_t s)
+{
+    auto fn = &k_step_mfma<KIND, D>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] { attr_err = allow_big_lds(fn); });
+    if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
+    const MfmaLds L(a.n, a.n_prev);
+    hipLaunchKernelGGL(fn, dim3(batch), dim3(L.nwaves * kWave), (size_t)L.total, s, a);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+template <typename T>
+smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int batch, hipStream_t s);
+
+template <>
+smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
+{
+    if (use_mfma(a.n, a.n_prev)) {
+        switch (d.kind) {
+        case SMSQ_MODEL_GROWTH1D: return launch_mfma_kd<GROWTH1D, 1>(a, batch, s);
+        case SMSQ_MODEL_RANGE2D: return launch_mfma_kd<RANGE2D, 2>(a, batch, s);
+        case SMSQ_MODEL_CV4D: return launch_mfma_kd<CV4D, 4>(a, batch, s);
+        case SMSQ_MODEL_ARM7: return launch_mfma_kd<ARM7, 7>(a, batch, s);
+        case SMSQ_MODEL_LINGAUSS:
+            switch (d.d) {
+            case 1: return launch_mfma_kd<LINGAUSS, 1>(a, batch, s);
+            case 2: return launch_mfma_kd<LINGAUSS, 2>(a, batch, s);
+            case 3: return launch_mfma_kd<LINGAUSS, 3>(a, batch, s);
+            case 4: return launch_mfma_kd<LINGAUSS, 4>(a, batch, s);
+            }
+        }
+        return SMSQ_ERR_INVALID;
+    }
     switch (d.kind) {
-    case SMSQ_MODEL_GROWTH1D: return launch_step_kd<T, GROWTH1D, 1>(a, batch, s);
-    case SMSQ_MODEL_RANGE2D: return launch_step_kd<T, RANGE2D, 2>(a, batch, s);
-    case SMSQ_MODEL_CV4D: return launch_step_kd<T, CV4D, 4>(a, batch, s);
-    case SMSQ_MODEL_ARM7: return launch_step_kd<T, ARM7, 7>(a, batch, s);
+    case SMSQ_MODEL_GROWTH1D: return launch_step_kd<float, GROWTH1D, 1>(a, batch, s);
+    case SMSQ_MODEL_RANGE2D: return launch_step_kd<float, RANGE2D, 2>(a, batch, s);
+    case SMSQ_MODEL_CV4D: return launch_step_kd<float, CV4D, 4>(a, batch, s);
+    case SMSQ_MODEL_ARM7: return launch_step_kd<float, ARM7, 7>(a, batch, s);
     case SMSQ_MODEL_LINGAUSS:
         switch (d.d) {
-        case 1: return launch_step_kd<T, LINGAUSS, 1>(a, batch, s);
-        case 2: return launch_step_kd<T, LINGAUSS, 2>(a, batch, s);
-        case 3: return launch_step_kd<T, LINGAUSS, 3>(a, batch, s);
-        case 4: return launch_step_kd<T, LINGAUSS, 4>(a, batch, s);
+        case 1: return launch_step_kd<float, LINGAUSS, 1>(a, batch, s);
+        case 2: return launch_step_kd<float, LINGAUSS, 2>(a, batch, s);
+        case 3: return launch_step_kd<float, LINGAUSS, 3>(a, batch, s);
+        case 4: return launch_step_kd<float, LINGAUSS, 4>(a, batch, s);
+        }
+    }
+    return SMSQ_ERR_INVALID;
+}
+
+template <>
+smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<double> &a, int batch, hipStream_t s)
+{
+    switch (d.kind) {
+    case SMSQ_MODEL_GROWTH1D: return launch_step_kd<double, GROWTH1D, 1>(a, batch, s);
+    case SMSQ_MODEL_RANGE2D: return launch_step_kd<double, RANGE2D, 2>(a, batch, s);
+    case SMSQ_MODEL_CV4D: return launch_step_kd<double, CV4D, 4>(a, batch, s);
+    case SMSQ_MODEL_ARM7: return launch_step_kd<double, ARM7, 7>(a, batch, s);
+    case SMSQ_MODEL_LINGAUSS:
+        switch (d.d) {
+        case 1: return launch_step_kd<double, LINGAUSS, 1>(a, batch, s);
+        case 2: return launch_step_kd<double, LINGAUSS, 2>(a, batch, s);
+        case 3: return launch_step_kd<double, LINGAUSS, 3>(a, batch, s);
+        case 4: return launch_step_kd<double, LINGAUSS, 4>(a, batch, s);
         }
     }
     return SMSQ_ERR_INVALID;

@@ -106,6 +106,13 @@ __device__ inline void normals8(uint64_t seed, uint32_t seq, uint32_t t, uint32_
     }
 }
 
+// Index of the calling wave in its workgroup, as a scalar (wave-uniform)
+// value so that loops over per-wave work compile to scalar loop control.
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
 // ---- wave-level reductions ---------------------------------------------------
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {

@@ -83,7 +83,7 @@ __device__ T block_median_sqdist(const T *sx, int n, uint32_t *hist, uint32_t *r
     using KO = KeyOf<T>;
     using K = typename KO::K;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nt / kWave;
+    const int lane = tid & (kWave - 1), wave = wave_id(), nwaves = nt / kWave;
     const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
     if (M == 0) return __builtin_nan("");
     uint32_t rank = (M - 1) / 2;

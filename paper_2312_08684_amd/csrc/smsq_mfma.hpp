@@ -1,0 +1,855 @@
+// FP32 step kernel on the matrix cores (v_mfma_f32_16x16x4f32, wave64).
+//
+// Same computation as k_step (one workgroup per sequence, state in LDS), with
+// the pairwise work of every SVGD iteration (eq. SVGD_newupdate) on MFMA:
+//   * bandwidth: the squared distances D_ik = n_i + n_k - 2 x_i . x_k come
+//     from 16x16 Gram tiles; the exact lower median is found by one pass that
+//     counts the distances below a window predicted from the previous
+//     iterations' medians and keeps those inside it, followed by a radix
+//     selection among the kept values (full radix selection as fallback);
+//   * scores: the transition-mixture softmax over the previous particles,
+//     logit_kj = 2 mh_j . xh_k + c_j - |mh_j|^2 (log2 units; the common
+//     -|xh_k|^2 drops out), as 16x16 logit tiles [xh_k, 1] . [2 mh_j, c'_j],
+//     a per-particle reference maximum raised only when a tile exceeds it by
+//     2^8, exp2 on the VALU, and the weighted sums sum_j e_kj [2 mh_j, 1]
+//     accumulated by MFMA;
+//   * Stein direction: Gram tiles give the kernel argument
+//     2 beta x_k . x_i - beta n_k (the norm rides in the free eighth
+//     K-column), kappa_ik = exp2(that - beta n_i) with beta = log2(e) / h,
+//     and sum_k kappa_ik [s_k, 1, x_k] is accumulated by MFMA.
+// Particles are stored centred on the mean of the previous step's transition
+// means, which keeps |x|^2 small next to the squared distances in FP32.
+//
+// Operand layouts of v_mfma_f32_16x16x4f32 (checked on gfx950): lane l gives
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
+// D[4 (l / 16) + r][l % 16].
+#pragma once
+
+#include "smsq_kernels.hpp"
+
+namespace smsq {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float fmax_(float a, float b) { return a > b ? a : b; }
+
+// a block-uniform value kept in a scalar register
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// max over the four 16-lane groups that hold the same column (lanes l, l^16,
+// l^32, l^48)
+__device__ __forceinline__ float group_max4(float v)
+{
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    const float m1 = fmax_(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
+    return fmax_(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
+constexpr int kTilesPerWave = 4;  // register blocking: 64 particles per wave task
+constexpr int kWaveScratch = 512; // floats of per-wave LDS scratch
+constexpr int kWinCap = 4096;     // capacity of the median window buffer (floats)
+constexpr int kWinRegion = kWinCap / 16; // per-wave share of the window buffer
+constexpr int kWinTarget = 1024;  // aimed-for number of distances in the window
+constexpr float kRescaleGap = 8.f; // log2 headroom before the softmax reference moves
+
+// LDS byte layout of the MFMA step workgroup.
+struct MfmaLds {
+    long off_x, off_s, off_m, off_phip, off_scr, off_win, off_z, off_mask, off_red, total;
+    int npad, nppad, nwaves;
+    __host__ __device__ MfmaLds(int n, int n_prev)
+    {
+        npad = (n + 63) / 64 * 64;
+        nppad = (n_prev + 15) / 16 * 16;
+        nwaves = npad / 64 < 16 ? npad / 64 : 16;
+        long o = 0;
+        off_x = o; o += align16((long)npad * 8 * 4);
+        off_s = o; o += align16((long)npad * 8 * 4);
+        off_m = o; o += align16((long)nppad * 8 * 4);
+        off_phip = o; o += align16((long)nppad * 4);
+        long scr = (long)nwaves * kWaveScratch * 4;
+        if (scr < (long)kBins * 4) scr = (long)kBins * 4;  // also the radix-selection histogram
+        off_scr = o; o += scr;
+        off_win = o; o += (long)(kWinCap + 256) * 4;       // window buffer + its histogram
+        off_z = o; o += align16((long)kMaxObs * 4);
+        off_mask = o; o += 64;
+        off_red = o; o += 512;  // uint slots 0..63, float slots from byte 256
+        total = o;
+    }
+};
+
+// Visits the squared distances D_ik = n_i + n_k - 2 x_i . x_k of every pair
+// i < k from 16x16 MFMA Gram tiles: the A rows are the source particles with
+// their norm n_k in column 7 (padding for d <= 7), the B columns are
+// -2 x_i with a 1 in row 7, so the tile holds n_k - 2 x_k . x_i and one add
+// of n_i finishes it.  Each wave takes whole rows of tiles (target tile ib,
+// source tiles kb >= ib) and issues the MFMAs of four source tiles before
+// using any result.  fn(Dv, valid) receives the four distances of a lane for
+// one tile (k = 16 kb + 4 g + r, i = 16 ib + col); in the diagonal tile only
+// k > i is valid.  Pad particles have n = +inf, so their distances are +inf.
+template <typename Fn>
+__device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn &&fn)
+{
+    constexpr int kBatch = 4;
+    const int lane = threadIdx.x & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const int nt16 = npad / 16;
+    // Rows of tiles (target tile ib, source tiles kb >= ib) go to the waves in
+    // snake order, which gives every wave the same number of tiles when the
+    // row count is a multiple of 2 * nwaves.
+    for (int rr = 0;; ++rr) {
+        const int ib = (rr & 1) ? (rr + 1) * nwaves - 1 - wave : rr * nwaves + wave;
+        if (ib >= nt16) break;
+        const int i0 = ib * 16;
+        const float *xi = X8 + (long)(i0 + col) * 8;
+        const float bi0 = -2.f * xi[g];
+        const float bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
+        const float nni = xi[7];
+        // diagonal tile: only k > i
+        {
+            const f32x4 G = mfma16(xi[4 + g], bi1, mfma16(xi[g], bi0, f32x4{0.f, 0.f, 0.f, 0.f}));
+            float Dv[4];
+            bool valid[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Dv[r] = G[r] + nni;
+                valid[r] = 4 * g + r > col;
+            }
+            fn(Dv, valid);
+        }
+        // A operands of a batch of source tiles; past the row's end a tile is
+        // repeated and its results are not used
+        float a0[kBatch], a1[kBatch];
+        auto load_batch = [&](int kb) {
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const float *xk = X8 + (long)(min(kb + u, nt16 - 1) * 16 + col) * 8;
+                a0[u] = xk[g];
+                a1[u] = xk[4 + g];
+            }
+        };
+        load_batch(ib + 1);
+        for (int kb = ib + 1; kb < nt16; kb += kBatch) {
+            f32x4 G[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) G[u] = mfma16(a1[u], bi1, mfma16(a0[u], bi0, f32x4{0.f, 0.f, 0.f, 0.f}));
+            load_batch(kb + kBatch);  // next batch's loads overlap this batch's work
+            const bool valid[4] = {true, true, true, true};
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (kb + u >= nt16) break;
+                float Dv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Dv[r] = G[u][r] + nni;
+                fn(Dv, valid);
+            }
+        }
+    }
+}
+
+// Exact order statistic `rank` of the squared distances by radix selection
+// over the bit patterns (digits of 11, 11 and 10 bits); every pass recomputes
+// the distances.  In diagonal tiles only pairs k > i count.
+__device__ float radix_median_mfma(const float *X8, int npad, uint32_t rank, uint32_t *hist,
+                                   uint32_t *red)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id();
+    uint32_t prefix = 0, pmask = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+        const int shift = pass == 0 ? 21 : pass == 1 ? 10 : 0;
+        const uint32_t dmask = pass == 2 ? 0x3ffu : 0x7ffu;
+        for (int b = tid; b < kBins; b += nt) hist[b] = 0;
+        __syncthreads();
+        for_each_distance(X8, npad, [&](const float (&Dv)[4], const bool (&valid)[4]) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t key = __float_as_uint(fmax_(Dv[r], 0.f));
+                if (valid[r] && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
+            }
+        });
+        __syncthreads();
+        if (wave == 0) {
+            constexpr int per = kBins / kWave;
+            uint32_t cnt = 0;
+            for (int q = 0; q < per; ++q) cnt += hist[lane * per + q];
+            const uint32_t incl = wave_incl_scan(cnt, lane);
+            const uint32_t excl = incl - cnt;
+            if (lane == 0) { red[0] = 0; red[1] = 0; }
+            __builtin_amdgcn_wave_barrier();
+            if (rank >= excl && rank < incl) {
+                uint32_t r = rank - excl;
+                for (int q = 0; q < per; ++q) {
+                    const uint32_t h = hist[lane * per + q];
+                    if (r < h) { red[0] = (uint32_t)(lane * per + q); red[1] = r; break; }
+                    r -= h;
+                }
+            }
+        }
+        __syncthreads();
+        prefix |= red[0] << shift;
+        rank = red[1];
+        pmask |= dmask << shift;
+        __syncthreads();
+    }
+    return __uint_as_float(prefix);
+}
+
+// Exact order statistic r of the values kept in the window buffer: wave w's
+// values sit in buf[w * kWinRegion ...] with wcnt[w] of them, all in
+// [lo, hi) (key_lo, key_hi their bit patterns).  Radix selection on the key
+// offsets key - key_lo, 8 bits per pass, as many passes as the span needs.
+__device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregions, uint32_t r, uint32_t key_lo,
+                               uint32_t key_hi, uint32_t *hist, uint32_t *red)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id();
+    const uint32_t span = key_hi - key_lo;
+    const int bits = span == 0 ? 1 : 32 - __clz(span);
+    const int passes = (bits + 7) / 8;
+    const int nslots = nregions * kWinRegion;
+    uint32_t prefix = 0, pmask = 0;
+    for (int p = passes - 1; p >= 0; --p) {
+        const int shift = 8 * p;
+        for (int q = tid; q < 256; q += nt) hist[q] = 0;
+        __syncthreads();
+        for (int s = tid; s < nslots; s += nt) {
+            if ((uint32_t)(s % kWinRegion) < wcnt[s / kWinRegion]) {
+                const uint32_t k = __float_as_uint(buf[s]) - key_lo;
+                if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 0xffu], 1u);
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t c[4];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { c[q] = hist[lane * 4 + q]; cnt += c[q]; }
+            const uint32_t incl = wave_incl_scan(cnt, lane);
+            const uint32_t excl = incl - cnt;
+            if (r >= excl && r < incl) {
+                uint32_t rr = r - excl;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (rr < c[q]) { red[8] = (uint32_t)(lane * 4 + q); red[9] = rr; break; }
+                    rr -= c[q];
+                }
+            }
+        }
+        __syncthreads();
+        prefix |= red[8] << shift;
+        r = red[9];
+        pmask |= 0xffu << shift;
+        __syncthreads();
+    }
+    return __uint_as_float(key_lo + prefix);
+}
+
+// One wave's walk over its share of the distance tiles, one tile per step:
+// rows of tiles (target tile ib) in snake order over the waves, the diagonal
+// tile of a row first, then its source tiles kb > ib.  Holds the current
+// row's B operand (-2 x_i with a 1 in row 7) and target norms.
+struct TileWalker {
+    int nt16, nwaves, wave, rr, ib, kb;
+    float bi0, bi1, nni;
+
+    __device__ void start(const float *X8, int npad, int g, int col)
+    {
+        nt16 = npad / 16;
+        nwaves = blockDim.x >> 6;
+        wave = wave_id();
+        rr = -1;
+        next_row(X8, g, col);
+    }
+    __device__ void next_row(const float *X8, int g, int col)
+    {
+        ++rr;
+        ib = (rr & 1) ? (rr + 1) * nwaves - 1 - wave : rr * nwaves + wave;
+        kb = ib;
+        if (ib < nt16) {
+            const float *xi = X8 + (long)(ib * 16 + col) * 8;
+            bi0 = -2.f * xi[g];
+            bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
+            nni = xi[7];
+        }
+    }
+    __device__ bool done() const { return ib >= nt16; }
+    template <typename Fn> __device__ void step(const float *X8, int g, int col, Fn &&fn)
+    {
+        const float *xk = X8 + (long)(kb * 16 + col) * 8;
+        const f32x4 G = mfma16(xk[4 + g], bi1, mfma16(xk[g], bi0, f32x4{0.f, 0.f, 0.f, 0.f}));
+        const bool diag = kb == ib;
+        float Dv[4];
+        bool valid[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Dv[r] = G[r] + nni;
+            valid[r] = !diag || (4 * g + r > col);
+        }
+        fn(Dv, valid);
+        if (++kb >= nt16) next_row(X8, g, col);
+    }
+};
+
+// Median tracker across the iterations of one step.  The previous two
+// medians predict a window [lo, hi).  While the particles are unchanged (the
+// score pass of the same iteration) the waves visit every distance once,
+// counting those below lo and keeping those inside the window, each wave in
+// its own region of the window buffer; finish() then selects the exact
+// rank-th value among the kept ones.  When there is no prediction yet, the
+// window misses the rank or a region overflows, the full radix selection
+// runs instead.  Both read the same MFMA distances, so the result is the same
+// exact lower median either way.
+struct MedianTracker {
+    float med1, med2, density;
+    int have;        // number of medians recorded (0, 1, 2+)
+    bool active;     // a window pass is under way this iteration
+    float lo, hi;    // the window
+    uint32_t below;  // per lane: distances below lo
+    uint32_t kept;   // per wave: distances kept
+
+    __device__ void reset()
+    {
+        med1 = med2 = density = 0.f;
+        have = 0;
+        active = false;
+    }
+
+    // window of this iteration (active only with a previous median)
+    __device__ void plan()
+    {
+        active = have >= 1 && med1 > 0.f;
+        below = 0;
+        kept = 0;
+        if (!active) return;
+        const float move = have >= 2 ? fabsf(med1 - med2) : 0.f;
+        const float pred = have >= 2 ? med1 + (med1 - med2) : med1;
+        float w = density > 0.f ? (float)kWinTarget / (2.f * density) : 1e-3f * med1;
+        w = fmax_(w, 3.f * move);
+        w = fmax_(w, 2e-5f * med1);
+        lo = uniform(fmax_(pred - w, 0.f));
+        hi = uniform(pred + w);
+    }
+
+    __device__ void visit(const float (&Dv)[4], const bool (&valid)[4], float *region)
+    {
+        bool inw[4];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool lt = Dv[r] < lo;
+            below += (valid[r] && lt) ? 1u : 0u;
+            inw[r] = valid[r] && !lt && Dv[r] < hi;
+            any |= inw[r];
+        }
+        if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const unsigned long long mk = __builtin_amdgcn_ballot_w64(inw[r]);
+                const uint32_t pos = kept + lanes_below(mk);
+                if (inw[r] && pos < (uint32_t)kWinRegion) region[pos] = Dv[r] + 0.f;  // no -0
+                kept += (uint32_t)__builtin_popcountll(mk);
+            }
+        }
+    }
+
+    // After every wave has visited its tiles (no barrier needed before the
+    // call).  Returns the exact lower median.
+    __device__ float finish(const float *X8, int n, int npad, float *buf, uint32_t *hist_small,
+                            uint32_t *hist, uint32_t *red)
+    {
+        const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
+        if (M == 0) return __builtin_nanf("");
+        const uint32_t rank = (M - 1) / 2;
+        const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
+        uint32_t *wcnt = red + 10;    // per-wave kept counts (red[10..25])
+        uint32_t *wbelow = red + 26;  // per-wave below counts (red[26..41])
+        float med = 0.f;
+        bool done = false;
+        if (active) {
+            const uint32_t bw = wave_sum(below);
+            if (lane == 0) {
+                wbelow[wave] = bw;
+                wcnt[wave] = kept;
+            }
+            __syncthreads();
+            uint32_t cnt_lo = 0, n_in = 0;
+            bool overflow = false;
+            for (int q = 0; q < nwaves; ++q) {
+                cnt_lo += wbelow[q];
+                n_in += wcnt[q];
+                overflow |= wcnt[q] > (uint32_t)kWinRegion;
+            }
+            density = uniform((float)n_in / (hi - lo));
+            if (!overflow && rank >= cnt_lo && rank < cnt_lo + n_in) {
+                med = buffer_select(buf, wcnt, nwaves, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi),
+                                    hist_small, red);
+                done = true;
+            }
+            __syncthreads();
+        }
+        if (!done) med = radix_median_mfma(X8, npad, rank, hist, red);
+        med = uniform(med);
+        med2 = med1;
+        med1 = med;
+        have = have < 2 ? have + 1 : 2;
+        active = false;
+        return med;
+    }
+};
+
+template <int KIND, int D>
+__global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
+{
+    using F = Family<float, KIND, D>;
+    using R = RealOps<float>;
+    static_assert(D <= 7, "K-column 7 carries the norms");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, np = a.n_prev;
+    const MfmaLds L(n, np);
+    const int npad = L.npad, nppad = L.nppad;
+    float *X8 = (float *)(smem + L.off_x);     // [npad][8]  centred particles, |x|^2 in column 7 (pad: 0.., +inf)
+    float *S8 = (float *)(smem + L.off_s);     // [npad][8]  scores
+    float *M8 = (float *)(smem + L.off_m);     // [nppad][8] (2 mh_j (d), 0.., c'_j)
+    float *PHP = (float *)(smem + L.off_phip); // [nppad] previous forward-recursion scores
+    float *SCR = (float *)(smem + L.off_scr);
+    uint32_t *hist = (uint32_t *)(smem + L.off_scr);
+    float *WIN = (float *)(smem + L.off_win);                    // median window buffer
+    uint32_t *whist = (uint32_t *)(smem + L.off_win) + kWinCap;  // its histogram
+    float *sz = (float *)(smem + L.off_z);
+    uint8_t *smask = smem + L.off_mask;
+    uint32_t *red = (uint32_t *)(smem + L.off_red);
+    float *redf = (float *)(smem + L.off_red + 256);
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const DevModel<float> &m = a.m;
+    const float *xprev = a.x_prev + (long)b * a.x_prev_stride;
+    float *xg = a.x + (long)b * a.x_stride;
+    const float inf = R::inf();
+
+    for (int o = tid; o < m.obs_dim; o += nt) sz[o] = a.z[(long)b * a.z_stride + o];
+    const uint8_t *mk = nullptr;
+    if (a.mask) {
+        for (int o = tid; o < m.n_obs; o += nt) smask[o] = a.mask[(long)b * a.mask_stride + o];
+        mk = smask;
+    }
+    float rs[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) rs[c] = c < D ? m.rs[c] : 0.f;
+
+    // reference point: mean of the transition means
+    float ref[D];
+    for (int c = 0; c < D; ++c) {
+        float part = 0.f;
+        for (int j = tid; j < np; j += nt) {
+            float xp[D], mu[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) xp[q] = xprev[(long)j * D + q];
+            F::mean(m, a.t, xp, mu);
+            part += mu[c];
+        }
+        part = wave_sum(part);
+        if (lane == 0) redf[wave] = part;
+        __syncthreads();
+        float tot = 0.f;
+        for (int w = 0; w < nwaves; ++w) tot += redf[w];
+        ref[c] = uniform(tot / (float)np);
+        __syncthreads();
+    }
+
+    // transition means, centred and log2-scaled: M8[j] = (2 mh_j, 0.., c'_j),
+    // c'_j = log2 w_j - |mh_j|^2; pad rows give logit -inf
+    for (int j = tid; j < nppad; j += nt) {
+        float row[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) row[c] = 0.f;
+        if (j < np) {
+            float xp[D], mu[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) xp[q] = xprev[(long)j * D + q];
+            F::mean(m, a.t, xp, mu);
+            float nrm = 0.f;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const float mh = (mu[c] - ref[c]) * rs[c];
+                row[c] = 2.f * mh;
+                nrm += mh * mh;
+            }
+            const float lw = a.log_w ? a.log_w[(long)b * a.log_w_stride + j] : -R::log_((float)np);
+            row[7] = lw * (float)kLog2e - nrm;
+        } else {
+            row[7] = -inf;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) M8[(long)j * 8 + c] = row[c];
+    }
+    // initial particles, centred
+    for (int i = tid; i < npad; i += nt) {
+        float xi[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) xi[c] = 0.f;
+        if (i < n) {
+            if (a.init_given) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) xi[c] = xg[(long)i * D + c] - ref[c];
+            } else {
+                float xp[D], mu[D];
+                const int j = i % np;
+#pragma unroll
+                for (int c = 0; c < D; ++c) xp[c] = xprev[(long)j * D + c];
+                F::mean(m, a.t, xp, mu);
+                double nz[8];
+                normals8(a.seed, a.seq_offset + (uint32_t)b, (uint32_t)a.t, (uint32_t)i, D, nz);
+#pragma unroll
+                for (int c = 0; c < D; ++c) xi[c] = (mu[c] + m.sqrt_q[c] * (float)nz[c]) - ref[c];
+            }
+        }
+        float nrm = 0.f;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) nrm += xi[c] * xi[c];
+        xi[7] = i < n ? nrm : inf;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            X8[(long)i * 8 + c] = xi[c];
+            S8[(long)i * 8 + c] = 0.f;
+        }
+    }
+    __syncthreads();
+
+    // mean of the centred transition means (literal score reading)
+    float mbar_all[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) mbar_all[c] = 0.f;
+    if (a.do_svgd && a.trans_mode == 1) {
+        for (int c = 0; c < D; ++c) {
+            float part = 0.f;
+            for (int j = tid; j < np; j += nt) part += M8[(long)j * 8 + c] * 0.5f / rs[c];
+            part = wave_sum(part);
+            if (lane == 0) redf[wave] = part;
+            __syncthreads();
+            float tot = 0.f;
+            for (int w = 0; w < nwaves; ++w) tot += redf[w];
+            mbar_all[c] = uniform(tot / (float)np);
+            __syncthreads();
+        }
+    }
+
+    const int ntasks = npad / 64;
+    const int njt = nppad / 16;
+    const int nkt = npad / 16;
+    const float inv_n = 1.f / (float)n;
+    float h = 1.f;
+    float *scr = SCR + wave * kWaveScratch;
+    MedianTracker tracker;
+    tracker.reset();
+
+    for (int it = 0; a.do_svgd && it < a.n_iter; ++it) {
+        // (1) the bandwidth needs the exact lower median of the squared
+        // distances of the current particles; its window pass is spread over
+        // the score pass, which leaves the particles unchanged
+        const bool need_median = a.bw_mode == 0 || it == 0;
+        if (need_median) tracker.plan();
+        TileWalker walker;
+        if (tracker.active) walker.start(X8, npad, g, col);
+        float *wregion = WIN + wave * kWinRegion;
+        auto walk = [&]() {
+            if (tracker.active && !walker.done())
+                walker.step(X8, g, col, [&](const float (&Dv)[4], const bool (&valid)[4]) {
+                    tracker.visit(Dv, valid, wregion);
+                });
+        };
+
+        // (2) scores
+        for (int task = wave; task < ntasks; task += nwaves) {
+            const int kbase = task * 64;
+            if (a.trans_mode == 0) {
+                f32x4 O[kTilesPerWave];
+                float mx[kTilesPerWave];
+                float bx0[kTilesPerWave], bx1[kTilesPerWave];
+#pragma unroll
+                for (int q = 0; q < kTilesPerWave; ++q) {
+                    const int kk = kbase + 16 * q + col;
+                    const int kd0 = g, kd1 = 4 + g;
+                    bx0[q] = kd0 < D ? X8[(long)kk * 8 + kd0] * rs[kd0] : 0.f;
+                    bx1[q] = kd1 < D ? X8[(long)kk * 8 + kd1] * rs[kd1] : (kd1 == 7 ? 1.f : 0.f);
+                    O[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    mx[q] = -inf;
+                }
+                // value operand of lane (col, g): column col of row j of
+                // [2 mh_j, 1, 0..] = fma(M8[j][col < 7 ? col : 0], vf, vc)
+                const float vf = col < 7 ? 1.f : 0.f, vc = col == 7 ? 1.f : 0.f;
+                const float *vrow = M8 + (long)(4 * g) * 8 + (col < 7 ? col : 0);  // finite column for col >= 7
+                // software pipeline: the logits of tile jt + 1 are issued before
+                // the exponentials of tile jt (the last tile repeats, unused)
+                f32x4 Lg[kTilesPerWave];
+                auto logits = [&](int jt, f32x4 (&Lo)[kTilesPerWave]) {
+                    const float *mrow = M8 + (long)(jt * 16 + col) * 8;
+                    const float am0 = mrow[g], am1 = mrow[4 + g];
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am0, bx0[q], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am1, bx1[q], Lo[q]);
+                };
+                logits(0, Lg);
+                for (int jt = 0; jt < njt; ++jt) {
+                    const float *vr = vrow + (long)(jt * 16) * 8;
+                    float av[4];
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm) av[mm] = __builtin_fmaf(vr[mm * 8], vf, vc);
+                    f32x4 Ln[kTilesPerWave];
+                    logits(min(jt + 1, njt - 1), Ln);
+                    f32x4 E[kTilesPerWave];
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q) {
+                        const float lmax = fmax_(fmax_(Lg[q][0], Lg[q][1]), fmax_(Lg[q][2], Lg[q][3]));
+                        if (__builtin_amdgcn_ballot_w64(lmax > mx[q] + kRescaleGap)) {
+                            // move the reference of the columns whose maximum ran
+                            // more than 2^8 past it (all four groups agree)
+                            const float gm = group_max4(lmax);
+                            const bool up = gm > mx[q] + kRescaleGap;
+                            const float nm = up ? gm : mx[q];
+                            const float sc = up ? (mx[q] == -inf ? 0.f : R::exp2_(mx[q] - nm)) : 1.f;
+                            O[q] *= sc;
+                            mx[q] = nm;
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) E[q][r] = R::exp2_(Lg[q][r] - mx[q]);
+                    }
+                    // independent accumulators back to back
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+                        for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], E[q][mm], O[q]);
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q) Lg[q] = Ln[q];
+                    // two tiles of the median window pass ride along
+                    walk();
+                    walk();
+                }
+                // O[q] lane l register r = (c = 4g + r, particle kbase + 16 q + col);
+                // rows c < 7 hold sum_j e 2 mh_j, row 7 sum_j e
+                if (g < 2) {
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) scr[(q * 8 + 4 * g + r) * 16 + col] = O[q][r];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            {
+                const int k = kbase + lane;
+                const int q = lane >> 4;
+                float srow[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) srow[c] = 0.f;
+                srow[7] = 1.f;  // the Stein pass sums kappa through this column
+                if (k < n) {
+                    float xt[D], xa[D], gr[D];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        xt[c] = X8[(long)k * 8 + c];
+                        xa[c] = xt[c] + ref[c];
+                    }
+                    F::grad(m, sz, mk, xa, gr);
+                    if (a.trans_mode == 0) {
+                        const float inv_sum = 1.f / scr[(q * 8 + 7) * 16 + col];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            const float mb = scr[(q * 8 + c) * 16 + col] * inv_sum * 0.5f / rs[c];
+                            srow[c] = gr[c] - (xt[c] - mb) * m.inv_q[c];
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) srow[c] = gr[c] - (xt[c] - mbar_all[c]) * m.inv_q[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) S8[(long)k * 8 + c] = srow[c];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (tracker.active)
+            while (!walker.done()) walk();
+        __syncthreads();
+        if (need_median) {
+            const float med = tracker.finish(X8, n, npad, WIN, whist, hist, red);
+            h = uniform(bandwidth_from_median(med, n, a.bw_scale));
+        }
+        if (a.h_out && tid == 0) a.h_out[(long)b * a.h_stride + it] = h;
+        const float beta = uniform((float)kLog2e / h);
+
+        // (3) Stein direction
+        const float twob = 2.f * beta;
+        const float coef1 = g == 3 ? -beta : twob;  // K-column 7 carries -beta n_k
+        const float c2 = 2.f / h;
+        float phi[kTilesPerWave][2];
+        for (int task = wave; task < ntasks; task += nwaves) {
+            const int ibase = task * 64;
+            float bi0[kTilesPerWave], bi1[kTilesPerWave], nbi[kTilesPerWave];
+            f32x4 O[kTilesPerWave];
+#pragma unroll
+            for (int q = 0; q < kTilesPerWave; ++q) {
+                const int ii = ibase + 16 * q + col;
+                bi0[q] = X8[(long)ii * 8 + g];
+                bi1[q] = g == 3 ? 1.f : X8[(long)ii * 8 + 4 + g];
+                nbi[q] = beta * X8[(long)ii * 8 + 7];
+                O[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            // value operand of lane (col, g), row k: column col of
+            // [s_k (d), 0.., 1, x_k (d), 0..] -- S8 row for col < 8 (its column
+            // 7 holds 1), X8 row for col >= 8; lane col = 15 reads column 0
+            // (finite; output row 15 is unused)
+            const float *vbase = (col < 8 ? S8 + col : X8 + (col < 15 ? col - 8 : 0)) + (long)(4 * g) * 8;
+            // Gram tiles: A rows (2 beta x_k, -beta n_k in K-column 7); the
+            // tiles of kt + 1 are issued before the exponentials of tile kt
+            // (the last tile repeats, unused)
+            f32x4 G[kTilesPerWave];
+            auto gram = [&](int kt, f32x4 (&Go)[kTilesPerWave]) {
+                const float *xr = X8 + (long)(kt * 16 + col) * 8;
+                const float ak0 = twob * xr[g], ak1 = coef1 * xr[4 + g];
+#pragma unroll
+                for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak0, bi0[q], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak1, bi1[q], Go[q]);
+            };
+            gram(0, G);
+            for (int kt = 0; kt < nkt; ++kt) {
+                const float *vb = vbase + (long)(kt * 16) * 8;
+                float av[4];
+#pragma unroll
+                for (int mm = 0; mm < 4; ++mm) av[mm] = vb[mm * 8];
+                f32x4 Gn[kTilesPerWave];
+                gram(min(kt + 1, nkt - 1), Gn);
+                f32x4 P[kTilesPerWave];
+#pragma unroll
+                for (int q = 0; q < kTilesPerWave; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) P[q][r] = R::exp2_(G[q][r] - nbi[q]);
+                // independent accumulators back to back
+#pragma unroll
+                for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], P[q][mm], O[q]);
+#pragma unroll
+                for (int q = 0; q < kTilesPerWave; ++q) G[q] = Gn[q];
+            }
+            // O[q] lane l register r = (c = 4g + r, target ibase + 16 q + col):
+            // c < d: sum kappa s_k; c = 7: sum kappa; 8 + c: sum kappa x_k
+#pragma unroll
+            for (int q = 0; q < kTilesPerWave; ++q) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) scr[(4 * g + r) * 16 + col] = O[q][r];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int ii = ibase + 16 * q + col;
+                const float ksum = scr[7 * 16 + col];
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int c = g + 4 * h2;
+                    float v = 0.f;
+                    if (c < D)
+                        v = (scr[c * 16 + col] + c2 * (X8[(long)ii * 8 + c] * ksum - scr[(8 + c) * 16 + col])) * inv_n;
+                    phi[q][h2] = v;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        __syncthreads();
+        // synchronous update, then unscaled squared norms for the next median
+        for (int task = wave; task < ntasks; task += nwaves) {
+#pragma unroll
+            for (int q = 0; q < kTilesPerWave; ++q) {
+                const int ii = task * 64 + 16 * q + col;
+                if (ii < n) {
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int c = g + 4 * h2;
+                        if (c < D) X8[(long)ii * 8 + c] += a.step * phi[q][h2];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += nt) {
+            float nrm = 0.f;
+#pragma unroll
+            for (int c = 0; c < D; ++c) { const float v = X8[(long)i * 8 + c]; nrm += v * v; }
+            X8[(long)i * 8 + 7] = nrm;
+        }
+        __syncthreads();
+    }
+
+    bool bad = false;
+    for (int i = tid; a.do_svgd && i < n; i += nt) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const float v = X8[(long)i * 8 + c] + ref[c];
+            bad |= !R::finite(v);
+            xg[(long)i * D + c] = v;
+        }
+    }
+
+    if (a.do_viterbi) {
+        for (int j = tid; j < np; j += nt) PHP[j] = a.phi_prev ? a.phi_prev[(long)b * a.phi_prev_stride + j] : 0.f;
+        __syncthreads();
+        for (int i = tid; i < n; i += nt) {
+            float xs[D], xa[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const float xt = X8[(long)i * 8 + c];
+                xs[c] = xt * rs[c];
+                xa[c] = xt + ref[c];
+            }
+            ArgBest<float> ab{-inf, -inf, 0};
+            bool nan_seen = false;
+            for (int j = 0; j < np; ++j) {
+                float q2 = 0.f;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const float r = xs[c] - 0.5f * M8[(long)j * 8 + c];
+                    q2 += r * r;
+                }
+                const float A = m.log_z - (float)kLn2 * q2;
+                const float cij = A + PHP[j];
+                nan_seen |= (cij != cij);
+                if (j == 0) { ab.best = cij; ab.arg = 0; }
+                else argbest_push(ab, cij, j);
+            }
+            const float ell = F::loglik(m, sz, mk, xa);
+            const float ph = ab.best + ell;
+            nan_seen |= (ph != ph);
+            bad |= nan_seen;
+            a.phi[(long)b * a.phi_stride + i] = ph;
+            a.psi[(long)b * a.psi_stride + i] = ab.arg;
+            if (a.flags) {
+                const float mag = ab.best < 0 ? -ab.best : ab.best;
+                const float sc_ = mag > 1.f ? mag : 1.f;
+                a.flags[(long)b * a.flags_stride + i] = (np > 1 && ab.second >= ab.best - a.tie_tol * sc_) ? 1 : 0;
+            }
+        }
+    }
+    if (bad) atomicOr(a.status, STATUS_NONFINITE);
+}
+
+} // namespace smsq

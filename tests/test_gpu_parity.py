@@ -235,6 +235,15 @@ def test_svgd_step_teacher_forced(name, n, n_prev, L, step, dt):
     _compare_svgd(desc, dt, xp, None, z, mask, x, L, step)
 
 
+@pytest.mark.parametrize("name,n,n_prev,L,step", SVGD_CASES)
+def test_svgd_step_vector_alu_kernel(name, n, n_prev, L, step, monkeypatch):
+    """The FP32 vector-ALU step kernel (selected instead of the matrix-core one)."""
+    announce("svgd step valu", name, n, n_prev, L)
+    monkeypatch.setenv("SMSQ_STEP_KERNEL", "valu")
+    wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 22, "f32")
+    _compare_svgd(desc, "f32", xp, None, z, mask, x, L, step)
+
+
 @pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "one_particle",
                                      "two_particles", "ragged_1025"])
 def test_svgd_step_variants(variant):

@@ -49,6 +49,16 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Lanes of the diagonal 16x16 distance tile that hold a pair k > i in
+// result register r (k = 4 (l / 16) + r, i = l % 16).
+__host__ __device__ constexpr unsigned long long diag_lanes(int r)
+{
+    unsigned long long m = 0;
+    for (int l = 0; l < 64; ++l)
+        if (4 * (l >> 4) + r > (l & 15)) m |= 1ull << l;
+    return m;
+}
+
 // max over the four 16-lane groups that hold the same column (lanes l, l^16,
 // l^32, l^48)
 __device__ __forceinline__ float group_max4(float v)
@@ -94,12 +104,14 @@ struct MfmaLds {
 // Visits the squared distances D_ik = n_i + n_k - 2 x_i . x_k of every pair
 // i < k from 16x16 MFMA Gram tiles: the A rows are the source particles with
 // their norm n_k in column 7 (padding for d <= 7), the B columns are
-// -2 x_i with a 1 in row 7, so the tile holds n_k - 2 x_k . x_i and one add
-// of n_i finishes it.  Each wave takes whole rows of tiles (target tile ib,
-// source tiles kb >= ib) and issues the MFMAs of four source tiles before
-// using any result.  fn(Dv, valid) receives the four distances of a lane for
-// one tile (k = 16 kb + 4 g + r, i = 16 ib + col); in the diagonal tile only
-// k > i is valid.  Pad particles have n = +inf, so their distances are +inf.
+// -2 x_i with a 1 in row 7, and the accumulator starts at n_i, so the tile
+// holds the distances themselves.  Each wave takes whole rows of tiles
+// (target tile ib, source tiles kb >= ib) and issues the MFMAs of four source
+// tiles before using any result.  fn(Dv, diag) receives the four distances
+// of a lane for one tile (k = 16 kb + 4 g + r, i = 16 ib + col); in the
+// diagonal tile (diag true) only the lanes of diag_lanes(r) hold pairs k > i.
+// Pad particles have n = +inf, so their distances are +inf.  The median
+// window pass (TileWalker) computes every distance the same way.
 template <typename Fn>
 __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn &&fn)
 {
@@ -118,18 +130,8 @@ __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn 
         const float bi0 = -2.f * xi[g];
         const float bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
         const float nni = xi[7];
-        // diagonal tile: only k > i
-        {
-            const f32x4 G = mfma16(xi[4 + g], bi1, mfma16(xi[g], bi0, f32x4{0.f, 0.f, 0.f, 0.f}));
-            float Dv[4];
-            bool valid[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Dv[r] = G[r] + nni;
-                valid[r] = 4 * g + r > col;
-            }
-            fn(Dv, valid);
-        }
+        const f32x4 cn = {nni, nni, nni, nni};
+        fn(mfma16(xi[4 + g], bi1, mfma16(xi[g], bi0, cn)), true);
         // A operands of a batch of source tiles; past the row's end a tile is
         // repeated and its results are not used
         float a0[kBatch], a1[kBatch];
@@ -145,16 +147,12 @@ __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn 
         for (int kb = ib + 1; kb < nt16; kb += kBatch) {
             f32x4 G[kBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) G[u] = mfma16(a1[u], bi1, mfma16(a0[u], bi0, f32x4{0.f, 0.f, 0.f, 0.f}));
+            for (int u = 0; u < kBatch; ++u) G[u] = mfma16(a1[u], bi1, mfma16(a0[u], bi0, cn));
             load_batch(kb + kBatch);  // next batch's loads overlap this batch's work
-            const bool valid[4] = {true, true, true, true};
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 if (kb + u >= nt16) break;
-                float Dv[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Dv[r] = G[u][r] + nni;
-                fn(Dv, valid);
+                fn(G[u], false);
             }
         }
     }
@@ -173,11 +171,12 @@ __device__ float radix_median_mfma(const float *X8, int npad, uint32_t rank, uin
         const uint32_t dmask = pass == 2 ? 0x3ffu : 0x7ffu;
         for (int b = tid; b < kBins; b += nt) hist[b] = 0;
         __syncthreads();
-        for_each_distance(X8, npad, [&](const float (&Dv)[4], const bool (&valid)[4]) {
+        for_each_distance(X8, npad, [&](const f32x4 &Dv, bool diag) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t key = __float_as_uint(fmax_(Dv[r], 0.f));
-                if (valid[r] && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
+                const bool valid = !diag || ((diag_lanes(r) >> lane) & 1ull);
+                if (valid && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
             }
         });
         __syncthreads();
@@ -256,13 +255,14 @@ __device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregi
     return __uint_as_float(key_lo + prefix);
 }
 
-// One wave's walk over its share of the distance tiles, one tile per step:
-// rows of tiles (target tile ib) in snake order over the waves, the diagonal
-// tile of a row first, then its source tiles kb > ib.  Holds the current
-// row's B operand (-2 x_i with a 1 in row 7) and target norms.
+// One wave's walk over its share of the distance tiles (the rows of tiles of
+// for_each_distance, in the same order), two source tiles kb, kb + 1 per
+// step.  Holds the current row's B operand (-2 x_i with a 1 in row 7) and
+// the target norms as the accumulator input.
 struct TileWalker {
     int nt16, nwaves, wave, rr, ib, kb;
-    float bi0, bi1, nni;
+    float bi0, bi1;
+    f32x4 cn;
 
     __device__ void start(const float *X8, int npad, int g, int col)
     {
@@ -281,24 +281,29 @@ struct TileWalker {
             const float *xi = X8 + (long)(ib * 16 + col) * 8;
             bi0 = -2.f * xi[g];
             bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
-            nni = xi[7];
+            const float nni = xi[7];
+            cn = f32x4{nni, nni, nni, nni};
         }
     }
     __device__ bool done() const { return ib >= nt16; }
-    template <typename Fn> __device__ void step(const float *X8, int g, int col, Fn &&fn)
+    __device__ bool diag() const { return kb == ib; }
+    __device__ bool second() const { return kb + 1 < nt16; }
+    // distances of tiles kb and kb + 1 (clamped to the row: always in
+    // bounds, also once the walk is done; results past the end are unused)
+    __device__ void issue(const float *X8, int g, int col, f32x4 &D0, f32x4 &D1) const
     {
-        const float *xk = X8 + (long)(kb * 16 + col) * 8;
-        const f32x4 G = mfma16(xk[4 + g], bi1, mfma16(xk[g], bi0, f32x4{0.f, 0.f, 0.f, 0.f}));
-        const bool diag = kb == ib;
-        float Dv[4];
-        bool valid[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            Dv[r] = G[r] + nni;
-            valid[r] = !diag || (4 * g + r > col);
-        }
-        fn(Dv, valid);
-        if (++kb >= nt16) next_row(X8, g, col);
+        const int k0 = min(kb, nt16 - 1), k1 = min(kb + 1, nt16 - 1);
+        const float *x0 = X8 + (long)(k0 * 16 + col) * 8;
+        const float *x1 = X8 + (long)(k1 * 16 + col) * 8;
+        D0 = mfma16(x0[g], bi0, cn);
+        D1 = mfma16(x1[g], bi0, cn);
+        D0 = mfma16(x0[4 + g], bi1, D0);
+        D1 = mfma16(x1[4 + g], bi1, D1);
+    }
+    __device__ void advance(const float *X8, int g, int col)
+    {
+        kb += 2;
+        if (kb >= nt16) next_row(X8, g, col);
     }
 };
 
@@ -316,8 +321,8 @@ struct MedianTracker {
     int have;        // number of medians recorded (0, 1, 2+)
     bool active;     // a window pass is under way this iteration
     float lo, hi;    // the window
-    uint32_t below;  // per lane: distances below lo
-    uint32_t kept;   // per wave: distances kept
+    uint32_t below;  // per wave: distances below lo
+    uint32_t kept;   // per wave: distances kept (kOverflow once the region is full)
 
     __device__ void reset()
     {
@@ -342,24 +347,32 @@ struct MedianTracker {
         hi = uniform(pred + w);
     }
 
-    __device__ void visit(const float (&Dv)[4], const bool (&valid)[4], float *region)
+    static constexpr uint32_t kOverflow = 0x40000000u;
+
+    // one tile of distances (diag: only pairs k > i count)
+    __device__ void visit(const f32x4 &Dv, bool diag, float *region)
     {
-        bool inw[4];
-        bool any = false;
+        unsigned long long inw[4], any = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const bool lt = Dv[r] < lo;
-            below += (valid[r] && lt) ? 1u : 0u;
-            inw[r] = valid[r] && !lt && Dv[r] < hi;
+            const unsigned long long vm = diag ? diag_lanes(r) : ~0ull;
+            const unsigned long long lt = __builtin_amdgcn_ballot_w64(Dv[r] < lo) & vm;
+            const unsigned long long lh = __builtin_amdgcn_ballot_w64(Dv[r] < hi) & vm;
+            below += (uint32_t)__builtin_popcountll(lt);
+            inw[r] = lh & ~lt;
             any |= inw[r];
         }
-        if (__builtin_amdgcn_ballot_w64(any)) {
+        if (any) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const unsigned long long mk = __builtin_amdgcn_ballot_w64(inw[r]);
-                const uint32_t pos = kept + lanes_below(mk);
-                if (inw[r] && pos < (uint32_t)kWinRegion) region[pos] = Dv[r] + 0.f;  // no -0
-                kept += (uint32_t)__builtin_popcountll(mk);
+                if (!inw[r]) continue;
+                const uint32_t cnt = (uint32_t)__builtin_popcountll(inw[r]);
+                if (kept + cnt > (uint32_t)kWinRegion) {
+                    kept = kOverflow;
+                    break;
+                }
+                if ((inw[r] >> (threadIdx.x & 63)) & 1ull) region[kept + lanes_below(inw[r])] = Dv[r] + 0.f;  // no -0
+                kept += cnt;
             }
         }
     }
@@ -378,9 +391,8 @@ struct MedianTracker {
         float med = 0.f;
         bool done = false;
         if (active) {
-            const uint32_t bw = wave_sum(below);
             if (lane == 0) {
-                wbelow[wave] = bw;
+                wbelow[wave] = below;
                 wcnt[wave] = kept;
             }
             __syncthreads();
@@ -566,11 +578,12 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
         TileWalker walker;
         if (tracker.active) walker.start(X8, npad, g, col);
         float *wregion = WIN + wave * kWinRegion;
-        auto walk = [&]() {
-            if (tracker.active && !walker.done())
-                walker.step(X8, g, col, [&](const float (&Dv)[4], const bool (&valid)[4]) {
-                    tracker.visit(Dv, valid, wregion);
-                });
+        auto walk_step = [&]() {
+            f32x4 W0, W1;
+            walker.issue(X8, g, col, W0, W1);
+            tracker.visit(W0, walker.diag(), wregion);
+            if (walker.second()) tracker.visit(W1, false, wregion);
+            walker.advance(X8, g, col);
         };
 
         // (2) scores
@@ -578,7 +591,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
             const int kbase = task * 64;
             if (a.trans_mode == 0) {
                 f32x4 O[kTilesPerWave];
-                float mx[kTilesPerWave];
+                f32x4 cm[kTilesPerWave];  // -reference of each particle column, as the accumulator input
                 float bx0[kTilesPerWave], bx1[kTilesPerWave];
 #pragma unroll
                 for (int q = 0; q < kTilesPerWave; ++q) {
@@ -587,59 +600,88 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                     bx0[q] = kd0 < D ? X8[(long)kk * 8 + kd0] * rs[kd0] : 0.f;
                     bx1[q] = kd1 < D ? X8[(long)kk * 8 + kd1] * rs[kd1] : (kd1 == 7 ? 1.f : 0.f);
                     O[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    mx[q] = -inf;
+                    cm[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
                 // value operand of lane (col, g): column col of row j of
                 // [2 mh_j, 1, 0..] = fma(M8[j][col < 7 ? col : 0], vf, vc)
                 const float vf = col < 7 ? 1.f : 0.f, vc = col == 7 ? 1.f : 0.f;
                 const float *vrow = M8 + (long)(4 * g) * 8 + (col < 7 ? col : 0);  // finite column for col >= 7
-                // software pipeline: the logits of tile jt + 1 are issued before
-                // the exponentials of tile jt (the last tile repeats, unused)
-                f32x4 Lg[kTilesPerWave];
+                // logits of tile jt relative to the column references
                 auto logits = [&](int jt, f32x4 (&Lo)[kTilesPerWave]) {
                     const float *mrow = M8 + (long)(jt * 16 + col) * 8;
                     const float am0 = mrow[g], am1 = mrow[4 + g];
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am0, bx0[q], f32x4{0.f, 0.f, 0.f, 0.f});
+                    for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am0, bx0[q], cm[q]);
 #pragma unroll
                     for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am1, bx1[q], Lo[q]);
                 };
-                logits(0, Lg);
-                for (int jt = 0; jt < njt; ++jt) {
-                    const float *vr = vrow + (long)(jt * 16) * 8;
-                    float av[4];
+                // Raises the reference of the columns of a relative logit tile
+                // whose maximum lies more than 2^8 above it (all four lane
+                // groups of a column agree), rescaling the sums and the tile;
+                // with `first`, sets the references to the tile's maxima.  The
+                // test compares the bit patterns as integers: for a positive
+                // bound that orders like the floats, and NaN also triggers.
+                auto rebase = [&](f32x4 (&T)[kTilesPerWave], bool first) {
+                    int m = __float_as_int(T[0][0]);
 #pragma unroll
-                    for (int mm = 0; mm < 4; ++mm) av[mm] = __builtin_fmaf(vr[mm * 8], vf, vc);
-                    f32x4 Ln[kTilesPerWave];
-                    logits(min(jt + 1, njt - 1), Ln);
-                    f32x4 E[kTilesPerWave];
+                    for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q) {
-                        const float lmax = fmax_(fmax_(Lg[q][0], Lg[q][1]), fmax_(Lg[q][2], Lg[q][3]));
-                        if (__builtin_amdgcn_ballot_w64(lmax > mx[q] + kRescaleGap)) {
-                            // move the reference of the columns whose maximum ran
-                            // more than 2^8 past it (all four groups agree)
+                        for (int r = 0; r < 4; ++r) m = max(m, __float_as_int(T[q][r]));
+                    if (first || __builtin_amdgcn_ballot_w64(m > __float_as_int(kRescaleGap))) {
+#pragma unroll
+                        for (int q = 0; q < kTilesPerWave; ++q) {
+                            const float lmax = fmax_(fmax_(T[q][0], T[q][1]), fmax_(T[q][2], T[q][3]));
                             const float gm = group_max4(lmax);
-                            const bool up = gm > mx[q] + kRescaleGap;
-                            const float nm = up ? gm : mx[q];
-                            const float sc = up ? (mx[q] == -inf ? 0.f : R::exp2_(mx[q] - nm)) : 1.f;
-                            O[q] *= sc;
-                            mx[q] = nm;
+                            const bool up = first ? gm > -inf : gm > kRescaleGap;
+                            const float sh = up ? gm : 0.f;
+                            O[q] *= first ? 1.f : R::exp2_(-sh);
+                            T[q] -= sh;
+                            cm[q] -= sh;
                         }
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) E[q][r] = R::exp2_(Lg[q][r] - mx[q]);
                     }
-                    // independent accumulators back to back
+                };
+                // Two logit tiles per round (the buffers alternate), software
+                // pipelined: the logits of tile jt + 1 are issued and checked
+                // around the exponentials and sums of tile jt; with WALK, two
+                // tiles of the median window pass ride along.
+                auto score_loop = [&](auto walk_tag) {
+                    constexpr bool WALK = decltype(walk_tag)::value;
+                    auto tile = [&](int jt, f32x4 (&T)[kTilesPerWave], f32x4 (&Tn)[kTilesPerWave]) {
+                        const float *vr = vrow + (long)(jt * 16) * 8;
+                        float av[4];
 #pragma unroll
-                    for (int mm = 0; mm < 4; ++mm)
+                        for (int mm = 0; mm < 4; ++mm) av[mm] = __builtin_fmaf(vr[mm * 8], vf, vc);
+                        logits(min(jt + 1, njt - 1), Tn);
+                        f32x4 W0, W1;
+                        if (WALK) walker.issue(X8, g, col, W0, W1);
 #pragma unroll
-                        for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], E[q][mm], O[q]);
+                        for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q) Lg[q] = Ln[q];
-                    // two tiles of the median window pass ride along
-                    walk();
-                    walk();
-                }
+                            for (int r = 0; r < 4; ++r) T[q][r] = R::exp2_(T[q][r]);
+                        // independent accumulators back to back
+#pragma unroll
+                        for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+                            for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], T[q][mm], O[q]);
+                        if (WALK && !walker.done()) {
+                            tracker.visit(W0, walker.diag(), wregion);
+                            if (walker.second()) tracker.visit(W1, false, wregion);
+                            walker.advance(X8, g, col);
+                        }
+                        rebase(Tn, false);
+                    };
+                    f32x4 TA[kTilesPerWave], TB[kTilesPerWave];
+                    logits(0, TA);
+                    rebase(TA, true);
+                    for (int jt = 0; jt < njt; jt += 2) {
+                        tile(jt, TA, TB);
+                        if (jt + 1 < njt) tile(jt + 1, TB, TA);
+                    }
+                };
+                if (tracker.active && !walker.done())
+                    score_loop(std::true_type{});
+                else
+                    score_loop(std::false_type{});
                 // O[q] lane l register r = (c = 4g + r, particle kbase + 16 q + col);
                 // rows c < 7 hold sum_j e 2 mh_j, row 7 sum_j e
                 if (g < 2) {
@@ -687,7 +729,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (tracker.active)
-            while (!walker.done()) walk();
+            while (!walker.done()) walk_step();
         __syncthreads();
         if (need_median) {
             const float med = tracker.finish(X8, n, npad, WIN, whist, hist, red);
@@ -698,19 +740,23 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
 
         // (3) Stein direction
         const float twob = 2.f * beta;
-        const float coef1 = g == 3 ? -beta : twob;  // K-column 7 carries -beta n_k
         const float c2 = 2.f / h;
         float phi[kTilesPerWave][2];
         for (int task = wave; task < ntasks; task += nwaves) {
             const int ibase = task * 64;
-            float bi0[kTilesPerWave], bi1[kTilesPerWave], nbi[kTilesPerWave];
+            // B columns (2 beta x_i, -beta in K-row 7); the accumulator starts
+            // at -beta n_i, so a Gram tile holds the exponent
+            // -beta |x_k - x_i|^2 of kappa directly
+            float bi0[kTilesPerWave], bi1[kTilesPerWave];
+            f32x4 cb[kTilesPerWave];
             f32x4 O[kTilesPerWave];
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = ibase + 16 * q + col;
-                bi0[q] = X8[(long)ii * 8 + g];
-                bi1[q] = g == 3 ? 1.f : X8[(long)ii * 8 + 4 + g];
-                nbi[q] = beta * X8[(long)ii * 8 + 7];
+                bi0[q] = twob * X8[(long)ii * 8 + g];
+                bi1[q] = g == 3 ? -beta : twob * X8[(long)ii * 8 + 4 + g];
+                const float nb = -beta * X8[(long)ii * 8 + 7];
+                cb[q] = f32x4{nb, nb, nb, nb};
                 O[q] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
             // value operand of lane (col, g), row k: column col of
@@ -718,38 +764,39 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
             // 7 holds 1), X8 row for col >= 8; lane col = 15 reads column 0
             // (finite; output row 15 is unused)
             const float *vbase = (col < 8 ? S8 + col : X8 + (col < 15 ? col - 8 : 0)) + (long)(4 * g) * 8;
-            // Gram tiles: A rows (2 beta x_k, -beta n_k in K-column 7); the
-            // tiles of kt + 1 are issued before the exponentials of tile kt
-            // (the last tile repeats, unused)
-            f32x4 G[kTilesPerWave];
+            // Gram tiles: A rows (x_k, n_k in K-column 7)
             auto gram = [&](int kt, f32x4 (&Go)[kTilesPerWave]) {
                 const float *xr = X8 + (long)(kt * 16 + col) * 8;
-                const float ak0 = twob * xr[g], ak1 = coef1 * xr[4 + g];
+                const float ak0 = xr[g], ak1 = xr[4 + g];
 #pragma unroll
-                for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak0, bi0[q], f32x4{0.f, 0.f, 0.f, 0.f});
+                for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak0, bi0[q], cb[q]);
 #pragma unroll
                 for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak1, bi1[q], Go[q]);
             };
-            gram(0, G);
-            for (int kt = 0; kt < nkt; ++kt) {
+            // one source tile: the Gram tiles of kt + 1 are issued before the
+            // exponentials of tile kt (the last tile repeats, unused); the two
+            // buffers alternate
+            auto tile = [&](int kt, f32x4 (&G)[kTilesPerWave], f32x4 (&Gn)[kTilesPerWave]) {
                 const float *vb = vbase + (long)(kt * 16) * 8;
                 float av[4];
 #pragma unroll
                 for (int mm = 0; mm < 4; ++mm) av[mm] = vb[mm * 8];
-                f32x4 Gn[kTilesPerWave];
                 gram(min(kt + 1, nkt - 1), Gn);
-                f32x4 P[kTilesPerWave];
 #pragma unroll
                 for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) P[q][r] = R::exp2_(G[q][r] - nbi[q]);
+                    for (int r = 0; r < 4; ++r) G[q][r] = R::exp2_(G[q][r]);
                 // independent accumulators back to back
 #pragma unroll
                 for (int mm = 0; mm < 4; ++mm)
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], P[q][mm], O[q]);
-#pragma unroll
-                for (int q = 0; q < kTilesPerWave; ++q) G[q] = Gn[q];
+                    for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], G[q][mm], O[q]);
+            };
+            f32x4 GA[kTilesPerWave], GB[kTilesPerWave];
+            gram(0, GA);
+            for (int kt = 0; kt < nkt; kt += 2) {
+                tile(kt, GA, GB);
+                if (kt + 1 < nkt) tile(kt + 1, GB, GA);
             }
             // O[q] lane l register r = (c = 4g + r, target ibase + 16 q + col):
             // c < d: sum kappa s_k; c = 7: sum kappa; 8 + c: sum kappa x_k

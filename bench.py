@@ -27,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32 = 157.3e12   # MI355X FP32 vector peak (FLOP/s)
+PEAK_FP32 = 157.3e12   # MI355X FP32 peak (FLOP/s), matrix cores and vector ALU alike
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12      # B/s
 
@@ -186,9 +186,11 @@ def main():
         "viterbi_edges_per_s": edges / (ms / 1e3),
         "sequences_per_s": B / (ms / 1e3),
         "counted_tflops": flops_total / (ms / 1e3) / 1e12,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_step (fused SVGD iterations + forward recursion), steady-state launch",
+                     "kernel": ("k_step_mfma (fused SVGD iterations + forward recursion, FP32 matrix cores)"
+                                if dt == "f32" else "k_step (fused SVGD iterations + forward recursion, FP64)")
+                     + ", steady-state launch",
                      "kernel_avg_ms": k_avg_ms, "flops_per_launch": flops_launch},
         "viterbi_lattice": lat,
     }

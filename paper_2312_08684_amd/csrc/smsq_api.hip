@@ -152,7 +152,7 @@ bool use_mfma(int n, int n_prev)
     const char *e = std::getenv("SMSQ_STEP_KERNEL");
     if (e && std::strcmp(e, "valu") == 0) return false;
     const MfmaLds L(n, n_prev);
-    return L.npad <= 1024 && L.total <= kLdsLimit;
+    return L.npad <= kMaxParticles && L.total <= kLdsLimit;
 }
 
 template <int KIND, int D>

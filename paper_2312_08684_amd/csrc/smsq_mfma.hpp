@@ -69,10 +69,16 @@ __device__ __forceinline__ float group_max4(float v)
     return fmax_(__uint_as_float(b[0]), __uint_as_float(b[1]));
 }
 
+// Up to sixteen waves per workgroup (four per SIMD), one 64-particle task
+// each at the largest size.
+constexpr int kMaxWaves = 16;
 constexpr int kTilesPerWave = 4;  // register blocking: 64 particles per wave task
-constexpr int kWaveScratch = 512; // floats of per-wave LDS scratch
+constexpr int kMaxParticles = 1024;  // largest sequence the kernel takes
+constexpr int kTaskSlots = kMaxParticles / 64 / kMaxWaves;  // tasks per wave at most
+constexpr int kWaveScratch = 256; // floats of per-wave LDS scratch (one 16x16 tile)
+constexpr int kVtRows = 9;        // rows of the transition-mean table: 2 mh (7), 1, c'
 constexpr int kWinCap = 4096;     // capacity of the median window buffer (floats)
-constexpr int kWinRegion = kWinCap / 16; // per-wave share of the window buffer
+constexpr int kWinRegion = kWinCap / kMaxWaves; // per-wave share of the window buffer
 constexpr int kWinTarget = 1024;  // aimed-for number of distances in the window
 constexpr float kRescaleGap = 8.f; // log2 headroom before the softmax reference moves
 
@@ -84,11 +90,11 @@ struct MfmaLds {
     {
         npad = (n + 63) / 64 * 64;
         nppad = (n_prev + 15) / 16 * 16;
-        nwaves = npad / 64 < 16 ? npad / 64 : 16;
+        nwaves = npad / 64 < kMaxWaves ? npad / 64 : kMaxWaves;
         long o = 0;
         off_x = o; o += align16((long)npad * 8 * 4);
         off_s = o; o += align16((long)npad * 8 * 4);
-        off_m = o; o += align16((long)nppad * 8 * 4);
+        off_m = o; o += align16((long)kVtRows * nppad * 4);
         off_phip = o; o += align16((long)nppad * 4);
         long scr = (long)nwaves * kWaveScratch * 4;
         if (scr < (long)kBins * 4) scr = (long)kBins * 4;  // also the radix-selection histogram
@@ -255,15 +261,106 @@ __device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregi
     return __uint_as_float(key_lo + prefix);
 }
 
-// One wave's walk over its share of the distance tiles (the rows of tiles of
-// for_each_distance, in the same order), two source tiles kb, kb + 1 per
-// step.  Holds the current row's B operand (-2 x_i with a 1 in row 7) and
-// the target norms as the accumulator input.
+// Exact order statistic r of the values kept in the window buffer (same
+// layout as buffer_select), in one histogram pass: the key offsets
+// key - key_lo go to kBins bins (the top bits of the span), one wave finds
+// the bin holding rank r, gathers that bin's values into cand and ranks them
+// by comparison.  hist (kBins counters) must be zero on entry and visible to
+// all waves.  A bin with more than 64 values (heavy ties) falls back to
+// buffer_select.
+__device__ float window_select(const float *buf, const uint32_t *wcnt, int nregions, uint32_t r, uint32_t key_lo,
+                               uint32_t key_hi, uint32_t *hist, uint32_t *red, float *cand, uint32_t *hist_small)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
+    const uint32_t span = key_hi - key_lo;
+    const int bits = span == 0 ? 1 : 32 - __clz(span);
+    constexpr int kBinBits = 11;
+    static_assert(kBins == 1 << kBinBits, "one bin per counter");
+    const int shift = bits > kBinBits ? bits - kBinBits : 0;
+    for (int w = wave; w < nregions; w += nwaves) {
+        const uint32_t c = wcnt[w];
+        for (uint32_t s = lane; s < c; s += kWave)
+            atomicAdd(&hist[(__float_as_uint(buf[w * kWinRegion + s]) - key_lo) >> shift], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        constexpr int per = kBins / kWave;
+        uint32_t cnt = 0;
+        for (int q = 0; q < per; ++q) cnt += hist[lane * per + q];
+        const uint32_t incl = wave_incl_scan(cnt, lane);
+        const uint32_t excl = incl - cnt;
+        if (r >= excl && r < incl) {
+            uint32_t rr = r - excl;
+            for (int q = 0; q < per; ++q) {
+                const uint32_t hq = hist[lane * per + q];
+                if (rr < hq) {
+                    red[2] = (uint32_t)(lane * per + q);
+                    red[3] = rr;
+                    red[4] = hq;
+                    break;
+                }
+                rr -= hq;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t bin = red[2], rr = red[3], cb = red[4];
+    if (cb > (uint32_t)kWave) return buffer_select(buf, wcnt, nregions, r, key_lo, key_hi, hist_small, red);
+    if (wave == 0) {
+        uint32_t base = 0;
+        for (int w = 0; w < nregions; ++w) {
+            const uint32_t c = wcnt[w];
+            for (uint32_t s0 = 0; s0 < c; s0 += kWave) {
+                const uint32_t s = s0 + lane;
+                float v = 0.f;
+                bool in = false;
+                if (s < c) {
+                    v = buf[w * kWinRegion + s];
+                    in = ((__float_as_uint(v) - key_lo) >> shift) == bin;
+                }
+                const unsigned long long mk = __builtin_amdgcn_ballot_w64(in);
+                if (in) cand[base + lanes_below(mk)] = v;
+                base += (uint32_t)__builtin_popcountll(mk);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((uint32_t)lane < cb) {
+            const float v = cand[lane];
+            uint32_t less = 0, leq = 0;
+            for (uint32_t t = 0; t < cb; ++t) {
+                const float u = cand[t];
+                less += u < v ? 1u : 0u;
+                leq += u <= v ? 1u : 0u;
+            }
+            if (less <= rr && rr < leq) red[5] = __float_as_uint(v);
+        }
+    }
+    __syncthreads();
+    return __uint_as_float(red[5]);
+}
+
+// One wave's walk over its share of the off-diagonal distance tiles (the
+// rows of tiles of for_each_distance, in the same order, source tiles
+// kb > ib), two source tiles kb, kb + 1 per step.  Holds the current row's
+// B operand (-2 x_i with a 1 in row 7) and the target norms as the
+// accumulator input.  The diagonal tiles of the wave's rows are visited by
+// diagonals().
 struct TileWalker {
     int nt16, nwaves, wave, rr, ib, kb;
     float bi0, bi1;
     f32x4 cn;
 
+    __device__ int row_of(int r) const { return (r & 1) ? (r + 1) * nwaves - 1 - wave : r * nwaves + wave; }
+    __device__ void load_row(const float *X8, int g, int col)
+    {
+        const float *xi = X8 + (long)(ib * 16 + col) * 8;
+        bi0 = -2.f * xi[g];
+        bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
+        const float nni = xi[7];
+        cn = f32x4{nni, nni, nni, nni};
+    }
     __device__ void start(const float *X8, int npad, int g, int col)
     {
         nt16 = npad / 16;
@@ -272,21 +369,17 @@ struct TileWalker {
         rr = -1;
         next_row(X8, g, col);
     }
+    // next row with an off-diagonal tile
     __device__ void next_row(const float *X8, int g, int col)
     {
-        ++rr;
-        ib = (rr & 1) ? (rr + 1) * nwaves - 1 - wave : rr * nwaves + wave;
-        kb = ib;
-        if (ib < nt16) {
-            const float *xi = X8 + (long)(ib * 16 + col) * 8;
-            bi0 = -2.f * xi[g];
-            bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
-            const float nni = xi[7];
-            cn = f32x4{nni, nni, nni, nni};
-        }
+        do {
+            ++rr;
+            ib = row_of(rr);
+            kb = ib + 1;
+        } while (ib < nt16 && kb >= nt16);
+        if (ib < nt16) load_row(X8, g, col);
     }
     __device__ bool done() const { return ib >= nt16; }
-    __device__ bool diag() const { return kb == ib; }
     __device__ bool second() const { return kb + 1 < nt16; }
     // distances of tiles kb and kb + 1 (clamped to the row: always in
     // bounds, also once the walk is done; results past the end are unused)
@@ -305,6 +398,17 @@ struct TileWalker {
         kb += 2;
         if (kb >= nt16) next_row(X8, g, col);
     }
+    // the diagonal tile of every row of this wave, fn(D, true)
+    template <typename Fn> __device__ void diagonals(const float *X8, int g, int col, Fn &&fn)
+    {
+        for (int r = 0;; ++r) {
+            ib = row_of(r);
+            if (ib >= nt16) break;
+            load_row(X8, g, col);
+            const float *xk = X8 + (long)(ib * 16 + col) * 8;
+            fn(mfma16(xk[4 + g], bi1, mfma16(xk[g], bi0, cn)), true);
+        }
+    }
 };
 
 // Median tracker across the iterations of one step.  The previous two
@@ -321,7 +425,7 @@ struct MedianTracker {
     int have;        // number of medians recorded (0, 1, 2+)
     bool active;     // a window pass is under way this iteration
     float lo, hi;    // the window
-    uint32_t below;  // per wave: distances below lo
+    uint32_t below;  // per lane: distances below lo
     uint32_t kept;   // per wave: distances kept (kOverflow once the region is full)
 
     __device__ void reset()
@@ -349,30 +453,36 @@ struct MedianTracker {
 
     static constexpr uint32_t kOverflow = 0x40000000u;
 
-    // one tile of distances (diag: only pairs k > i count)
-    __device__ void visit(const f32x4 &Dv, bool diag, float *region)
+    // One tile of distances (diag: only pairs k > i count).  The common case
+    // is vector work only: a per-lane count of the distances below lo, and
+    // one test for a distance inside the window, on the bit-pattern offsets
+    // key(D) - key(lo) (unsigned, below span exactly when lo <= D < hi; a
+    // negative D or NaN never is).  Only a tile holding window distances
+    // appends them to the wave's region.
+    __device__ void visit(f32x4 Dv, bool diag, float *region)
     {
-        unsigned long long inw[4], any = 0;
+        if (diag) {
+            const int l = threadIdx.x & 63;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (!((diag_lanes(r) >> l) & 1ull)) Dv[r] = __builtin_huge_valf();
+        }
+        const uint32_t klo = __float_as_uint(lo), span = __float_as_uint(hi) - klo;
+        uint32_t u[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const unsigned long long vm = diag ? diag_lanes(r) : ~0ull;
-            const unsigned long long lt = __builtin_amdgcn_ballot_w64(Dv[r] < lo) & vm;
-            const unsigned long long lh = __builtin_amdgcn_ballot_w64(Dv[r] < hi) & vm;
-            below += (uint32_t)__builtin_popcountll(lt);
-            inw[r] = lh & ~lt;
-            any |= inw[r];
+            below += Dv[r] < lo ? 1u : 0u;
+            u[r] = __float_as_uint(Dv[r]) - klo;
         }
-        if (any) {
+        const uint32_t um = min(min(u[0], u[1]), min(u[2], u[3]));
+        if (__builtin_amdgcn_ballot_w64(um < span)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                if (!inw[r]) continue;
-                const uint32_t cnt = (uint32_t)__builtin_popcountll(inw[r]);
-                if (kept + cnt > (uint32_t)kWinRegion) {
-                    kept = kOverflow;
-                    break;
-                }
-                if ((inw[r] >> (threadIdx.x & 63)) & 1ull) region[kept + lanes_below(inw[r])] = Dv[r] + 0.f;  // no -0
-                kept += cnt;
+                const unsigned long long mk = __builtin_amdgcn_ballot_w64(u[r] < span);
+                const uint32_t cnt = (uint32_t)__builtin_popcountll(mk);
+                const bool fits = kept + cnt <= (uint32_t)kWinRegion;  // kOverflow stays
+                if (fits && u[r] < span) region[kept + lanes_below(mk)] = Dv[r] + 0.f;  // no -0
+                kept = fits ? kept + cnt : kOverflow;
             }
         }
     }
@@ -386,15 +496,19 @@ struct MedianTracker {
         if (M == 0) return __builtin_nanf("");
         const uint32_t rank = (M - 1) / 2;
         const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
+        // red[0..1] radix selection, red[2..5] window_select, red[8..9]
+        // buffer_select
         uint32_t *wcnt = red + 10;    // per-wave kept counts (red[10..25])
         uint32_t *wbelow = red + 26;  // per-wave below counts (red[26..41])
         float med = 0.f;
         bool done = false;
         if (active) {
+            const uint32_t bw = wave_sum(below);
             if (lane == 0) {
-                wbelow[wave] = below;
+                wbelow[wave] = bw;
                 wcnt[wave] = kept;
             }
+            for (int q = tid; q < kBins; q += nt) hist[q] = 0;
             __syncthreads();
             uint32_t cnt_lo = 0, n_in = 0;
             bool overflow = false;
@@ -405,8 +519,8 @@ struct MedianTracker {
             }
             density = uniform((float)n_in / (hi - lo));
             if (!overflow && rank >= cnt_lo && rank < cnt_lo + n_in) {
-                med = buffer_select(buf, wcnt, nwaves, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi),
-                                    hist_small, red);
+                med = window_select(buf, wcnt, nwaves, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi),
+                                    hist, red, (float *)hist_small, hist_small);
                 done = true;
             }
             __syncthreads();
@@ -421,8 +535,23 @@ struct MedianTracker {
     }
 };
 
+// Wave priority from progress through a pass of n tile steps (called every
+// second step): 3 in the first quarter down to 0 in the last.  The SIMD
+// arbiter otherwise favours the oldest wave, which then finishes a pass far
+// ahead of the others and leaves the tail of the pass to few waves.
+__device__ __forceinline__ void progress_priority(int step, int n)
+{
+    const int q = (step * 4) / n;
+    if (step == 0) __builtin_amdgcn_s_setprio(3);
+    else if (q != ((step - 2) * 4) / n) {
+        if (q == 1) __builtin_amdgcn_s_setprio(2);
+        else if (q == 2) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+    }
+}
+
 template <int KIND, int D>
-__global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
+__global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
 {
     using F = Family<float, KIND, D>;
     using R = RealOps<float>;
@@ -433,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
     const int npad = L.npad, nppad = L.nppad;
     float *X8 = (float *)(smem + L.off_x);     // [npad][8]  centred particles, |x|^2 in column 7 (pad: 0.., +inf)
     float *S8 = (float *)(smem + L.off_s);     // [npad][8]  scores
-    float *M8 = (float *)(smem + L.off_m);     // [nppad][8] (2 mh_j (d), 0.., c'_j)
+    float *VT = (float *)(smem + L.off_m);     // [9][nppad] rows 2 mh_c (c < 7; 0 for c >= d), 1, c'_j
     float *PHP = (float *)(smem + L.off_phip); // [nppad] previous forward-recursion scores
     float *SCR = (float *)(smem + L.off_scr);
     uint32_t *hist = (uint32_t *)(smem + L.off_scr);
@@ -483,12 +612,14 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
         __syncthreads();
     }
 
-    // transition means, centred and log2-scaled: M8[j] = (2 mh_j, 0.., c'_j),
-    // c'_j = log2 w_j - |mh_j|^2; pad rows give logit -inf
+    // transition means, centred and log2-scaled, component-major:
+    // VT[c][j] = 2 mh_jc (c < 7), VT[7][j] = 1, VT[8][j] = c'_j =
+    // log2 w_j - |mh_j|^2; pad columns give logit -inf
     for (int j = tid; j < nppad; j += nt) {
-        float row[8];
+        float row[kVtRows];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) row[c] = 0.f;
+        for (int c = 0; c < kVtRows; ++c) row[c] = 0.f;
+        row[7] = 1.f;
         if (j < np) {
             float xp[D], mu[D];
 #pragma unroll
@@ -502,12 +633,12 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                 nrm += mh * mh;
             }
             const float lw = a.log_w ? a.log_w[(long)b * a.log_w_stride + j] : -R::log_((float)np);
-            row[7] = lw * (float)kLog2e - nrm;
+            row[8] = lw * (float)kLog2e - nrm;
         } else {
-            row[7] = -inf;
+            row[8] = -inf;
         }
 #pragma unroll
-        for (int c = 0; c < 8; ++c) M8[(long)j * 8 + c] = row[c];
+        for (int c = 0; c < kVtRows; ++c) VT[(long)c * nppad + j] = row[c];
     }
     // initial particles, centred
     for (int i = tid; i < npad; i += nt) {
@@ -549,7 +680,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
     if (a.do_svgd && a.trans_mode == 1) {
         for (int c = 0; c < D; ++c) {
             float part = 0.f;
-            for (int j = tid; j < np; j += nt) part += M8[(long)j * 8 + c] * 0.5f / rs[c];
+            for (int j = tid; j < np; j += nt) part += VT[(long)c * nppad + j] * 0.5f / rs[c];
             part = wave_sum(part);
             if (lane == 0) redf[wave] = part;
             __syncthreads();
@@ -581,7 +712,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
         auto walk_step = [&]() {
             f32x4 W0, W1;
             walker.issue(X8, g, col, W0, W1);
-            tracker.visit(W0, walker.diag(), wregion);
+            tracker.visit(W0, false, wregion);
             if (walker.second()) tracker.visit(W1, false, wregion);
             walker.advance(X8, g, col);
         };
@@ -589,8 +720,8 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
         // (2) scores
         for (int task = wave; task < ntasks; task += nwaves) {
             const int kbase = task * 64;
+            float osum[8];  // trans_mode 0: sum_j e_kj [2 mh_j, 1] of this lane's particle kbase + lane
             if (a.trans_mode == 0) {
-                f32x4 O[kTilesPerWave];
                 f32x4 cm[kTilesPerWave];  // -reference of each particle column, as the accumulator input
                 float bx0[kTilesPerWave], bx1[kTilesPerWave];
 #pragma unroll
@@ -599,17 +730,27 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                     const int kd0 = g, kd1 = 4 + g;
                     bx0[q] = kd0 < D ? X8[(long)kk * 8 + kd0] * rs[kd0] : 0.f;
                     bx1[q] = kd1 < D ? X8[(long)kk * 8 + kd1] * rs[kd1] : (kd1 == 7 ? 1.f : 0.f);
-                    O[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                     cm[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-                // value operand of lane (col, g): column col of row j of
-                // [2 mh_j, 1, 0..] = fma(M8[j][col < 7 ? col : 0], vf, vc)
-                const float vf = col < 7 ? 1.f : 0.f, vc = col == 7 ? 1.f : 0.f;
-                const float *vrow = M8 + (long)(4 * g) * 8 + (col < 7 ? col : 0);  // finite column for col >= 7
+                // Sums on the 4x4x1 (16-block) MFMA with one particle per lane:
+                // lane l holds rows c = 4 ch + i of particle kbase + l in
+                // O4[ch][par] register i (two accumulators per half, for
+                // alternating j); block b = l / 4 takes A = VT[4 ch + l % 4][j]
+                // from its lanes and B = e_j of its four particles.
+                f32x4 O4[2][2];
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+                    for (int par = 0; par < 2; ++par) O4[ch][par] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const float *vt0 = VT + (long)(lane & 3) * nppad;        // rows c = l % 4
+                const float *vt1 = VT + (long)(4 + (lane & 3)) * nppad;  // rows c = 4 + l % 4
+                // logit A operands: K-row g (2 mh), K-row 4 + g (row 7 of the
+                // table, the 1, becomes c'_j in K-row 7)
+                const float *am0p = VT + (long)g * nppad + col;
+                const float *am1p = VT + (long)(g == 3 ? 8 : 4 + g) * nppad + col;
                 // logits of tile jt relative to the column references
                 auto logits = [&](int jt, f32x4 (&Lo)[kTilesPerWave]) {
-                    const float *mrow = M8 + (long)(jt * 16 + col) * 8;
-                    const float am0 = mrow[g], am1 = mrow[4 + g];
+                    const float am0 = am0p[jt * 16], am1 = am1p[jt * 16];
 #pragma unroll
                     for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am0, bx0[q], cm[q]);
 #pragma unroll
@@ -622,49 +763,83 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                 // test compares the bit patterns as integers: for a positive
                 // bound that orders like the floats, and NaN also triggers.
                 auto rebase = [&](f32x4 (&T)[kTilesPerWave], bool first) {
-                    int m = __float_as_int(T[0][0]);
+                    int mxi = __float_as_int(T[0][0]);
 #pragma unroll
                     for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) m = max(m, __float_as_int(T[q][r]));
-                    if (first || __builtin_amdgcn_ballot_w64(m > __float_as_int(kRescaleGap))) {
+                        for (int r = 0; r < 4; ++r) mxi = max(mxi, __float_as_int(T[q][r]));
+                    if (first || __builtin_amdgcn_ballot_w64(mxi > __float_as_int(kRescaleGap))) {
+                        float shq[kTilesPerWave];
 #pragma unroll
                         for (int q = 0; q < kTilesPerWave; ++q) {
                             const float lmax = fmax_(fmax_(T[q][0], T[q][1]), fmax_(T[q][2], T[q][3]));
                             const float gm = group_max4(lmax);
                             const bool up = first ? gm > -inf : gm > kRescaleGap;
-                            const float sh = up ? gm : 0.f;
-                            O[q] *= first ? 1.f : R::exp2_(-sh);
-                            T[q] -= sh;
-                            cm[q] -= sh;
+                            shq[q] = up ? gm : 0.f;
+                            T[q] -= shq[q];
+                            cm[q] -= shq[q];
+                        }
+                        if (!first) {
+                            // lane l's particle is column col of tile q = l / 16
+                            const float sh = g == 0 ? shq[0] : g == 1 ? shq[1] : g == 2 ? shq[2] : shq[3];
+                            const float sc = R::exp2_(-sh);
+#pragma unroll
+                            for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+                                for (int par = 0; par < 2; ++par) O4[ch][par] *= sc;
                         }
                     }
                 };
-                // Two logit tiles per round (the buffers alternate), software
-                // pipelined: the logits of tile jt + 1 are issued and checked
-                // around the exponentials and sums of tile jt; with WALK, two
-                // tiles of the median window pass ride along.
+                // exponentials of a relative logit tile, moved to one particle
+                // per lane: afterwards register T[m][r] of lane l holds e for
+                // j = 16 jt + 4 m + r and particle kbase + l (a 4x4 transpose
+                // of lane groups against tiles, two rounds of lane swaps)
+                auto exp_transpose = [&](f32x4 (&T)[kTilesPerWave]) {
+#pragma unroll
+                    for (int q = 0; q < kTilesPerWave; ++q)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) T[q][r] = R::exp2_(T[q][r]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(T[q][r]),
+                                                                             __float_as_uint(T[q + 2][r]), false, false);
+                            T[q][r] = __uint_as_float(sw[0]);
+                            T[q + 2][r] = __uint_as_float(sw[1]);
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; q += 2) {
+                            const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(T[q][r]),
+                                                                             __float_as_uint(T[q + 1][r]), false, false);
+                            T[q][r] = __uint_as_float(sw[0]);
+                            T[q + 1][r] = __uint_as_float(sw[1]);
+                        }
+                    }
+                };
+                // One logit tile per step, software-pipelined: the logits of
+                // tile jt + 1 are issued (and checked) around the exponentials
+                // and sums of tile jt; with WALK, two tiles of the median
+                // window pass ride along.
                 auto score_loop = [&](auto walk_tag) {
                     constexpr bool WALK = decltype(walk_tag)::value;
                     auto tile = [&](int jt, f32x4 (&T)[kTilesPerWave], f32x4 (&Tn)[kTilesPerWave]) {
-                        const float *vr = vrow + (long)(jt * 16) * 8;
-                        float av[4];
-#pragma unroll
-                        for (int mm = 0; mm < 4; ++mm) av[mm] = __builtin_fmaf(vr[mm * 8], vf, vc);
                         logits(min(jt + 1, njt - 1), Tn);
                         f32x4 W0, W1;
                         if (WALK) walker.issue(X8, g, col, W0, W1);
+                        exp_transpose(T);
 #pragma unroll
-                        for (int q = 0; q < kTilesPerWave; ++q)
+                        for (int mq = 0; mq < 4; ++mq) {
+                            const f32x4 va0 = *(const f32x4 *)(vt0 + jt * 16 + 4 * mq);
+                            const f32x4 va1 = *(const f32x4 *)(vt1 + jt * 16 + 4 * mq);
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) T[q][r] = R::exp2_(T[q][r]);
-                        // independent accumulators back to back
-#pragma unroll
-                        for (int mm = 0; mm < 4; ++mm)
-#pragma unroll
-                            for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], T[q][mm], O[q]);
+                            for (int r = 0; r < 4; ++r) {
+                                O4[0][r & 1] = __builtin_amdgcn_mfma_f32_4x4x1f32(va0[r], T[mq][r], O4[0][r & 1], 0, 0, 0);
+                                O4[1][r & 1] = __builtin_amdgcn_mfma_f32_4x4x1f32(va1[r], T[mq][r], O4[1][r & 1], 0, 0, 0);
+                            }
+                        }
                         if (WALK && !walker.done()) {
-                            tracker.visit(W0, walker.diag(), wregion);
+                            tracker.visit(W0, false, wregion);
                             if (walker.second()) tracker.visit(W1, false, wregion);
                             walker.advance(X8, g, col);
                         }
@@ -674,6 +849,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                     logits(0, TA);
                     rebase(TA, true);
                     for (int jt = 0; jt < njt; jt += 2) {
+                        progress_priority(jt, njt);
                         tile(jt, TA, TB);
                         if (jt + 1 < njt) tile(jt + 1, TB, TA);
                     }
@@ -682,21 +858,14 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                     score_loop(std::true_type{});
                 else
                     score_loop(std::false_type{});
-                // O[q] lane l register r = (c = 4g + r, particle kbase + 16 q + col);
-                // rows c < 7 hold sum_j e 2 mh_j, row 7 sum_j e
-                if (g < 2) {
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) scr[(q * 8 + 4 * g + r) * 16 + col] = O[q][r];
+                for (int i = 0; i < 4; ++i) {
+                    osum[i] = O4[0][0][i] + O4[0][1][i];
+                    osum[4 + i] = O4[1][0][i] + O4[1][1][i];
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             {
                 const int k = kbase + lane;
-                const int q = lane >> 4;
                 float srow[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) srow[c] = 0.f;
@@ -710,10 +879,10 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                     }
                     F::grad(m, sz, mk, xa, gr);
                     if (a.trans_mode == 0) {
-                        const float inv_sum = 1.f / scr[(q * 8 + 7) * 16 + col];
+                        const float inv_sum = 1.f / osum[7];
 #pragma unroll
                         for (int c = 0; c < D; ++c) {
-                            const float mb = scr[(q * 8 + c) * 16 + col] * inv_sum * 0.5f / rs[c];
+                            const float mb = osum[c] * inv_sum * 0.5f / rs[c];
                             srow[c] = gr[c] - (xt[c] - mb) * m.inv_q[c];
                         }
                     } else {
@@ -728,8 +897,11 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (tracker.active)
+        __builtin_amdgcn_s_setprio(0);
+        if (tracker.active) {
             while (!walker.done()) walk_step();
+            walker.diagonals(X8, g, col, [&](const f32x4 &Dd, bool dg) { tracker.visit(Dd, dg, wregion); });
+        }
         __syncthreads();
         if (need_median) {
             const float med = tracker.finish(X8, n, npad, WIN, whist, hist, red);
@@ -741,8 +913,11 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
         // (3) Stein direction
         const float twob = 2.f * beta;
         const float c2 = 2.f / h;
-        float phi[kTilesPerWave][2];
-        for (int task = wave; task < ntasks; task += nwaves) {
+        float phi[kTaskSlots][kTilesPerWave][2];  // kept in registers until every wave is done
+#pragma unroll
+        for (int ts = 0; ts < kTaskSlots; ++ts) {
+            const int task = wave + ts * nwaves;
+            if (task >= ntasks) break;
             const int ibase = task * 64;
             // B columns (2 beta x_i, -beta in K-row 7); the accumulator starts
             // at -beta n_i, so a Gram tile holds the exponent
@@ -795,6 +970,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
             f32x4 GA[kTilesPerWave], GB[kTilesPerWave];
             gram(0, GA);
             for (int kt = 0; kt < nkt; kt += 2) {
+                progress_priority(kt, nkt);
                 tile(kt, GA, GB);
                 if (kt + 1 < nkt) tile(kt + 1, GB, GA);
             }
@@ -815,16 +991,20 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                     float v = 0.f;
                     if (c < D)
                         v = (scr[c * 16 + col] + c2 * (X8[(long)ii * 8 + c] * ksum - scr[(8 + c) * 16 + col])) * inv_n;
-                    phi[q][h2] = v;
+                    phi[ts][q][h2] = v;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // synchronous update, then unscaled squared norms for the next median
-        for (int task = wave; task < ntasks; task += nwaves) {
+#pragma unroll
+        for (int ts = 0; ts < kTaskSlots; ++ts) {
+            const int task = wave + ts * nwaves;
+            if (task >= ntasks) break;
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = task * 64 + 16 * q + col;
@@ -832,7 +1012,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
 #pragma unroll
                     for (int h2 = 0; h2 < 2; ++h2) {
                         const int c = g + 4 * h2;
-                        if (c < D) X8[(long)ii * 8 + c] += a.step * phi[q][h2];
+                        if (c < D) X8[(long)ii * 8 + c] += a.step * phi[ts][q][h2];
                     }
                 }
             }
@@ -874,7 +1054,7 @@ __global__ __launch_bounds__(1024) void k_step_mfma(StepArgs<float> a)
                 float q2 = 0.f;
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
-                    const float r = xs[c] - 0.5f * M8[(long)j * 8 + c];
+                    const float r = xs[c] - 0.5f * VT[(long)c * nppad + j];
                     q2 += r * r;
                 }
                 const float A = m.log_z - (float)kLn2 * q2;

@@ -77,9 +77,9 @@ constexpr int kMaxParticles = 1024;  // largest sequence the kernel takes
 constexpr int kTaskSlots = kMaxParticles / 64 / kMaxWaves;  // tasks per wave at most
 constexpr int kWaveScratch = 256; // floats of per-wave LDS scratch (one 16x16 tile)
 constexpr int kVtRows = 9;        // rows of the transition-mean table: 2 mh (7), 1, c'
-constexpr int kWinCap = 4096;     // capacity of the median window buffer (floats)
+constexpr int kWinCap = 8192;     // capacity of the median window buffer (floats)
 constexpr int kWinRegion = kWinCap / kMaxWaves; // per-wave share of the window buffer
-constexpr int kWinTarget = 1024;  // aimed-for number of distances in the window
+constexpr int kWinTarget = 512;   // aimed-for number of distances in the window
 constexpr float kRescaleGap = 8.f; // log2 headroom before the softmax reference moves
 
 // LDS byte layout of the MFMA step workgroup.
@@ -1017,12 +1017,21 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
                 }
             }
         }
-        __syncthreads();
-        for (int i = tid; i < n; i += nt) {
-            float nrm = 0.f;
+        // a wave's particles were written by its own lanes only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int c = 0; c < D; ++c) { const float v = X8[(long)i * 8 + c]; nrm += v * v; }
-            X8[(long)i * 8 + 7] = nrm;
+        for (int ts = 0; ts < kTaskSlots; ++ts) {
+            const int task = wave + ts * nwaves;
+            if (task >= ntasks) break;
+            const int i = task * 64 + lane;
+            if (i < n) {
+                float nrm = 0.f;
+#pragma unroll
+                for (int c = 0; c < D; ++c) { const float v = X8[(long)i * 8 + c]; nrm += v * v; }
+                X8[(long)i * 8 + 7] = nrm;
+            }
         }
         __syncthreads();
     }

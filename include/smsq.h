@@ -222,6 +222,82 @@ smsq_status_t smsq_run_sequence(smsq_model_t model, smsq_dtype_t dtype, int T, i
                                 void *xmap_out, void *logpost_out, void *particles_out,
                                 void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- Batched ragged form ------------------------------------------------
+ * Thousands of independent sequences of different model family, particle
+ * count n and length T run Algorithm 2 together: every time step t is one
+ * persistent launch over all sequences with T >= t (one workgroup per
+ * sequence step, taken longest first from an atomic queue), followed at the
+ * end by one backtrack launch over all sequences.  FP32, matrix-core step
+ * kernel; families GROWTH1D, RANGE2D, CV4D and ARM7.
+ *
+ * The plan owns its device storage (every step's particles, forward-
+ * recursion scores and backpointers of every sequence), allocated at
+ * creation; runs allocate nothing.  Caller arrays named in
+ * smsq_batch_seq_t are device pointers that must stay valid while the plan
+ * runs.  A sequence's results equal those of smsq_run_sequence with the same
+ * model, n, T, seed and options. */
+typedef struct smsq_batch_plan_s *smsq_batch_plan_t;
+
+typedef struct {
+    int model;              /* index into the plan's model/options arrays */
+    int n;                  /* particles per step, 1..1024 */
+    int T;                  /* steps, >= 1 */
+    int init_given;         /* 0: predictive initial particles (Philox, as in
+                               smsq_batch_step with seq_offset 0); 1: the plan's
+                               particle storage of step t already holds them
+                               (written by a learned proposal before the run) */
+    uint64_t seed;
+    const void *x0;         /* [d] FP32 known initial state */
+    const void *z;          /* [T][obs_dim] FP32 observations */
+    const uint8_t *z_mask;  /* [T][n_obs] or NULL */
+    void *xmap_out;         /* [T+1][d] FP32 MAP trajectory out (x_0 first) */
+    void *logpost_out;      /* [1] FP32 J out */
+} smsq_batch_seq_t;
+
+typedef struct {
+    int count;              /* sequences */
+    int T_max;              /* launches per run: T_max steps + 1 backtrack */
+    int waves;              /* waves per workgroup of the step launches (8 or 16) */
+    int grid;               /* persistent workgroups per step launch */
+    size_t lds_bytes;       /* dynamic LDS per workgroup */
+    size_t device_bytes;    /* device memory held by the plan */
+    double tuned_ms[2];     /* autotuner timings per step: 16 waves, 8 waves (0 if not run) */
+} smsq_batch_info_t;
+
+/* Validates the sequences, orders every step's active sequences by
+ * descending n^2 L and allocates the plan's storage.  models[k] and
+ * opts[k] (host) describe model index k; n_models >= 1.  Starts with 16
+ * waves per workgroup.  Errors: SMSQ_ERR_INVALID (bad index, size, pointer
+ * or options), SMSQ_ERR_UNSUPPORTED (family not carried, n too large for
+ * LDS), SMSQ_ERR_HIP (allocation). (host) */
+smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd_opts_t *opts,
+                                     int n_models, const smsq_batch_seq_t *seqs, int count,
+                                     smsq_batch_plan_t *out);
+
+/* Autotuner: runs the first `steps` (>= 2) steps eagerly on `stream` with
+ * each workgroup shape (16 waves, one 64-particle task per wave; 8 waves,
+ * two tasks per wave) and grid size from the occupancy of that shape, times
+ * the steps after the first with HIP events, and keeps the faster shape.
+ * Synchronises the stream. (host) */
+smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t plan, int steps, hipStream_t stream);
+
+/* Runs every sequence end to end on `stream` (asynchronous).  use_graph:
+ * the T_max + 1 launches (and the reset of the queue counters and status)
+ * are captured once into a hipGraph on first use and replayed afterwards;
+ * `stream` must then be a non-default stream. */
+smsq_status_t smsq_batch_run(smsq_batch_plan_t plan, int use_graph, hipStream_t stream);
+
+/* Device pointers of sequence `seq`'s storage in the plan: particles
+ * [T][n][d], forward-recursion scores [T][n], backpointers [T][n].  Any
+ * output pointer may be NULL. (host) */
+smsq_status_t smsq_batch_storage(smsq_batch_plan_t plan, int seq, void **particles, void **phi,
+                                 int32_t **psi);
+
+smsq_status_t smsq_batch_plan_info(smsq_batch_plan_t plan, smsq_batch_info_t *out);
+/* Device status of the last run (after stream sync): SMSQ_OK or SMSQ_ERR_NONFINITE. */
+smsq_status_t smsq_batch_status(smsq_batch_plan_t plan, smsq_status_t *out);
+smsq_status_t smsq_batch_plan_destroy(smsq_batch_plan_t plan);
+
 /* Reads the workspace status word (synchronous device-to-host copy; call
  * after the work has been synchronised).  *out is SMSQ_OK or
  * SMSQ_ERR_NONFINITE. */

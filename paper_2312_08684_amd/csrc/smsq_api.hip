@@ -8,10 +8,13 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <algorithm>
+#include <vector>
 
 #include "smsq.h"
 #include "smsq_kernels.hpp"
 #include "smsq_mfma.hpp"
+#include "smsq_batch.hpp"
 
 #include <cstdlib>
 
@@ -126,11 +129,14 @@ bool step_shape_ok(smsq_dtype_t dt, int n, int n_prev, int d)
     return (n + nt - 1) / nt <= kMaxRowsPerThread;
 }
 
-template <typename KernelFn> hipError_t allow_big_lds(KernelFn fn)
+template <typename KernelFn> hipError_t allow_big_lds(KernelFn fn, long static_bytes = 0)
 {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsLimit - static_bytes));
 }
+
+// static LDS of the persistent batch kernels (the queue slot), rounded up
+constexpr long kBatchStaticLds = 256;
 
 template <typename T, int KIND, int D>
 smsq_status_t launch_step_kd(const StepArgs<T> &a, int batch, hipStream_t s)
@@ -310,6 +316,116 @@ RunLayout run_layout(smsq_dtype_t dt, int batch, int T, int n, int d)
 }
 
 bool dtype_ok(smsq_dtype_t dt) { return dt == SMSQ_F32 || dt == SMSQ_F64; }
+
+// ---- batched ragged plans ------------------------------------------------
+
+int device_cus()
+{
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 1;
+    });
+    return cus;
+}
+
+hipError_t batch_kernel_attrs()
+{
+    static hipError_t err = hipSuccess;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        err = allow_big_lds(&k_batch_step_w16, kBatchStaticLds);
+        if (err == hipSuccess) err = allow_big_lds(&k_batch_step_w8, kBatchStaticLds);
+    });
+    return err;
+}
+
+template <typename P> hipError_t dev_alloc(P **p, size_t count, size_t &total)
+{
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    const size_t bytes = align256(count * sizeof(P));
+    total += bytes;
+    return hipMalloc((void **)p, bytes);
+}
+
+} // namespace
+
+struct smsq_batch_plan_s {
+    int count = 0, T_max = 0, max_active = 0;
+    std::vector<int> list_off, list_cnt;  // per step t - 1
+    std::vector<SeqDesc> host;            // per sequence
+    SeqDesc *seqs = nullptr;
+    int *lists = nullptr;
+    StepArgs<float> *items = nullptr;
+    uint8_t *codes = nullptr;
+    uint32_t *counters = nullptr, *status = nullptr;
+    float *parts = nullptr, *phis = nullptr;
+    int32_t *psis = nullptr, *idx = nullptr;
+    size_t lds = 0, device_bytes = 0;
+    int waves = 16;
+    double tuned[2] = {0.0, 0.0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_waves = 0;
+
+    int grid() const
+    {
+        int nb = 0;
+        const hipError_t e = waves == 16
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step_w16, 16 * kWave, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step_w8, 8 * kWave, lds);
+        if (e != hipSuccess || nb < 1) nb = 1;
+        return std::max(1, std::min(device_cus() * nb, max_active));
+    }
+    void free_all()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        void *ps[] = {seqs, lists, items, codes, counters, status, parts, phis, psis, idx};
+        for (void *q : ps)
+            if (q) hipFree(q);
+    }
+    // One step launch pair (prep + persistent step) for step t.
+    smsq_status_t step(int t, hipStream_t s) const
+    {
+        const int cnt = list_cnt[t - 1];
+        if (cnt == 0) return SMSQ_OK;
+        hipLaunchKernelGGL(k_batch_prep, dim3((cnt + 63) / 64), dim3(64), 0, s, seqs, lists + list_off[t - 1], cnt,
+                           t, items, codes, status);
+        const int g = std::min(grid(), cnt);
+        if (waves == 16)
+            hipLaunchKernelGGL(k_batch_step_w16, dim3(g), dim3(16 * kWave), lds, s, items, codes, cnt,
+                               counters + (t - 1));
+        else
+            hipLaunchKernelGGL(k_batch_step_w8, dim3(g), dim3(8 * kWave), lds, s, items, codes, cnt,
+                               counters + (t - 1));
+        return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+    }
+    smsq_status_t reset(hipStream_t s) const
+    {
+        hipLaunchKernelGGL(k_fill_u32, dim3((T_max + 255) / 256), dim3(256), 0, s, counters, 0u, T_max);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, status, 0u, 1);
+        return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+    }
+    smsq_status_t enqueue(hipStream_t s) const
+    {
+        smsq_status_t st = reset(s);
+        for (int t = 1; st == SMSQ_OK && t <= T_max; ++t) st = step(t, s);
+        if (st != SMSQ_OK) return st;
+        hipLaunchKernelGGL(k_backtrack_ragged, dim3(count), dim3(kWave), 0, s, seqs, count, status);
+        return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+    }
+};
+
+namespace {
+
+bool batch_family(int kind) { return kind >= SMSQ_MODEL_GROWTH1D && kind <= SMSQ_MODEL_ARM7; }
 
 } // namespace
 
@@ -506,6 +622,221 @@ smsq_status_t smsq_clear_device_status(void *ws, hipStream_t stream)
     if (!ws) return SMSQ_ERR_INVALID;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, status_ptr(ws), 0u, 1);
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd_opts_t *opts, int n_models,
+                                     const smsq_batch_seq_t *seqs, int count, smsq_batch_plan_t *out)
+{
+    if (!out) return SMSQ_ERR_INVALID;
+    *out = nullptr;
+    if (!models || !opts || n_models < 1 || !seqs || count < 1) return SMSQ_ERR_INVALID;
+    for (int k = 0; k < n_models; ++k)
+        if (!models[k] || !opts_ok(&opts[k])) return SMSQ_ERR_INVALID;
+    long lds = 0;
+    int T_max = 0;
+    size_t n_parts = 0, n_phi = 0, n_T = 0;
+    for (int i = 0; i < count; ++i) {
+        const smsq_batch_seq_t &q = seqs[i];
+        if (q.model < 0 || q.model >= n_models || q.n < 1 || q.T < 1 || !q.x0 || !q.z || !q.xmap_out ||
+            !q.logpost_out || (q.init_given != 0 && q.init_given != 1))
+            return SMSQ_ERR_INVALID;
+        const smsq_model_desc_t &d = models[q.model]->desc;
+        if (!batch_family(d.kind)) return SMSQ_ERR_UNSUPPORTED;
+        const MfmaLds L1(q.n, q.n), L2(q.n, 1);
+        if (L1.npad > kMaxParticles || L1.total > kLdsLimit - kBatchStaticLds ||
+            L2.total > kLdsLimit - kBatchStaticLds)
+            return SMSQ_ERR_UNSUPPORTED;
+        lds = std::max(lds, std::max(L1.total, L2.total));
+        T_max = std::max(T_max, q.T);
+        n_parts += (size_t)q.T * q.n * d.d;
+        n_phi += (size_t)q.T * q.n;
+        n_T += (size_t)q.T;
+    }
+    if (batch_kernel_attrs() != hipSuccess) return SMSQ_ERR_HIP;
+    smsq_batch_plan_s *p = new (std::nothrow) smsq_batch_plan_s;
+    if (!p) return SMSQ_ERR_HIP;
+    p->count = count;
+    p->T_max = T_max;
+    p->lds = (size_t)lds;
+    // per-step lists, longest processing time first (n^2 L, then sequence index)
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto cost = [&](int i) { return (double)seqs[i].n * seqs[i].n * opts[seqs[i].model].n_iter; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<int> lists;
+    lists.reserve(n_T);
+    p->list_off.resize(T_max);
+    p->list_cnt.resize(T_max);
+    for (int t = 1; t <= T_max; ++t) {
+        p->list_off[t - 1] = (int)lists.size();
+        for (int i : order)
+            if (seqs[i].T >= t) lists.push_back(i);
+        p->list_cnt[t - 1] = (int)lists.size() - p->list_off[t - 1];
+        p->max_active = std::max(p->max_active, p->list_cnt[t - 1]);
+    }
+    size_t total = 0;
+    hipError_t e = dev_alloc(&p->seqs, (size_t)count, total);
+    if (e == hipSuccess) e = dev_alloc(&p->lists, lists.size(), total);
+    if (e == hipSuccess) e = dev_alloc(&p->items, (size_t)p->max_active, total);
+    if (e == hipSuccess) e = dev_alloc(&p->codes, (size_t)p->max_active, total);
+    if (e == hipSuccess) e = dev_alloc(&p->counters, (size_t)T_max, total);
+    if (e == hipSuccess) e = dev_alloc(&p->status, (size_t)1, total);
+    if (e == hipSuccess) e = dev_alloc(&p->parts, n_parts, total);
+    if (e == hipSuccess) e = dev_alloc(&p->phis, n_phi, total);
+    if (e == hipSuccess) e = dev_alloc(&p->psis, n_phi, total);
+    if (e == hipSuccess) e = dev_alloc(&p->idx, n_T, total);
+    if (e != hipSuccess) {
+        p->free_all();
+        delete p;
+        return SMSQ_ERR_HIP;
+    }
+    p->device_bytes = total;
+    p->host.resize(count);
+    size_t o_parts = 0, o_phi = 0, o_T = 0;
+    for (int i = 0; i < count; ++i) {
+        const smsq_batch_seq_t &q = seqs[i];
+        const smsq_model_desc_t &d = models[q.model]->desc;
+        const smsq_svgd_opts_t &o = opts[q.model];
+        SeqDesc &sd = p->host[i];
+        std::memset(&sd, 0, sizeof(sd));
+        sd.m = make_dev_model<float>(d);
+        sd.x0 = (const float *)q.x0;
+        sd.z = (const float *)q.z;
+        sd.mask = q.z_mask;
+        sd.parts = p->parts + o_parts;
+        sd.phis = p->phis + o_phi;
+        sd.psis = p->psis + o_phi;
+        sd.idx = p->idx + o_T;
+        sd.xmap = (float *)q.xmap_out;
+        sd.logpost = (float *)q.logpost_out;
+        sd.n = q.n;
+        sd.T = q.T;
+        sd.d = d.d;
+        sd.code = d.kind;
+        sd.n_iter = o.n_iter;
+        sd.bw_mode = o.bw_mode;
+        sd.trans_mode = o.trans_mode;
+        sd.init_given = q.init_given;
+        sd.step = (float)o.step;
+        sd.bw_scale = (float)o.bw_scale;
+        sd.seed = q.seed;
+        o_parts += (size_t)q.T * q.n * d.d;
+        o_phi += (size_t)q.T * q.n;
+        o_T += (size_t)q.T;
+    }
+    e = hipMemcpy(p->seqs, p->host.data(), sizeof(SeqDesc) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->lists, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        p->free_all();
+        delete p;
+        return SMSQ_ERR_HIP;
+    }
+    *out = p;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t p, int steps, hipStream_t stream)
+{
+    if (!p || steps < 2) return SMSQ_ERR_INVALID;
+    const int k = std::min(steps, p->T_max);
+    if (k < 2) return SMSQ_OK;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SMSQ_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return SMSQ_ERR_HIP;
+    }
+    const int shapes[2] = {16, 8};
+    smsq_status_t st = SMSQ_OK;
+    for (int c = 0; c < 2 && st == SMSQ_OK; ++c) {
+        p->waves = shapes[c];
+        st = p->reset(stream);
+        if (st == SMSQ_OK) st = p->step(1, stream);
+        if (st != SMSQ_OK) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) { st = SMSQ_ERR_HIP; break; }
+        for (int t = 2; t <= k && st == SMSQ_OK; ++t) st = p->step(t, stream);
+        if (st != SMSQ_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = SMSQ_ERR_HIP;
+            break;
+        }
+        p->tuned[c] = ms / (k - 1);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != SMSQ_OK) return st;
+    p->waves = p->tuned[1] < p->tuned[0] ? 8 : 16;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_batch_run(smsq_batch_plan_t p, int use_graph, hipStream_t stream)
+{
+    if (!p) return SMSQ_ERR_INVALID;
+    if (!use_graph) return p->enqueue(stream);
+    if (stream == nullptr) return SMSQ_ERR_INVALID;
+    if (!p->exec || p->graph_waves != p->waves) {
+        if (p->exec) hipGraphExecDestroy(p->exec);
+        if (p->graph) hipGraphDestroy(p->graph);
+        p->exec = nullptr;
+        p->graph = nullptr;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SMSQ_ERR_HIP;
+        const smsq_status_t st = p->enqueue(stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(stream, &g);
+        if (st != SMSQ_OK || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return st != SMSQ_OK ? st : SMSQ_ERR_HIP;
+        }
+        p->graph = g;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            p->exec = nullptr;
+            return SMSQ_ERR_HIP;
+        }
+        p->graph_waves = p->waves;
+    }
+    return hipGraphLaunch(p->exec, stream) == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_batch_storage(smsq_batch_plan_t p, int seq, void **particles, void **phi, int32_t **psi)
+{
+    if (!p || seq < 0 || seq >= p->count) return SMSQ_ERR_INVALID;
+    if (particles) *particles = p->host[seq].parts;
+    if (phi) *phi = p->host[seq].phis;
+    if (psi) *psi = p->host[seq].psis;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_batch_plan_info(smsq_batch_plan_t p, smsq_batch_info_t *out)
+{
+    if (!p || !out) return SMSQ_ERR_INVALID;
+    out->count = p->count;
+    out->T_max = p->T_max;
+    out->waves = p->waves;
+    out->grid = p->grid();
+    out->lds_bytes = p->lds;
+    out->device_bytes = p->device_bytes;
+    out->tuned_ms[0] = p->tuned[0];
+    out->tuned_ms[1] = p->tuned[1];
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_batch_status(smsq_batch_plan_t p, smsq_status_t *out)
+{
+    if (!p || !out) return SMSQ_ERR_INVALID;
+    uint32_t v = 0;
+    if (hipMemcpy(&v, p->status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return SMSQ_ERR_HIP;
+    *out = (v & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_batch_plan_destroy(smsq_batch_plan_t p)
+{
+    if (!p) return SMSQ_ERR_INVALID;
+    p->free_all();
+    delete p;
+    return SMSQ_OK;
 }
 
 const char *smsq_status_string(smsq_status_t s)

@@ -74,7 +74,7 @@ __device__ __forceinline__ float group_max4(float v)
 constexpr int kMaxWaves = 16;
 constexpr int kTilesPerWave = 4;  // register blocking: 64 particles per wave task
 constexpr int kMaxParticles = 1024;  // largest sequence the kernel takes
-constexpr int kTaskSlots = kMaxParticles / 64 / kMaxWaves;  // tasks per wave at most
+// A workgroup of W waves takes up to W * TS tasks (TS task slots per wave).
 constexpr int kWaveScratch = 256; // floats of per-wave LDS scratch (one 16x16 tile)
 constexpr int kVtRows = 9;        // rows of the transition-mean table: 2 mh (7), 1, c'
 constexpr int kWinCap = 8192;     // capacity of the median window buffer (floats)
@@ -550,8 +550,10 @@ __device__ __forceinline__ void progress_priority(int step, int n)
     }
 }
 
-template <int KIND, int D>
-__global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
+// One sequence's time step (b: its index in the strided batch of `a`).  The
+// workgroup owns the sequence: all state in LDS, every barrier block-wide.
+template <int KIND, int D, int TS>
+__device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const int b)
 {
     using F = Family<float, KIND, D>;
     using R = RealOps<float>;
@@ -573,7 +575,6 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
     uint32_t *red = (uint32_t *)(smem + L.off_red);
     float *redf = (float *)(smem + L.off_red + 256);
 
-    const int b = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
     const int g = lane >> 4, col = lane & 15;
@@ -913,9 +914,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
         // (3) Stein direction
         const float twob = 2.f * beta;
         const float c2 = 2.f / h;
-        float phi[kTaskSlots][kTilesPerWave][2];  // kept in registers until every wave is done
+        float phi[TS][kTilesPerWave][2];  // kept in registers until every wave is done
 #pragma unroll
-        for (int ts = 0; ts < kTaskSlots; ++ts) {
+        for (int ts = 0; ts < TS; ++ts) {
             const int task = wave + ts * nwaves;
             if (task >= ntasks) break;
             const int ibase = task * 64;
@@ -1002,7 +1003,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
         __syncthreads();
         // synchronous update, then unscaled squared norms for the next median
 #pragma unroll
-        for (int ts = 0; ts < kTaskSlots; ++ts) {
+        for (int ts = 0; ts < TS; ++ts) {
             const int task = wave + ts * nwaves;
             if (task >= ntasks) break;
 #pragma unroll
@@ -1022,7 +1023,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int ts = 0; ts < kTaskSlots; ++ts) {
+        for (int ts = 0; ts < TS; ++ts) {
             const int task = wave + ts * nwaves;
             if (task >= ntasks) break;
             const int i = task * 64 + lane;
@@ -1086,6 +1087,12 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
         }
     }
     if (bad) atomicOr(a.status, STATUS_NONFINITE);
+}
+
+template <int KIND, int D>
+__global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
+{
+    step_mfma_body<KIND, D, kMaxParticles / 64 / kMaxWaves>(a, blockIdx.x);
 }
 
 } // namespace smsq

@@ -25,6 +25,8 @@ SYMBOLS = [
     "smsq_viterbi_step", "smsq_backtrack", "smsq_batch_step", "smsq_run_batch",
     "smsq_run_sequence", "smsq_get_device_status", "smsq_clear_device_status",
     "smsq_status_string", "smsq_max_particles",
+    "smsq_batch_plan_create", "smsq_batch_plan_tune", "smsq_batch_run", "smsq_batch_storage",
+    "smsq_batch_plan_info", "smsq_batch_status", "smsq_batch_plan_destroy",
 ]
 
 
@@ -37,6 +39,17 @@ class SmsqError(RuntimeError):
 class ModelDesc(C.Structure):
     _fields_ = [("kind", C.c_int), ("d", C.c_int), ("obs_dim", C.c_int), ("n_obs", C.c_int),
                 ("q_var", C.c_double * 8), ("params", C.c_double * 64)]
+
+
+class BatchSeq(C.Structure):
+    _fields_ = [("model", C.c_int), ("n", C.c_int), ("T", C.c_int), ("init_given", C.c_int),
+                ("seed", C.c_uint64), ("x0", C.c_void_p), ("z", C.c_void_p), ("z_mask", C.c_void_p),
+                ("xmap_out", C.c_void_p), ("logpost_out", C.c_void_p)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("count", C.c_int), ("T_max", C.c_int), ("waves", C.c_int), ("grid", C.c_int),
+                ("lds_bytes", C.c_size_t), ("device_bytes", C.c_size_t), ("tuned_ms", C.c_double * 2)]
 
 
 class SvgdOpts(C.Structure):
@@ -77,6 +90,14 @@ def load(path: str = LIB_PATH):
     L.smsq_status_string.argtypes = [C.c_int]
     L.smsq_status_string.restype = C.c_char_p
     L.smsq_max_particles.argtypes = [vp, i32]
+    L.smsq_batch_plan_create.argtypes = [C.POINTER(vp), C.POINTER(SvgdOpts), i32, C.POINTER(BatchSeq), i32,
+                                         C.POINTER(vp)]
+    L.smsq_batch_plan_tune.argtypes = [vp, i32, vp]
+    L.smsq_batch_run.argtypes = [vp, i32, vp]
+    L.smsq_batch_storage.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+    L.smsq_batch_plan_info.argtypes = [vp, C.POINTER(BatchInfo)]
+    L.smsq_batch_status.argtypes = [vp, C.POINTER(C.c_int)]
+    L.smsq_batch_plan_destroy.argtypes = [vp]
     for name in SYMBOLS:
         fn = getattr(L, name)
         if fn.restype is None or fn.restype is C.c_int:
@@ -351,3 +372,109 @@ def run_sequence(model: Model, dtype, x0: torch.Tensor, z: torch.Tensor, z_mask:
                                   ws.numel(), _stream(stream))
     _check(st, "smsq_run_sequence")
     return xmap, J
+
+
+class BatchPlan:
+    """Batched ragged plan (smsq_batch_plan_*): independent FP32 sequences of
+    different model family, n and T, one persistent launch per time step.
+
+    models: list of Model; opts: list of SvgdOpts (one per model);
+    seqs: list of dicts with keys model, n, x0 [d], z [T, obs_dim], z_mask
+    ([T, n_obs] uint8 or None), seed, init_given (optional, default 0).
+    The plan allocates xmap [T+1, d] and J [1] per sequence (``xmap``, ``J``).
+    """
+
+    def __init__(self, models, opts_list, seqs):
+        L = load()
+        self.models = models
+        self.opts = (SvgdOpts * len(opts_list))(*opts_list)
+        self._keep = []
+        self.xmap, self.J = [], []
+        arr = (BatchSeq * len(seqs))()
+        for i, q in enumerate(seqs):
+            k = int(q["model"])
+            d = models[k].d if 0 <= k < len(models) else 1  # a bad index is the C ABI's to reject
+            z = q["z"]
+            T = z.shape[0]
+            x0 = q["x0"]
+            xm = torch.empty((T + 1, d), dtype=torch.float32, device=x0.device)
+            J = torch.empty(1, dtype=torch.float32, device=x0.device)
+            self.xmap.append(xm)
+            self.J.append(J)
+            mask = q.get("z_mask")
+            self._keep += [x0, z, mask]
+            arr[i] = BatchSeq(k, int(q["n"]), int(T), int(q.get("init_given", 0)), int(q["seed"]),
+                              _ptr(x0, torch.float32, "x0"), _ptr(z, torch.float32, "z"),
+                              _ptr(mask, torch.uint8, "z_mask"), _ptr(xm), _ptr(J))
+        handles = (C.c_void_p * len(models))(*[m.handle for m in models])
+        h = C.c_void_p()
+        _check(L.smsq_batch_plan_create(handles, self.opts, len(models), arr, len(seqs), C.byref(h)),
+               "smsq_batch_plan_create")
+        self.handle = h
+        self.count = len(seqs)
+        self.seqs = seqs
+
+    def tune(self, steps: int = 3, stream=None):
+        _check(load().smsq_batch_plan_tune(self.handle, int(steps), _stream(stream)), "smsq_batch_plan_tune")
+        return self.info()
+
+    def run(self, use_graph: bool = False, stream=None):
+        _check(load().smsq_batch_run(self.handle, 1 if use_graph else 0, _stream(stream)), "smsq_batch_run")
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(load().smsq_batch_plan_info(self.handle, C.byref(i)), "smsq_batch_plan_info")
+        return {"count": i.count, "T_max": i.T_max, "waves": i.waves, "grid": i.grid,
+                "lds_bytes": i.lds_bytes, "device_bytes": i.device_bytes, "tuned_ms": list(i.tuned_ms)}
+
+    def status(self) -> int:
+        out = C.c_int(0)
+        _check(load().smsq_batch_status(self.handle, C.byref(out)), "smsq_batch_status")
+        return out.value
+
+    def storage(self, seq: int):
+        """Views of sequence seq's particles [T, n, d], phi [T, n] and psi [T, n]."""
+        pp, ph, ps = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        _check(load().smsq_batch_storage(self.handle, seq, C.byref(pp), C.byref(ph), C.byref(ps)),
+               "smsq_batch_storage")
+        q = self.seqs[seq]
+        T, n, d = q["z"].shape[0], int(q["n"]), self.models[q["model"]].d
+        dev = q["x0"].device
+        return (_wrap(pp.value, (T, n, d), torch.float32, dev), _wrap(ph.value, (T, n), torch.float32, dev),
+                _wrap(ps.value, (T, n), torch.int32, dev))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().smsq_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _wrap(ptr: int, shape, dtype, device) -> torch.Tensor:
+    """A tensor copy of device memory owned by the library (copied with a
+    device-to-device copy so that torch owns the result)."""
+    n = int(np.prod(shape))
+    out = torch.empty(shape, dtype=dtype, device=device)
+    nbytes = n * out.element_size()
+    torch.cuda.synchronize()
+    err = _hip().hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), C.c_size_t(nbytes), 3)
+    if err != 0:
+        raise RuntimeError("hipMemcpy failed (%d)" % err)
+    return out
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = C.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip_lib.hipMemcpy.restype = C.c_int
+    return _hip_lib

@@ -1,0 +1,145 @@
+"""Batched ragged form (smsq_batch_plan_*): sequences of different model
+family, particle count and length advance one time step per persistent
+launch.  Every sequence's result must match the single-sequence path
+(smsq_run_sequence, same model, n, T, seed and options): the batched launch
+runs the same step body per sequence, and neither the exact median, the
+per-task sums nor the forward recursion depends on which workgroup shape
+took the step.  The body is compiled into a different kernel, where the
+compiler may contract a few multiply-adds differently, so particles agree to
+a few FP32 ulps (measured up to 1e-7 of the particle scale after 9 steps),
+not bit for bit; the bound below is a hundred times that.  hipGraph replays must reproduce the
+eager run bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2312_08684_amd import scenarios as S
+from paper_2312_08684_amd import smsq
+
+pytestmark = pytest.mark.gpu
+
+# (family, n, T, L): ragged in every dimension; n spans one to sixteen
+# 64-particle tasks, with ragged tails
+MIX = [
+    ("arm7", 1024, 4, 12),
+    ("cv4d", 512, 6, 10),
+    ("range2d", 256, 9, 10),
+    ("growth1d", 32, 7, 20),
+    ("arm7", 200, 5, 12),
+    ("range2d", 100, 3, 10),
+    ("cv4d", 96, 8, 10),
+    ("growth1d", 64, 2, 20),
+    ("arm7", 64, 6, 12),
+]
+
+
+def _build(mix, base_seed=0):
+    models, opts, seqs = [], [], []
+    for i, (name, n, T, L) in enumerate(mix):
+        wl = S.make_workload(name, B=1, seed=base_seed + i, n=n, T=T, n_iter=L)
+        models.append(smsq.Model(wl.model))
+        opts.append(smsq.opts_from(wl.opts))
+        seqs.append({
+            "model": i, "n": n, "seed": 1000 + i,
+            "x0": torch.tensor(wl.x0[0], dtype=torch.float32, device="cuda"),
+            "z": torch.tensor(wl.z[0], dtype=torch.float32, device="cuda"),
+            "z_mask": (torch.tensor(wl.mask[0], dtype=torch.uint8, device="cuda")
+                       if wl.mask is not None else None),
+        })
+    return models, opts, seqs
+
+
+def _single(models, opts, q):
+    m = models[q["model"]]
+    T = q["z"].shape[0]
+    parts = torch.empty((T, q["n"], m.d), dtype=torch.float32, device="cuda")
+    xmap, J = smsq.run_sequence(m, "f32", q["x0"], q["z"], q["z_mask"], q["n"], opts[q["model"]], q["seed"],
+                                particles=parts)
+    torch.cuda.synchronize()
+    return xmap, J, parts
+
+
+REL = 1e-5
+
+
+def _check_equal(plan, models, opts, seqs):
+    for i, q in enumerate(seqs):
+        xmap, J, parts = _single(models, opts, q)
+        p_parts, _, _ = plan.storage(i)
+        a, b = p_parts.cpu().double().numpy(), parts.cpu().double().numpy()
+        scale = max(1.0, np.abs(b).max())
+        err = np.abs(a - b).max() / scale
+        print("sequence %d %s: particles rel err %.2e, J %.7g vs %.7g" % (i, MIX[i] if i < len(MIX) else "",
+              err, plan.J[i].item(), J.item()), flush=True)
+        assert err <= REL, "sequence %d particles differ: %.3e" % (i, err)
+        xa, xb = plan.xmap[i].cpu().double().numpy(), xmap.cpu().double().numpy()
+        assert np.abs(xa - xb).max() <= REL * max(1.0, np.abs(xb).max()), "sequence %d MAP path" % i
+        assert abs(plan.J[i].item() - J.item()) <= REL * max(1.0, abs(J.item())), "sequence %d J" % i
+
+
+def test_batch_matches_single_sequences_16_waves():
+    models, opts, seqs = _build(MIX)
+    plan = smsq.BatchPlan(models, opts, seqs)
+    info = plan.info()
+    assert info["waves"] == 16 and info["T_max"] == 9 and info["count"] == len(MIX)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == smsq.OK
+    _check_equal(plan, models, opts, seqs)
+    for J in plan.J:
+        assert np.isfinite(J.item())
+
+
+def test_batch_autotuner_and_8_wave_shape():
+    models, opts, seqs = _build(MIX, base_seed=50)
+    plan = smsq.BatchPlan(models, opts, seqs)
+    info = plan.tune(steps=3)
+    print("autotuner", info, flush=True)
+    assert info["tuned_ms"][0] > 0 and info["tuned_ms"][1] > 0
+    assert info["waves"] == (8 if info["tuned_ms"][1] < info["tuned_ms"][0] else 16)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == smsq.OK
+    _check_equal(plan, models, opts, seqs)
+
+
+def test_batch_graph_replays_match_eager():
+    models, opts, seqs = _build(MIX[:6], base_seed=80)
+    plan = smsq.BatchPlan(models, opts, seqs)
+    plan.run()
+    torch.cuda.synchronize()
+    ref = [(x.clone(), J.clone()) for x, J in zip(plan.xmap, plan.J)]
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        for x, J in zip(plan.xmap, plan.J):
+            x.fill_(float("nan"))
+            J.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            plan.run(use_graph=True, stream=s)
+        s.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert np.isfinite(junk.item())
+        for i, (x, J) in enumerate(zip(plan.xmap, plan.J)):
+            assert torch.equal(x, ref[i][0]), "replay %d sequence %d" % (rep, i)
+            assert torch.equal(J, ref[i][1]), "replay %d sequence %d" % (rep, i)
+        assert plan.status() == smsq.OK
+
+
+def test_batch_plan_argument_errors():
+    models, opts, seqs = _build(MIX[:2])
+    bad = [dict(seqs[0], model=5)]
+    with pytest.raises(smsq.SmsqError):
+        smsq.BatchPlan(models, opts, bad)
+    big = [dict(seqs[0], n=1025)]
+    with pytest.raises(smsq.SmsqError):
+        smsq.BatchPlan(models, opts, big)
+    wl = S.make_workload("lingauss", B=1, seed=0, T=3)
+    lg = [smsq.Model(wl.model)]
+    q = {"model": 0, "n": 32, "seed": 1, "x0": torch.zeros(wl.model.d, device="cuda"),
+         "z": torch.zeros((3, wl.model.obs_dim), device="cuda"), "z_mask": None}
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.BatchPlan(lg, [smsq.opts_from(wl.opts)], [q])
+    assert e.value.status == smsq.ERR_UNSUPPORTED

@@ -1,0 +1,113 @@
+"""Pins of the learned-proposal oracle (oracle/init_mlp.py), CPU only.
+
+Backpropagation is checked against central finite differences of the
+forward pass, the mixture NLL gradient against finite differences of the
+NLL, the NLL of a mixture of identical components against scipy's normal
+log-density, the bfloat16 rounding against hand-worked ties, and the
+features of a set of identical particles against their closed form."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+from oracle import init_mlp as M
+from paper_2312_08684_amd import scenarios as S
+
+
+def _params(rng, scale=0.2):
+    P = rng.normal(scale=scale, size=M.N_PARAMS)
+    return P
+
+
+def test_bf16_rounding_ties_to_even():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.0 - 2 ** -8, -2.0 - 2 ** -7 - 2 ** -9, 0.0])
+    r = M.bf16_round(x)
+    # spacing 2^-7 on [1, 2), 2^-6 on [2, 4).  Halfway 1 + 2^-8 -> even mantissa
+    # 1.0; 1 + 1.5 * 2^-7 (halfway) -> 1 + 2^-6; -2 - 2^-8 is below the halfway
+    # point -2 - 2^-7 -> -2; -2 - 2^-7 - 2^-9 is above it -> -2 - 2^-6
+    assert list(r) == [1.0, 1.0, 1.0 + 2 ** -6, -2.0, -2.0 - 2 ** -6, 0.0]
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    P = _params(rng)
+    F = rng.normal(size=(5, M.FEAT))
+    dout = rng.normal(size=(5, M.OUT))
+    out, cache = M.forward(P, F, bf16=False)
+    G = M.backward(cache, dout, bf16=False)
+
+    def f(Pv):
+        return float((M.forward(Pv, F, bf16=False)[0] * dout).sum())
+
+    idx = np.concatenate([rng.choice(np.arange(M.OFF_W1, M.OFF_B1), 8), rng.choice(np.arange(M.OFF_B1, M.OFF_W2), 4),
+                          rng.choice(np.arange(M.OFF_W2, M.OFF_B2), 8), rng.choice(np.arange(M.OFF_B2, M.OFF_W3), 4),
+                          rng.choice(np.arange(M.OFF_W3, M.OFF_B3), 8), rng.choice(np.arange(M.OFF_B3, M.N_PARAMS), 4)])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(P)
+        e[i] = h
+        fd = (f(P + e) - f(P - e)) / (2 * h)
+        assert abs(fd - G[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, G[i])
+
+
+def test_mixture_nll_gradient_matches_finite_differences():
+    rng = np.random.default_rng(5)
+    d = 3
+    out = rng.normal(scale=0.5, size=M.OUT)
+    out[8 + 1] = -9.0          # one log-scale below the clamp: zero gradient
+    a = np.zeros(8)
+    a[:d] = rng.normal(size=d)
+    s = np.ones(8)
+    s[:d] = [0.5, 1.0, 2.0]
+    X = a[:d] + rng.normal(size=(20, d))
+    loss, g = M.mixture_nll(out, a, s, X)
+    h = 1e-6
+    for i in range(M.OUT):
+        c, q = divmod(i, M.COMP)
+        if (1 + d <= q < 8) or q >= 8 + d:
+            assert g[i] == 0.0
+            continue
+        e = np.zeros_like(out)
+        e[i] = h
+        fd = (M.mixture_nll(out + e, a, s, X)[0] - M.mixture_nll(out - e, a, s, X)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+    assert g[8 + 1] == 0.0
+
+
+def test_identical_components_reduce_to_one_gaussian():
+    rng = np.random.default_rng(7)
+    mu, rho, s = 0.3, -0.4, 1.7
+    out = np.zeros(M.OUT)
+    for c in range(M.K):
+        out[c * M.COMP + 0] = rng.normal()      # any weights: the components coincide
+        out[c * M.COMP + 1] = mu
+        out[c * M.COMP + 8] = rho
+    a = np.zeros(8)
+    a[0] = 2.0
+    sv = np.ones(8)
+    sv[0] = s
+    X = rng.normal(size=(50, 1))
+    loss, _ = M.mixture_nll(out, a, sv, X)
+    ref = -stats.norm.logpdf(X[:, 0], loc=2.0 + s * mu, scale=s * np.exp(rho)).mean()
+    assert abs(loss - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_features_of_identical_particles():
+    wl = S.make_workload("arm7", B=1, seed=0, T=3)
+    desc = wl.model
+    d = desc.d
+    x = np.tile(wl.truth[0, 1], (6, 1))
+    phi = np.array([0.0, 2.0, 1.0, 2.0, -1.0, 0.5])   # first maximum at index 1
+    F, a, s = M.features(desc, 2, x, phi, wl.z[0, 1], None, 128)
+    a_ref = O.transition_mean(desc, 2, x[1])
+    sq = np.sqrt(np.asarray(desc.q_var[:d]))
+    assert F[3] == 1.0 and F[:3].sum() == 0.0
+    assert F[4] == pytest.approx(np.log(128) / 7.0, abs=1e-15)
+    assert np.allclose(F[5:5 + d], 0.0, atol=1e-12)
+    assert np.allclose(F[12:12 + d], np.log(1e-6) / 8.0, atol=1e-9)
+    assert np.allclose(F[19:19 + d], a_ref * 0.5, atol=0)
+    g = O.grad_loglik(desc, wl.z[0, 1], None, a_ref)
+    assert np.allclose(F[26:26 + d], np.arcsinh(sq * g) / 4.0, atol=0)
+    assert np.allclose(a[:d], a_ref, atol=0) and np.all(a[d:] == 0)
+    assert np.allclose(s[:d], sq, atol=0)
+    assert np.all(F[34:] == 0.0)

@@ -298,6 +298,90 @@ smsq_status_t smsq_batch_plan_info(smsq_batch_plan_t plan, smsq_batch_info_t *ou
 smsq_status_t smsq_batch_status(smsq_batch_plan_t plan, smsq_status_t *out);
 smsq_status_t smsq_batch_plan_destroy(smsq_batch_plan_t plan);
 
+/* ---- Learned initial particles (proposal network) ------------------------
+ * A small MLP (64 -> 256 -> 256 -> 120, ReLU) maps features of a sequence
+ * step (summary of the previous particle set around its best particle, the
+ * likelihood gradient of the new observation there) to an 8-component
+ * diagonal Gaussian mixture over the step's state, from which the initial
+ * particles are drawn.  It is trained on particle sets the method itself
+ * converged to, by the mixture negative log-likelihood.  GEMMs use BF16
+ * operands with FP32 accumulation; parameters and Adam state are FP32.
+ * Families GROWTH1D, RANGE2D, CV4D, ARM7; d <= 7.
+ *
+ * Parameters: one FP32 array of 113,272 values, W1 [256][64], b1 [256],
+ * W2 [256][256], b2 [256], W3 [120][256], b3 [120].  Outputs per example:
+ * component c (0..7) has the logit out[15c], mean offsets out[15c+1+k] and
+ * log-scales out[15c+8+k] (clamped to [-7, 3]) for dimensions k < d: mean
+ * a_k + s_k mu, standard deviation s_k exp(rho), with a the transition mean
+ * of the best previous particle and s = sqrt(q). */
+typedef struct smsq_init_mlp_s *smsq_init_mlp_t;
+typedef struct smsq_init_set_s *smsq_init_set_t;
+
+typedef struct {
+    int model;              /* index into the models array */
+    int t;                  /* step of the proposed particles (>= 2) */
+    int n;                  /* particles of the step */
+    int n_prev;             /* particles of step t - 1 */
+    const void *x_prev;     /* [n_prev][d] FP32 particles of step t - 1 */
+    const void *phi_prev;   /* [n_prev] FP32 forward-recursion scores of step t - 1 */
+    const void *z;          /* [obs_dim] FP32 observation of step t */
+    const uint8_t *z_mask;  /* [n_obs] or NULL */
+    void *particles;        /* [n][d] FP32: converged particles (training) or the
+                               proposal's samples (sampling, written) */
+    uint64_t seed;          /* Philox key of the sampler */
+    int seq;                /* Philox counter word 2 of the sampler */
+} smsq_init_example_t;
+
+/* Network with He-initialised weights (Philox normals keyed by seed) and
+ * zero biases; buffers for batches of up to max_batch examples.  (host) */
+smsq_status_t smsq_init_mlp_create(uint64_t seed, int max_batch, smsq_init_mlp_t *out);
+smsq_status_t smsq_init_mlp_destroy(smsq_init_mlp_t mlp);
+/* Device pointers of the FP32 parameters and of their gradient buffer
+ * (written by smsq_init_mlp_backward / _train_step); count = 113,272. */
+smsq_status_t smsq_init_mlp_params(smsq_init_mlp_t mlp, float **params, float **grads, size_t *count);
+/* After the caller wrote the parameters (e.g. loaded them): refresh the BF16
+ * weight copies and reset the Adam state. */
+smsq_status_t smsq_init_mlp_sync(smsq_init_mlp_t mlp, hipStream_t stream);
+
+/* A set of examples (host array of device pointers, copied). (host) */
+smsq_status_t smsq_init_set_create(const smsq_model_t *models, int n_models, const smsq_init_example_t *ex,
+                                   int count, smsq_init_set_t *out);
+smsq_status_t smsq_init_set_destroy(smsq_init_set_t set);
+
+/* Features of examples [first, first + count) into features [count][64]
+ * (FP32) and anchors / scales [count][8] (a, s; NULL allowed). */
+smsq_status_t smsq_init_features(smsq_init_mlp_t mlp, smsq_init_set_t set, int first, int count,
+                                 void *features, void *anchors, void *scales, hipStream_t stream);
+/* out [batch][120] = MLP(features [batch][64]), BF16 operands. */
+smsq_status_t smsq_init_mlp_forward(smsq_init_mlp_t mlp, int batch, const void *features, void *out,
+                                    hipStream_t stream);
+/* Gradient buffer = d(sum_e <dout_e, out_e>)/d(parameters) at the last
+ * forward of the same batch (call smsq_init_mlp_forward first). */
+smsq_status_t smsq_init_mlp_backward(smsq_init_mlp_t mlp, int batch, const void *dout, hipStream_t stream);
+/* Mixture NLL (mean over each example's particles) of examples [first,
+ * first + count) under outputs out [count][120]: loss [count], and
+ * dout [count][120] = gscale * d loss_e / d out_e. */
+smsq_status_t smsq_init_mixture_nll(smsq_init_set_t set, int first, int count, const void *out,
+                                    const void *anchors, const void *scales, double gscale, void *loss,
+                                    void *dout, hipStream_t stream);
+/* One Adam step (lr; beta 0.9, 0.999; eps 1e-8) on the mean NLL over
+ * examples [first, first + count): features, forward, loss, backward,
+ * update.  loss_out [1] (device, FP32) receives the mean loss, or NULL. */
+smsq_status_t smsq_init_mlp_train_step(smsq_init_mlp_t mlp, smsq_init_set_t set, int first, int count,
+                                       double lr, void *loss_out, hipStream_t stream);
+/* Draws each example's n particles from its proposal into `particles`;
+ * used [count] (device, int32, or NULL) is 1 where the outputs were finite
+ * and the samples written, 0 where nothing was written. */
+smsq_status_t smsq_init_mlp_sample(smsq_init_mlp_t mlp, smsq_init_set_t set, int first, int count,
+                                   int32_t *used, hipStream_t stream);
+
+/* Batched plans: initial particles of steps t >= 2 from the proposal (NULL:
+ * the predictive initialisation).  Per step the plan then also runs the
+ * features, the forward pass and the sampler; a sequence whose proposal is
+ * not finite falls back to the predictive initialisation for that step.
+ * max_batch of the network must cover the plan's sequences. (host) */
+smsq_status_t smsq_batch_plan_set_init(smsq_batch_plan_t plan, smsq_init_mlp_t mlp);
+
 /* Reads the workspace status word (synchronous device-to-host copy; call
  * after the work has been synchronised).  *out is SMSQ_OK or
  * SMSQ_ERR_NONFINITE. */

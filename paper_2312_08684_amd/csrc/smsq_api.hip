@@ -15,6 +15,7 @@
 #include "smsq_kernels.hpp"
 #include "smsq_mfma.hpp"
 #include "smsq_batch.hpp"
+#include "smsq_init.hpp"
 
 #include <cstdlib>
 
@@ -354,8 +355,101 @@ template <typename P> hipError_t dev_alloc(P **p, size_t count, size_t &total)
 
 } // namespace
 
+struct smsq_init_mlp_s {
+    int max_batch = 0, adam_t = 0;
+    float *P = nullptr, *G = nullptr, *Mo = nullptr, *Ve = nullptr;
+    uint16_t *w1b = nullptr, *w2b = nullptr, *w3b = nullptr;
+    float *F = nullptr, *anc = nullptr, *scl = nullptr;
+    uint16_t *Fb = nullptr;
+    float *pre1 = nullptr, *pre2 = nullptr, *out = nullptr, *dout = nullptr, *d2 = nullptr, *d1 = nullptr;
+    uint16_t *h1 = nullptr, *h2 = nullptr, *doutb = nullptr, *d2b = nullptr, *d1b = nullptr;
+    float *lossv = nullptr;
+    size_t bytes = 0;
+    void free_all()
+    {
+        void *ps[] = {P, G, Mo, Ve, w1b, w2b, w3b, F, anc, scl, Fb, pre1, pre2, out, dout, d2, d1,
+                      h1, h2, doutb, d2b, d1b, lossv};
+        for (void *q : ps)
+            if (q) hipFree(q);
+    }
+};
+
+struct smsq_init_set_s {
+    int count = 0, max_n = 0;
+    InitExample *ex = nullptr;
+};
+
+namespace {
+
+hipError_t zero_alloc_bytes(void **p, size_t bytes, size_t &total)
+{
+    *p = nullptr;
+    bytes = align256(bytes);
+    total += bytes;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) e = hipMemset(*p, 0, bytes);  // at creation, never inside a captured run
+    return e;
+}
+
+void gemm(int M, int N, int K, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn,
+          float *C, long ldc, uint16_t *Cb, long ldcb, const float *bias, const float *pre, long ldpre, int mode,
+          hipStream_t s)
+{
+    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((tiles + 3) / 4), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C,
+                       ldc, Cb, ldcb, bias, pre, ldpre, mode);
+}
+
+// forward on mlp->Fb (batch rows) into mlp->out
+void mlp_forward(smsq_init_mlp_s *m, int B, hipStream_t s)
+{
+    const int H = kInitHidden;
+    gemm(B, H, kInitFeat, m->Fb, kInitFeat, 1, m->w1b, 1, kInitFeat, m->pre1, H, m->h1, H, m->P + kOffB1, nullptr,
+         0, 0, s);
+    gemm(B, H, H, m->h1, H, 1, m->w2b, 1, H, m->pre2, H, m->h2, H, m->P + kOffB2, nullptr, 0, 0, s);
+    gemm(B, kInitOut, H, m->h2, H, 1, m->w3b, 1, H, m->out, kInitOut, nullptr, 0, m->P + kOffB3, nullptr, 0, 1, s);
+}
+
+// gradients of sum_e <dout_e, out_e> into mlp->G (dout in mlp->dout)
+void mlp_backward(smsq_init_mlp_s *m, int B, hipStream_t s)
+{
+    const int H = kInitHidden, O = kInitOut;
+    hipLaunchKernelGGL(k_to_bf16, dim3((B * O + 255) / 256), dim3(256), 0, s, m->dout, m->doutb, (long)B * O);
+    // W3, b3
+    gemm(O, H, B, m->doutb, 1, O, m->h2, H, 1, m->G + kOffW3, H, nullptr, 0, nullptr, nullptr, 0, 3, s);
+    hipLaunchKernelGGL(k_colsum, dim3((O + 63) / 64), dim3(64), 0, s, B, O, m->dout, (long)O, m->G + kOffB3);
+    // through layer 3 and the second ReLU
+    gemm(B, H, O, m->doutb, O, 1, m->w3b, H, 1, m->d2, H, m->d2b, H, nullptr, m->pre2, H, 2, s);
+    gemm(H, H, B, m->d2b, 1, H, m->h1, H, 1, m->G + kOffW2, H, nullptr, 0, nullptr, nullptr, 0, 3, s);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(64), 0, s, B, H, m->d2, (long)H, m->G + kOffB2);
+    // through layer 2 and the first ReLU
+    gemm(B, H, H, m->d2b, H, 1, m->w2b, H, 1, m->d1, H, m->d1b, H, nullptr, m->pre1, H, 2, s);
+    gemm(H, kInitFeat, B, m->d1b, 1, H, m->Fb, kInitFeat, 1, m->G + kOffW1, kInitFeat, nullptr, 0, nullptr, nullptr,
+         0, 3, s);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(64), 0, s, B, H, m->d1, (long)H, m->G + kOffB1);
+}
+
+void mlp_features(smsq_init_mlp_s *m, const InitExample *ex, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_features, dim3(count), dim3(kWave), 0, s, ex, count, m->F, m->Fb, m->anc, m->scl);
+}
+
+// features, forward and sampler for examples ex[0..count)
+smsq_status_t init_propose(smsq_init_mlp_s *m, const InitExample *ex, int count, int max_n, int32_t *used,
+                           hipStream_t s)
+{
+    if (count > m->max_batch) return SMSQ_ERR_INVALID;
+    mlp_features(m, ex, count, s);
+    mlp_forward(m, count, s);
+    hipLaunchKernelGGL(k_mix_sample, dim3((max_n + 255) / 256, count), dim3(256), 0, s, ex, count, m->out, m->anc,
+                       m->scl, used);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+} // namespace
+
 struct smsq_batch_plan_s {
-    int count = 0, T_max = 0, max_active = 0;
+    int count = 0, T_max = 0, max_active = 0, max_n = 0;
     std::vector<int> list_off, list_cnt;  // per step t - 1
     std::vector<SeqDesc> host;            // per sequence
     SeqDesc *seqs = nullptr;
@@ -371,6 +465,10 @@ struct smsq_batch_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_waves = 0;
+    smsq_init_mlp_s *mlp = nullptr;       // learned initial particles (null: predictive)
+    InitExample *init_ex = nullptr;       // [max_active]
+    int32_t *init_used = nullptr;         // [max_active]
+    const smsq_init_mlp_s *graph_mlp = nullptr;
 
     int grid() const
     {
@@ -387,7 +485,7 @@ struct smsq_batch_plan_s {
         if (graph) hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
-        void *ps[] = {seqs, lists, items, codes, counters, status, parts, phis, psis, idx};
+        void *ps[] = {seqs, lists, items, codes, counters, status, parts, phis, psis, idx, init_ex, init_used};
         for (void *q : ps)
             if (q) hipFree(q);
     }
@@ -398,6 +496,13 @@ struct smsq_batch_plan_s {
         if (cnt == 0) return SMSQ_OK;
         hipLaunchKernelGGL(k_batch_prep, dim3((cnt + 63) / 64), dim3(64), 0, s, seqs, lists + list_off[t - 1], cnt,
                            t, items, codes, status);
+        if (mlp && t >= 2) {
+            hipLaunchKernelGGL(k_init_prep, dim3((cnt + 63) / 64), dim3(64), 0, s, seqs, lists + list_off[t - 1],
+                               cnt, t, init_ex);
+            const smsq_status_t st = init_propose(mlp, init_ex, cnt, max_n, init_used, s);
+            if (st != SMSQ_OK) return st;
+            hipLaunchKernelGGL(k_init_apply, dim3((cnt + 63) / 64), dim3(64), 0, s, items, init_used, cnt);
+        }
         const int g = std::min(grid(), cnt);
         if (waves == 16)
             hipLaunchKernelGGL(k_batch_step_w16, dim3(g), dim3(16 * kWave), lds, s, items, codes, cnt,
@@ -633,7 +738,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     for (int k = 0; k < n_models; ++k)
         if (!models[k] || !opts_ok(&opts[k])) return SMSQ_ERR_INVALID;
     long lds = 0;
-    int T_max = 0;
+    int T_max = 0, max_n = 0;
     size_t n_parts = 0, n_phi = 0, n_T = 0;
     for (int i = 0; i < count; ++i) {
         const smsq_batch_seq_t &q = seqs[i];
@@ -647,6 +752,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
             L2.total > kLdsLimit - kBatchStaticLds)
             return SMSQ_ERR_UNSUPPORTED;
         lds = std::max(lds, std::max(L1.total, L2.total));
+        max_n = std::max(max_n, q.n);
         T_max = std::max(T_max, q.T);
         n_parts += (size_t)q.T * q.n * d.d;
         n_phi += (size_t)q.T * q.n;
@@ -657,6 +763,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     if (!p) return SMSQ_ERR_HIP;
     p->count = count;
     p->T_max = T_max;
+    p->max_n = max_n;
     p->lds = (size_t)lds;
     // per-step lists, longest processing time first (n^2 L, then sequence index)
     std::vector<int> order(count);
@@ -776,7 +883,7 @@ smsq_status_t smsq_batch_run(smsq_batch_plan_t p, int use_graph, hipStream_t str
     if (!p) return SMSQ_ERR_INVALID;
     if (!use_graph) return p->enqueue(stream);
     if (stream == nullptr) return SMSQ_ERR_INVALID;
-    if (!p->exec || p->graph_waves != p->waves) {
+    if (!p->exec || p->graph_waves != p->waves || p->graph_mlp != p->mlp) {
         if (p->exec) hipGraphExecDestroy(p->exec);
         if (p->graph) hipGraphDestroy(p->graph);
         p->exec = nullptr;
@@ -795,6 +902,7 @@ smsq_status_t smsq_batch_run(smsq_batch_plan_t p, int use_graph, hipStream_t str
             return SMSQ_ERR_HIP;
         }
         p->graph_waves = p->waves;
+        p->graph_mlp = p->mlp;
     }
     return hipGraphLaunch(p->exec, stream) == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
@@ -836,6 +944,227 @@ smsq_status_t smsq_batch_plan_destroy(smsq_batch_plan_t p)
     if (!p) return SMSQ_ERR_INVALID;
     p->free_all();
     delete p;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_init_mlp_create(uint64_t seed, int max_batch, smsq_init_mlp_t *out)
+{
+    if (!out) return SMSQ_ERR_INVALID;
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > (1 << 20)) return SMSQ_ERR_INVALID;
+    smsq_init_mlp_s *m = new (std::nothrow) smsq_init_mlp_s;
+    if (!m) return SMSQ_ERR_HIP;
+    m->max_batch = max_batch;
+    const size_t B = (size_t)max_batch, H = kInitHidden;
+    size_t t = 0;
+    hipError_t e = zero_alloc_bytes((void **)&m->P, kInitParams * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->G, kInitParams * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->Mo, kInitParams * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->Ve, kInitParams * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->w1b, H * kInitFeat * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->w2b, H * H * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->w3b, kInitOutPad * H * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->F, B * kInitFeat * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->Fb, B * kInitFeat * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->anc, B * 8 * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->scl, B * 8 * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->pre1, B * H * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->pre2, B * H * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->h1, B * H * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->h2, B * H * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->out, B * kInitOut * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->dout, B * kInitOut * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->doutb, B * kInitOut * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->d2, B * H * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->d1, B * H * 4, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->d2b, B * H * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->d1b, B * H * 2, t);
+    if (e == hipSuccess) e = zero_alloc_bytes((void **)&m->lossv, B * 4, t);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_init_he, dim3((kInitParams + 255) / 256), dim3(256), 0, nullptr, m->P, seed);
+        hipLaunchKernelGGL(k_init_weights_bf16, dim3((kInitParams + 255) / 256), dim3(256), 0, nullptr, m->P,
+                           m->w1b, m->w2b, m->w3b);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    if (e != hipSuccess) {
+        m->free_all();
+        delete m;
+        return SMSQ_ERR_HIP;
+    }
+    m->bytes = t;
+    *out = m;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_init_mlp_destroy(smsq_init_mlp_t m)
+{
+    if (!m) return SMSQ_ERR_INVALID;
+    m->free_all();
+    delete m;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_init_mlp_params(smsq_init_mlp_t m, float **params, float **grads, size_t *count)
+{
+    if (!m) return SMSQ_ERR_INVALID;
+    if (params) *params = m->P;
+    if (grads) *grads = m->G;
+    if (count) *count = (size_t)kInitParams;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_init_mlp_sync(smsq_init_mlp_t m, hipStream_t s)
+{
+    if (!m) return SMSQ_ERR_INVALID;
+    hipLaunchKernelGGL(k_init_weights_bf16, dim3((kInitParams + 255) / 256), dim3(256), 0, s, m->P, m->w1b, m->w2b,
+                       m->w3b);
+    hipLaunchKernelGGL(k_fill_f32, dim3((kInitParams + 255) / 256), dim3(256), 0, s, m->Mo, 0.f, kInitParams);
+    hipLaunchKernelGGL(k_fill_f32, dim3((kInitParams + 255) / 256), dim3(256), 0, s, m->Ve, 0.f, kInitParams);
+    m->adam_t = 0;
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_init_set_create(const smsq_model_t *models, int n_models, const smsq_init_example_t *ex,
+                                   int count, smsq_init_set_t *out)
+{
+    if (!out) return SMSQ_ERR_INVALID;
+    *out = nullptr;
+    if (!models || n_models < 1 || !ex || count < 1) return SMSQ_ERR_INVALID;
+    std::vector<InitExample> h(count);
+    int max_n = 0;
+    for (int i = 0; i < count; ++i) {
+        const smsq_init_example_t &q = ex[i];
+        if (q.model < 0 || q.model >= n_models || !models[q.model] || q.t < 2 || q.n < 1 || q.n_prev < 1 ||
+            !q.x_prev || !q.phi_prev || !q.z || !q.particles)
+            return SMSQ_ERR_INVALID;
+        const smsq_model_desc_t &d = models[q.model]->desc;
+        if (!batch_family(d.kind)) return SMSQ_ERR_UNSUPPORTED;
+        InitExample &x = h[i];
+        std::memset(&x, 0, sizeof(x));
+        x.m = make_dev_model<float>(d);
+        x.xprev = (const float *)q.x_prev;
+        x.phiprev = (const float *)q.phi_prev;
+        x.z = (const float *)q.z;
+        x.mask = q.z_mask;
+        x.target = (float *)q.particles;
+        x.np = q.n_prev;
+        x.n = q.n;
+        x.t = q.t;
+        x.code = d.kind;
+        x.seq = q.seq;
+        x.seed = q.seed;
+        max_n = std::max(max_n, q.n);
+    }
+    smsq_init_set_s *st = new (std::nothrow) smsq_init_set_s;
+    if (!st) return SMSQ_ERR_HIP;
+    st->count = count;
+    st->max_n = max_n;
+    if (hipMalloc((void **)&st->ex, sizeof(InitExample) * count) != hipSuccess ||
+        hipMemcpy(st->ex, h.data(), sizeof(InitExample) * count, hipMemcpyHostToDevice) != hipSuccess) {
+        if (st->ex) hipFree(st->ex);
+        delete st;
+        return SMSQ_ERR_HIP;
+    }
+    *out = st;
+    return SMSQ_OK;
+}
+
+smsq_status_t smsq_init_set_destroy(smsq_init_set_t st)
+{
+    if (!st) return SMSQ_ERR_INVALID;
+    if (st->ex) hipFree(st->ex);
+    delete st;
+    return SMSQ_OK;
+}
+
+namespace {
+bool range_ok(smsq_init_mlp_s *m, smsq_init_set_s *st, int first, int count)
+{
+    return m && st && first >= 0 && count >= 1 && first + count <= st->count && count <= m->max_batch;
+}
+} // namespace
+
+smsq_status_t smsq_init_features(smsq_init_mlp_t m, smsq_init_set_t st, int first, int count, void *features,
+                                 void *anchors, void *scales, hipStream_t s)
+{
+    if (!range_ok(m, st, first, count)) return SMSQ_ERR_INVALID;
+    mlp_features(m, st->ex + first, count, s);
+    if (features && hipMemcpyAsync(features, m->F, (size_t)count * kInitFeat * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    if (anchors && hipMemcpyAsync(anchors, m->anc, (size_t)count * 8 * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    if (scales && hipMemcpyAsync(scales, m->scl, (size_t)count * 8 * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_init_mlp_forward(smsq_init_mlp_t m, int batch, const void *features, void *out, hipStream_t s)
+{
+    if (!m || batch < 1 || batch > m->max_batch || !features || !out) return SMSQ_ERR_INVALID;
+    hipLaunchKernelGGL(k_to_bf16, dim3((batch * kInitFeat + 255) / 256), dim3(256), 0, s, (const float *)features,
+                       m->Fb, (long)batch * kInitFeat);
+    mlp_forward(m, batch, s);
+    if (hipMemcpyAsync(out, m->out, (size_t)batch * kInitOut * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_init_mlp_backward(smsq_init_mlp_t m, int batch, const void *dout, hipStream_t s)
+{
+    if (!m || batch < 1 || batch > m->max_batch || !dout) return SMSQ_ERR_INVALID;
+    if (hipMemcpyAsync(m->dout, dout, (size_t)batch * kInitOut * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    mlp_backward(m, batch, s);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_init_mixture_nll(smsq_init_set_t st, int first, int count, const void *out, const void *anchors,
+                                    const void *scales, double gscale, void *loss, void *dout, hipStream_t s)
+{
+    if (!st || first < 0 || count < 1 || first + count > st->count || !out || !anchors || !scales || !loss || !dout)
+        return SMSQ_ERR_INVALID;
+    hipLaunchKernelGGL(k_mix_nll, dim3(count), dim3(kWave), 0, s, st->ex + first, count, (const float *)out,
+                       (const float *)anchors, (const float *)scales, (float *)dout, (float *)loss, (float)gscale);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_init_mlp_train_step(smsq_init_mlp_t m, smsq_init_set_t st, int first, int count, double lr,
+                                       void *loss_out, hipStream_t s)
+{
+    if (!range_ok(m, st, first, count) || !(lr > 0.0)) return SMSQ_ERR_INVALID;
+    const InitExample *ex = st->ex + first;
+    mlp_features(m, ex, count, s);
+    mlp_forward(m, count, s);
+    hipLaunchKernelGGL(k_mix_nll, dim3(count), dim3(kWave), 0, s, ex, count, m->out, m->anc, m->scl, m->dout,
+                       m->lossv, 1.f / (float)count);
+    mlp_backward(m, count, s);
+    m->adam_t += 1;
+    hipLaunchKernelGGL(k_adam, dim3((kInitParams + 255) / 256), dim3(256), 0, s, m->P, m->G, m->Mo, m->Ve,
+                       kInitParams, (float)lr, 0.9f, 0.999f, 1e-8f, m->adam_t, m->w1b, m->w2b, m->w3b);
+    if (loss_out) hipLaunchKernelGGL(k_mean_f32, dim3(1), dim3(kWave), 0, s, m->lossv, count, (float *)loss_out);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t smsq_init_mlp_sample(smsq_init_mlp_t m, smsq_init_set_t st, int first, int count, int32_t *used,
+                                   hipStream_t s)
+{
+    if (!range_ok(m, st, first, count)) return SMSQ_ERR_INVALID;
+    return init_propose(m, st->ex + first, count, st->max_n, used, s);
+}
+
+smsq_status_t smsq_batch_plan_set_init(smsq_batch_plan_t p, smsq_init_mlp_t m)
+{
+    if (!p) return SMSQ_ERR_INVALID;
+    if (m && m->max_batch < p->max_active) return SMSQ_ERR_INVALID;
+    if (m && !p->init_ex) {
+        size_t total = 0;
+        if (dev_alloc(&p->init_ex, (size_t)p->max_active, total) != hipSuccess ||
+            dev_alloc(&p->init_used, (size_t)p->max_active, total) != hipSuccess)
+            return SMSQ_ERR_HIP;
+        p->device_bytes += total;
+    }
+    p->mlp = m;
     return SMSQ_OK;
 }
 

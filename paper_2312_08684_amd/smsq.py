@@ -27,6 +27,10 @@ SYMBOLS = [
     "smsq_status_string", "smsq_max_particles",
     "smsq_batch_plan_create", "smsq_batch_plan_tune", "smsq_batch_run", "smsq_batch_storage",
     "smsq_batch_plan_info", "smsq_batch_status", "smsq_batch_plan_destroy",
+    "smsq_init_mlp_create", "smsq_init_mlp_destroy", "smsq_init_mlp_params", "smsq_init_mlp_sync",
+    "smsq_init_set_create", "smsq_init_set_destroy", "smsq_init_features", "smsq_init_mlp_forward",
+    "smsq_init_mlp_backward", "smsq_init_mixture_nll", "smsq_init_mlp_train_step", "smsq_init_mlp_sample",
+    "smsq_batch_plan_set_init",
 ]
 
 
@@ -50,6 +54,12 @@ class BatchSeq(C.Structure):
 class BatchInfo(C.Structure):
     _fields_ = [("count", C.c_int), ("T_max", C.c_int), ("waves", C.c_int), ("grid", C.c_int),
                 ("lds_bytes", C.c_size_t), ("device_bytes", C.c_size_t), ("tuned_ms", C.c_double * 2)]
+
+
+class InitExample(C.Structure):
+    _fields_ = [("model", C.c_int), ("t", C.c_int), ("n", C.c_int), ("n_prev", C.c_int),
+                ("x_prev", C.c_void_p), ("phi_prev", C.c_void_p), ("z", C.c_void_p), ("z_mask", C.c_void_p),
+                ("particles", C.c_void_p), ("seed", C.c_uint64), ("seq", C.c_int)]
 
 
 class SvgdOpts(C.Structure):
@@ -98,6 +108,19 @@ def load(path: str = LIB_PATH):
     L.smsq_batch_plan_info.argtypes = [vp, C.POINTER(BatchInfo)]
     L.smsq_batch_status.argtypes = [vp, C.POINTER(C.c_int)]
     L.smsq_batch_plan_destroy.argtypes = [vp]
+    L.smsq_init_mlp_create.argtypes = [u64, i32, C.POINTER(vp)]
+    L.smsq_init_mlp_destroy.argtypes = [vp]
+    L.smsq_init_mlp_params.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_size_t)]
+    L.smsq_init_mlp_sync.argtypes = [vp, vp]
+    L.smsq_init_set_create.argtypes = [C.POINTER(vp), i32, C.POINTER(InitExample), i32, C.POINTER(vp)]
+    L.smsq_init_set_destroy.argtypes = [vp]
+    L.smsq_init_features.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
+    L.smsq_init_mlp_forward.argtypes = [vp, i32, vp, vp, vp]
+    L.smsq_init_mlp_backward.argtypes = [vp, i32, vp, vp]
+    L.smsq_init_mixture_nll.argtypes = [vp, i32, i32, vp, vp, vp, dbl, vp, vp, vp]
+    L.smsq_init_mlp_train_step.argtypes = [vp, vp, i32, i32, dbl, vp, vp]
+    L.smsq_init_mlp_sample.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.smsq_batch_plan_set_init.argtypes = [vp, vp]
     for name in SYMBOLS:
         fn = getattr(L, name)
         if fn.restype is None or fn.restype is C.c_int:
@@ -421,6 +444,13 @@ class BatchPlan:
     def run(self, use_graph: bool = False, stream=None):
         _check(load().smsq_batch_run(self.handle, 1 if use_graph else 0, _stream(stream)), "smsq_batch_run")
 
+    def set_init(self, mlp: Optional["InitMLP"]):
+        """Initial particles of steps t >= 2 from the proposal network (None:
+        the predictive initialisation)."""
+        _check(load().smsq_batch_plan_set_init(self.handle, mlp.handle if mlp is not None else None),
+               "smsq_batch_plan_set_init")
+        self._mlp = mlp
+
     def info(self) -> dict:
         i = BatchInfo()
         _check(load().smsq_batch_plan_info(self.handle, C.byref(i)), "smsq_batch_plan_info")
@@ -478,3 +508,137 @@ def _hip():
         _hip_lib.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
         _hip_lib.hipMemcpy.restype = C.c_int
     return _hip_lib
+
+
+def _copy_into(ptr: int, src: torch.Tensor):
+    """Device-to-device copy of a contiguous tensor into library-owned memory."""
+    src = src.contiguous()
+    torch.cuda.synchronize()
+    err = _hip().hipMemcpy(C.c_void_p(ptr), C.c_void_p(src.data_ptr()), C.c_size_t(src.numel() * src.element_size()), 3)
+    if err != 0:
+        raise RuntimeError("hipMemcpy failed (%d)" % err)
+
+
+N_INIT_PARAMS = 113272
+INIT_FEAT, INIT_OUT = 64, 120
+
+
+class InitMLP:
+    """Proposal network of the learned initialisation (smsq_init_mlp_*)."""
+
+    def __init__(self, seed: int = 0, max_batch: int = 4096):
+        h = C.c_void_p()
+        _check(load().smsq_init_mlp_create(int(seed), int(max_batch), C.byref(h)), "smsq_init_mlp_create")
+        self.handle = h
+        self.max_batch = max_batch
+
+    def _ptrs(self):
+        p, g, n = C.c_void_p(), C.c_void_p(), C.c_size_t()
+        _check(load().smsq_init_mlp_params(self.handle, C.byref(p), C.byref(g), C.byref(n)), "smsq_init_mlp_params")
+        return p.value, g.value, n.value
+
+    def params(self) -> torch.Tensor:
+        p, _, n = self._ptrs()
+        return _wrap(p, (n,), torch.float32, "cuda")
+
+    def grads(self) -> torch.Tensor:
+        _, g, n = self._ptrs()
+        return _wrap(g, (n,), torch.float32, "cuda")
+
+    def set_params(self, P: torch.Tensor):
+        p, _, n = self._ptrs()
+        if P.numel() != n or P.dtype != torch.float32 or not P.is_cuda:
+            raise ValueError("parameters must be a float32 device tensor of %d values" % n)
+        _copy_into(p, P)
+        _check(load().smsq_init_mlp_sync(self.handle, _stream(None)), "smsq_init_mlp_sync")
+        torch.cuda.synchronize()
+
+    def forward(self, F: torch.Tensor) -> torch.Tensor:
+        B = F.shape[0]
+        out = torch.empty((B, INIT_OUT), dtype=torch.float32, device=F.device)
+        _check(load().smsq_init_mlp_forward(self.handle, B, _ptr(F, torch.float32, "features"), _ptr(out),
+                                            _stream(None)), "smsq_init_mlp_forward")
+        return out
+
+    def backward(self, dout: torch.Tensor):
+        _check(load().smsq_init_mlp_backward(self.handle, dout.shape[0], _ptr(dout, torch.float32, "dout"),
+                                             _stream(None)), "smsq_init_mlp_backward")
+
+    def features(self, iset: "InitSet", first: int = 0, count: Optional[int] = None):
+        count = iset.count - first if count is None else count
+        F = torch.empty((count, INIT_FEAT), dtype=torch.float32, device="cuda")
+        A = torch.empty((count, 8), dtype=torch.float32, device="cuda")
+        Sc = torch.empty((count, 8), dtype=torch.float32, device="cuda")
+        _check(load().smsq_init_features(self.handle, iset.handle, first, count, _ptr(F), _ptr(A), _ptr(Sc),
+                                         _stream(None)), "smsq_init_features")
+        return F, A, Sc
+
+    def train_step(self, iset: "InitSet", first: int, count: int, lr: float) -> torch.Tensor:
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(load().smsq_init_mlp_train_step(self.handle, iset.handle, first, count, float(lr), _ptr(loss),
+                                               _stream(None)), "smsq_init_mlp_train_step")
+        return loss
+
+    def sample(self, iset: "InitSet", first: int = 0, count: Optional[int] = None) -> torch.Tensor:
+        count = iset.count - first if count is None else count
+        used = torch.empty(count, dtype=torch.int32, device="cuda")
+        _check(load().smsq_init_mlp_sample(self.handle, iset.handle, first, count, _ptr(used), _stream(None)),
+               "smsq_init_mlp_sample")
+        return used
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().smsq_init_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class InitSet:
+    """Examples of the proposal (smsq_init_set_*): dicts with keys model, t,
+    x_prev [n_prev, d], phi_prev [n_prev], z [obs_dim], z_mask or None,
+    particles [n, d] (targets, or where samples go), seed, seq."""
+
+    def __init__(self, models, examples):
+        arr = (InitExample * len(examples))()
+        self._keep = []
+        for i, q in enumerate(examples):
+            P = q["particles"]
+            arr[i] = InitExample(int(q["model"]), int(q["t"]), P.shape[0], q["x_prev"].shape[0],
+                                 _ptr(q["x_prev"], torch.float32, "x_prev"), _ptr(q["phi_prev"], torch.float32, "phi_prev"),
+                                 _ptr(q["z"], torch.float32, "z"), _ptr(q.get("z_mask"), torch.uint8, "z_mask"),
+                                 _ptr(P, torch.float32, "particles"), int(q.get("seed", 0)), int(q.get("seq", 0)))
+            self._keep += [q["x_prev"], q["phi_prev"], q["z"], q.get("z_mask"), P]
+        handles = (C.c_void_p * len(models))(*[m.handle for m in models])
+        h = C.c_void_p()
+        _check(load().smsq_init_set_create(handles, len(models), arr, len(examples), C.byref(h)),
+               "smsq_init_set_create")
+        self.handle = h
+        self.count = len(examples)
+        self.models = models
+
+    def nll(self, out: torch.Tensor, anchors: torch.Tensor, scales: torch.Tensor, first: int = 0,
+            gscale: float = 1.0):
+        count = out.shape[0]
+        loss = torch.empty(count, dtype=torch.float32, device="cuda")
+        dout = torch.empty((count, INIT_OUT), dtype=torch.float32, device="cuda")
+        _check(load().smsq_init_mixture_nll(self.handle, first, count, _ptr(out, torch.float32, "out"),
+                                            _ptr(anchors, torch.float32, "anchors"),
+                                            _ptr(scales, torch.float32, "scales"), float(gscale), _ptr(loss),
+                                            _ptr(dout), _stream(None)), "smsq_init_mixture_nll")
+        return loss, dout
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().smsq_init_set_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -242,10 +242,11 @@ typedef struct {
     int model;              /* index into the plan's model/options arrays */
     int n;                  /* particles per step, 1..1024 */
     int T;                  /* steps, >= 1 */
-    int init_given;         /* 0: predictive initial particles (Philox, as in
-                               smsq_batch_step with seq_offset 0); 1: the plan's
-                               particle storage of step t already holds them
-                               (written by a learned proposal before the run) */
+    int use_proposal;       /* 1: when the plan has a proposal network
+                               (smsq_batch_plan_set_init), the initial particles
+                               of steps t >= 2 are drawn from it; 0: always the
+                               predictive initialisation (Philox, as in
+                               smsq_batch_step with seq_offset 0) */
     uint64_t seed;
     const void *x0;         /* [d] FP32 known initial state */
     const void *z;          /* [T][obs_dim] FP32 observations */
@@ -369,16 +370,18 @@ smsq_status_t smsq_init_mixture_nll(smsq_init_set_t set, int first, int count, c
  * update.  loss_out [1] (device, FP32) receives the mean loss, or NULL. */
 smsq_status_t smsq_init_mlp_train_step(smsq_init_mlp_t mlp, smsq_init_set_t set, int first, int count,
                                        double lr, void *loss_out, hipStream_t stream);
-/* Draws each example's n particles from its proposal into `particles`;
- * used [count] (device, int32, or NULL) is 1 where the outputs were finite
- * and the samples written, 0 where nothing was written. */
+/* Draws each example's n particles from its proposal into `particles`
+ * (Philox4x32-10 keyed by seed, counter (i, t, seq, 2..4)); used [count]
+ * (device, int32, or NULL) is 1 where the outputs were finite and the
+ * samples written, 0 where nothing was written. */
 smsq_status_t smsq_init_mlp_sample(smsq_init_mlp_t mlp, smsq_init_set_t set, int first, int count,
                                    int32_t *used, hipStream_t stream);
 
-/* Batched plans: initial particles of steps t >= 2 from the proposal (NULL:
- * the predictive initialisation).  Per step the plan then also runs the
- * features, the forward pass and the sampler; a sequence whose proposal is
- * not finite falls back to the predictive initialisation for that step.
+/* Batched plans: initial particles of steps t >= 2 of the sequences with
+ * use_proposal = 1 from the proposal (NULL: the predictive initialisation
+ * everywhere).  Per step the plan then also runs the features, the forward
+ * pass and the sampler; a sequence whose proposal is not finite falls back
+ * to the predictive initialisation for that step.
  * max_batch of the network must cover the plan's sequences. (host) */
 smsq_status_t smsq_batch_plan_set_init(smsq_batch_plan_t plan, smsq_init_mlp_t mlp);
 

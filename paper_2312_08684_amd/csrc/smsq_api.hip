@@ -501,7 +501,7 @@ struct smsq_batch_plan_s {
                                cnt, t, init_ex);
             const smsq_status_t st = init_propose(mlp, init_ex, cnt, max_n, init_used, s);
             if (st != SMSQ_OK) return st;
-            hipLaunchKernelGGL(k_init_apply, dim3((cnt + 63) / 64), dim3(64), 0, s, items, init_used, cnt);
+            hipLaunchKernelGGL(k_init_apply, dim3((cnt + 63) / 64), dim3(64), 0, s, items, init_ex, init_used, cnt);
         }
         const int g = std::min(grid(), cnt);
         if (waves == 16)
@@ -743,7 +743,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     for (int i = 0; i < count; ++i) {
         const smsq_batch_seq_t &q = seqs[i];
         if (q.model < 0 || q.model >= n_models || q.n < 1 || q.T < 1 || !q.x0 || !q.z || !q.xmap_out ||
-            !q.logpost_out || (q.init_given != 0 && q.init_given != 1))
+            !q.logpost_out || (q.use_proposal != 0 && q.use_proposal != 1))
             return SMSQ_ERR_INVALID;
         const smsq_model_desc_t &d = models[q.model]->desc;
         if (!batch_family(d.kind)) return SMSQ_ERR_UNSUPPORTED;
@@ -823,7 +823,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
         sd.n_iter = o.n_iter;
         sd.bw_mode = o.bw_mode;
         sd.trans_mode = o.trans_mode;
-        sd.init_given = q.init_given;
+        sd.use_proposal = q.use_proposal;
         sd.step = (float)o.step;
         sd.bw_scale = (float)o.bw_scale;
         sd.seed = q.seed;

@@ -30,7 +30,7 @@ struct SeqDesc {
     float *logpost;         // [1] J out
     int32_t *idx;           // [T] MAP indices (plan storage)
     int n, T, d, code;
-    int n_iter, bw_mode, trans_mode, init_given;
+    int n_iter, bw_mode, trans_mode, use_proposal;
     float step, bw_scale;
     uint64_t seed;
 };
@@ -64,7 +64,7 @@ __global__ void k_batch_prep(const SeqDesc *__restrict__ seqs, const int *__rest
     a.n_iter = s.n_iter;
     a.bw_mode = s.bw_mode;
     a.trans_mode = s.trans_mode;
-    a.init_given = s.init_given;
+    a.init_given = 0;  // the learned proposal, when used, sets it per step
     a.do_svgd = 1;
     a.do_viterbi = 1;
     a.step = s.step;

@@ -357,20 +357,9 @@ __global__ __launch_bounds__(64) void k_mix_nll(const InitExample *__restrict__ 
 // Box-Muller, uniforms from Philox4x32-10 keyed by the example seed with
 // counter (i, t, seq, 2 + b), b = 0, 1, 2.  Non-finite outputs: used[e] = 0
 // and nothing is written (the predictive initialisation applies).
-__global__ __launch_bounds__(256) void k_mix_sample(const InitExample *__restrict__ ex, int count,
-                                                    const float *__restrict__ out, const float *__restrict__ anc,
-                                                    const float *__restrict__ scl, int32_t *used)
+template <int D>
+__device__ void mix_sample_one(const InitExample &x, int i, const float *o, const float *anc, const float *scl)
 {
-    const int e = blockIdx.y;
-    if (e >= count) return;
-    const InitExample &x = ex[e];
-    const float *o = out + (long)e * kInitOut;
-    bool ok = true;
-    for (int q = 0; q < kInitOut; ++q) ok &= __builtin_isfinite(o[q]);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && used) used[e] = ok ? 1 : 0;
-    if (!ok) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= x.n) return;
     float lmax = -__builtin_huge_valf();
     for (int c = 0; c < kInitK; ++c) lmax = fmaxf(lmax, o[c * kInitComp]);
     float w[kInitK], tot = 0.f;
@@ -394,15 +383,37 @@ __global__ __launch_bounds__(256) void k_mix_sample(const InitExample *__restric
         acc += w[q];
         if (uc < acc) { c = q; break; }
     }
-    const int d = x.m.d;
-    for (int k = 0; k < d; ++k) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
         const int p = k / 2;
         const double rad = sqrt(-2.0 * log(u[2 + 2 * p]));
         const double th = 2.0 * kPi * u[3 + 2 * p];
         const float xi = (float)((k & 1) ? rad * sin(th) : rad * cos(th));
         const float rho = fminf(fmaxf(o[c * kInitComp + 8 + k], kRhoMin), kRhoMax);
-        const float s = scl[e * 8 + k];
-        x.target[(long)i * d + k] = anc[e * 8 + k] + s * (o[c * kInitComp + 1 + k] + expf(rho) * xi);
+        x.target[(long)i * D + k] = anc[k] + scl[k] * (o[c * kInitComp + 1 + k] + expf(rho) * xi);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mix_sample(const InitExample *__restrict__ ex, int count,
+                                                    const float *__restrict__ out, const float *__restrict__ anc,
+                                                    const float *__restrict__ scl, int32_t *used)
+{
+    const int e = blockIdx.y;
+    if (e >= count) return;
+    const InitExample &x = ex[e];
+    const float *o = out + (long)e * kInitOut;
+    bool ok = true;
+    for (int q = 0; q < kInitOut; ++q) ok &= __builtin_isfinite(o[q]);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && used) used[e] = ok ? 1 : 0;
+    if (!ok) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= x.n) return;
+    const float *a = anc + e * 8, *sc = scl + e * 8;
+    switch (x.code) {
+    case GROWTH1D: mix_sample_one<1>(x, i, o, a, sc); break;
+    case RANGE2D: mix_sample_one<2>(x, i, o, a, sc); break;
+    case CV4D: mix_sample_one<4>(x, i, o, a, sc); break;
+    default: mix_sample_one<7>(x, i, o, a, sc); break;
     }
 }
 
@@ -443,7 +454,7 @@ __global__ void k_init_prep(const SeqDesc *__restrict__ seqs, const int *__restr
     x.mask = s.mask ? s.mask + (long)(t - 1) * s.m.n_obs : nullptr;
     x.target = s.parts + (long)(t - 1) * nd;
     x.np = s.n;
-    x.n = s.n;
+    x.n = s.use_proposal ? s.n : 0;  // nothing to draw for the others
     x.t = t;
     x.code = s.code;
     x.seq = 0;
@@ -452,11 +463,12 @@ __global__ void k_init_prep(const SeqDesc *__restrict__ seqs, const int *__restr
 }
 
 // After sampling: the step's items take the sampled particles (init_given)
-// where the proposal was finite.
-__global__ void k_init_apply(StepArgs<float> *items, const int32_t *__restrict__ used, int count)
+// where a sequence uses the proposal and its outputs were finite.
+__global__ void k_init_apply(StepArgs<float> *items, const InitExample *__restrict__ ex,
+                             const int32_t *__restrict__ used, int count)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < count) items[k].init_given = used[k];
+    if (k < count) items[k].init_given = ex[k].n > 0 ? used[k] : 0;
 }
 
 // He initialisation: W ~ N(0, 2 / fan_in) from Philox4x32-10 (key seed,

@@ -46,7 +46,7 @@ class ModelDesc(C.Structure):
 
 
 class BatchSeq(C.Structure):
-    _fields_ = [("model", C.c_int), ("n", C.c_int), ("T", C.c_int), ("init_given", C.c_int),
+    _fields_ = [("model", C.c_int), ("n", C.c_int), ("T", C.c_int), ("use_proposal", C.c_int),
                 ("seed", C.c_uint64), ("x0", C.c_void_p), ("z", C.c_void_p), ("z_mask", C.c_void_p),
                 ("xmap_out", C.c_void_p), ("logpost_out", C.c_void_p)]
 
@@ -403,7 +403,8 @@ class BatchPlan:
 
     models: list of Model; opts: list of SvgdOpts (one per model);
     seqs: list of dicts with keys model, n, x0 [d], z [T, obs_dim], z_mask
-    ([T, n_obs] uint8 or None), seed, init_given (optional, default 0).
+    ([T, n_obs] uint8 or None), seed, use_proposal (optional, default 1;
+    only matters once a proposal network is set).
     The plan allocates xmap [T+1, d] and J [1] per sequence (``xmap``, ``J``).
     """
 
@@ -426,7 +427,7 @@ class BatchPlan:
             self.J.append(J)
             mask = q.get("z_mask")
             self._keep += [x0, z, mask]
-            arr[i] = BatchSeq(k, int(q["n"]), int(T), int(q.get("init_given", 0)), int(q["seed"]),
+            arr[i] = BatchSeq(k, int(q["n"]), int(T), int(q.get("use_proposal", 1)), int(q["seed"]),
                               _ptr(x0, torch.float32, "x0"), _ptr(z, torch.float32, "z"),
                               _ptr(mask, torch.uint8, "z_mask"), _ptr(xm), _ptr(J))
         handles = (C.c_void_p * len(models))(*[m.handle for m in models])

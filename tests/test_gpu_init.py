@@ -145,12 +145,13 @@ def test_sampler_moments():
     _, A, Sc = mlp.features(iset)
     for k in range(2):
         X = targets[k].cpu().numpy().astype(np.float64)
+        nh = X.shape[0]
         m, v = M.mixture_moments(b3, A[k].cpu().numpy(), Sc[k].cpu().numpy(), d)
-        se = np.sqrt(v / nbig)
+        se = np.sqrt(v / nh)
         assert np.all(np.abs(X.mean(axis=0) - m) <= 5 * se), (X.mean(axis=0), m, se)
         # variance of the sample variance ~ 2 v^2 / n for near-Gaussian tails; mixtures: use the 4th moment
         v4 = ((X - X.mean(axis=0)) ** 4).mean(axis=0)
-        sev = np.sqrt(np.maximum(v4 - v ** 2, 1e-30) / nbig)
+        sev = np.sqrt(np.maximum(v4 - v ** 2, 1e-30) / nh)
         assert np.all(np.abs(X.var(axis=0) - v) <= 5 * sev), (X.var(axis=0), v, sev)
 
 

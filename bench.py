@@ -9,8 +9,12 @@ L = 100 iterations, T = 100 steps) with a batch of Monte-Carlo sequences.
 Printed as one JSON line: SVGD particle-iterations per second (value), the
 whole-job Viterbi edge rate, the roofline of the dominant kernel (the fused
 step kernel, timed per launch with HIP events on the launch stream), a
-lattice-mode forward-recursion bandwidth figure, and the CPU oracle timed on
-a bounded sample of the same workload.
+lattice-mode forward-recursion bandwidth figure, the CPU oracle timed on a
+bounded sample of the same workload, and (``batched``) a ragged mix of all
+four model families with uneven N and T run as batched plans: plain, plain
+at half the SVGD iterations, and the learned initialisation at half the
+iterations (trained first on plain runs of a separate mix), each against the
+full plain run's MAP log-posterior.
 """
 from __future__ import annotations
 
@@ -51,6 +55,8 @@ def parse():
     p.add_argument("--cpu-baseline", type=int, default=1)
     p.add_argument("--lattice-n", type=int, default=4096)
     p.add_argument("--lattice-batch", type=int, default=16)
+    p.add_argument("--batched-seqs", type=int, default=1024, help="ragged-mix sequences (0: skip)")
+    p.add_argument("--train-steps", type=int, default=4000)
     return p.parse_args()
 
 
@@ -99,6 +105,51 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
     return {"n": n, "lattices": batch, "edges_per_s": n * n / sec, "us_per_launch": sec * 1e6,
             "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM,
             "bytes_per_launch": nbytes}
+
+
+def batched_mix(torch, smsq, count: int, train_steps: int):
+    """Ragged mix (family uniform over the four, N from {32..1024}, T in
+    [50, 200]) as one batched plan per run, hipGraph replay, autotuned."""
+    from paper_2312_08684_amd import learned as LI
+    from paper_2312_08684_amd import scenarios as S
+    spec = LI.mix(count, seed=11, T_lo=50, T_hi=200)
+    pi = sum(n * T * S.PRESETS[f][2] for (f, n, T, _) in spec)   # particle-iterations at full L
+    plan, Jfull, t_full, _, _ = LI.run(spec, 1.0, tune=True)
+    info = plan.info()
+    del plan
+    _, Jhalf, t_half, _, _ = LI.run(spec, 0.5)
+    # proposal: trained on plain runs of a separate, shorter mix; gated per
+    # family on a validation mix
+    t0 = time.perf_counter()
+    tspec = LI.mix(320, seed=1, T_lo=20, T_hi=40)
+    tplan, _, _, tmodels, tseqs = LI.run(tspec, 1.0)
+    ex = LI.examples(tplan, tspec, tseqs)
+    mlp = smsq.InitMLP(seed=5, max_batch=max(4096, count))
+    losses = LI.train(mlp, tmodels, ex, steps=train_steps, batch=512, lr=1e-3, log_every=train_steps // 4)
+    del tplan, ex
+    gain = LI.choose_gate(mlp, LI.mix(64, seed=3, T_lo=50, T_hi=200), 0.5)
+    gate = {f: g["use"] for f, g in gain.items()}
+    t_train = time.perf_counter() - t0
+    _, Jl, t_l, _, _ = LI.run(spec, 0.5, mlp=mlp, gate=gate)
+    seqs = float(count)
+
+    def row(J, t, frac_L):
+        per = {}
+        for f in LI.FAMILIES:
+            idx = [i for i, sp in enumerate(spec) if sp[0] == f]
+            per[f] = {"matched_frac": float(np.mean(LI.matched(J[idx], Jfull[idx], [spec[i] for i in idx]))),
+                      "mean_J_gap": float(np.mean(J[idx] - Jfull[idx]))}
+        return {"seconds": t, "sequences_per_s": seqs / t, "particle_iters_per_s": pi * frac_L / t,
+                "matched_frac": float(np.mean(LI.matched(J, Jfull, spec))), "mean_J_gap": float(np.mean(J - Jfull)),
+                "per_family": per}
+
+    return {"sequences": count, "families": "growth1d range2d cv4d arm7", "N": "32..1024", "T": "50..200",
+            "workgroup_waves": info["waves"], "tuned_ms_per_step": info["tuned_ms"],
+            "plain_full_L": row(Jfull, t_full, 1.0), "plain_half_L": row(Jhalf, t_half, 0.5),
+            "learned_half_L": row(Jl, t_l, 0.5),
+            "learned": {"train_sequences": len(tspec), "train_T": "20..40", "train_steps": train_steps,
+                        "train_nll": losses, "gate_per_family": gain, "setup_seconds": t_train},
+            "match_rule": "J >= J_plain_full - 1e-3 max(|J_plain_full|, T)"}
 
 
 def main():
@@ -194,6 +245,8 @@ def main():
                      "kernel_avg_ms": k_avg_ms, "flops_per_launch": flops_launch},
         "viterbi_lattice": lat,
     }
+    if args.batched_seqs > 0:
+        out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(out), flush=True)

@@ -115,16 +115,29 @@ def train(mlp: smsq.InitMLP, models, ex: List[dict], steps: int, batch: int = 51
     return losses
 
 
-def choose_gate(mlp: smsq.InitMLP, spec, L_scale: float) -> Dict[str, float]:
-    """Per family: mean J gain of the proposal over the predictive
-    initialisation at the reduced iteration count (positive: use it)."""
+def choose_gate(mlp: smsq.InitMLP, spec, L_scale: float) -> Dict[str, dict]:
+    """Per family, on a validation mix at the reduced iteration count: the
+    proposal's J against the predictive initialisation's (mean and median
+    gain) and the share of sequences each brings within the match rule of
+    the full-iteration plain J.  ``use`` = median gain > 0 and no loss of
+    matched share; the median keeps a few far-drifted sequences from
+    deciding for a family."""
+    _, Jf, _, _, _ = run(spec, 1.0)
     _, Jp, _, _, _ = run(spec, L_scale)
     _, Jl, _, _, _ = run(spec, L_scale, mlp=mlp, gate={f: True for f in FAMILIES})
-    gain = {}
+    out = {}
     for f in FAMILIES:
         idx = [i for i, sp in enumerate(spec) if sp[0] == f]
-        gain[f] = float(np.mean(Jl[idx] - Jp[idx])) if idx else 0.0
-    return gain
+        if not idx:
+            out[f] = {"use": False}
+            continue
+        sub = [spec[i] for i in idx]
+        mp = float(np.mean(matched(Jp[idx], Jf[idx], sub)))
+        ml = float(np.mean(matched(Jl[idx], Jf[idx], sub)))
+        d = Jl[idx] - Jp[idx]
+        out[f] = {"mean_gain": float(np.mean(d)), "median_gain": float(np.median(d)), "matched_plain": mp,
+                  "matched_learned": ml, "use": bool(np.median(d) > 0.0 and ml >= mp)}
+    return out
 
 
 def matched(J, J_ref, spec, rel: float = 1e-3) -> np.ndarray:

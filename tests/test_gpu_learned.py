@@ -63,7 +63,7 @@ def test_trained_proposal_gains_at_half_the_iterations():
     assert losses[-1] < losses[0]
     val_spec = LI.mix(48, seed=3, T_lo=12, T_hi=24, n_choices=(32, 128, 256, 512))
     gain = LI.choose_gate(mlp, val_spec, 0.5)
-    gate = {f: g > 0.0 for f, g in gain.items()}
+    gate = {f: g["use"] for f, g in gain.items()}
     print("validation gain per family", gain, flush=True)
     test_spec = LI.mix(96, seed=2, T_lo=12, T_hi=24, n_choices=(32, 128, 256, 512))
     _, Jfull, t_full, _, _ = LI.run(test_spec, 1.0)

@@ -552,6 +552,15 @@ __device__ __forceinline__ void progress_priority(int step, int n)
 
 // One sequence's time step (b: its index in the strided batch of `a`).  The
 // workgroup owns the sequence: all state in LDS, every barrier block-wide.
+// Sum of a value over the four 16-lane rows of a wave, in every lane.
+__device__ __forceinline__ float sum_row_quarters(float v)
+{
+    auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
 template <int KIND, int D, int TS>
 __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const int b)
 {
@@ -912,8 +921,21 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         const float beta = uniform((float)kLog2e / h);
 
         // (3) Stein direction
+        //   phi_i = (sum_k kappa_ki v_k + c2 x_i sum_k kappa_ki) / n,
+        //   v_k = s_k - c2 x_k, c2 = 2 / h
+        // (the kernel-gradient term of the update folded into the score
+        // rows, so one contraction of kappa with [v, 1] gives both sums).
+        // The score rows become v in place; column kOne holds the 1.
         const float twob = 2.f * beta;
         const float c2 = 2.f / h;
+        constexpr int NG = D <= 3 ? 1 : 2;       // row groups of four in the sums
+        constexpr int kOne = NG == 1 ? 3 : 7;    // row that sums kappa
+        for (int k = tid; k < npad; k += nt) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) S8[(long)k * 8 + c] -= c2 * X8[(long)k * 8 + c];
+            if (kOne != 7) S8[(long)k * 8 + kOne] = 1.f;
+        }
+        __syncthreads();
         float phi[TS][kTilesPerWave][2];  // kept in registers until every wave is done
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {
@@ -925,7 +947,14 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             // -beta |x_k - x_i|^2 of kappa directly
             float bi0[kTilesPerWave], bi1[kTilesPerWave];
             f32x4 cb[kTilesPerWave];
-            f32x4 O[kTilesPerWave];
+            // Sums on the 4x4x1 (16-block) MFMA straight from the Gram tile
+            // layout: register r of lane l holds kappa of source
+            // 16 kt + 4 (l / 16) + r and target 16 q + l % 16, so block
+            // b = l / 4 takes B = that register and A = rows 4 gg + l % 4 of
+            // v for its source; lane l of O4[gg][q] accumulates rows
+            // 4 gg + i (register i) of target 16 q + l % 16 over the source
+            // quarter l / 16, summed across quarters after the pass
+            f32x4 O4[NG][kTilesPerWave];
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = ibase + 16 * q + col;
@@ -933,13 +962,10 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 bi1[q] = g == 3 ? -beta : twob * X8[(long)ii * 8 + 4 + g];
                 const float nb = -beta * X8[(long)ii * 8 + 7];
                 cb[q] = f32x4{nb, nb, nb, nb};
-                O[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int gg = 0; gg < NG; ++gg) O4[gg][q] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
-            // value operand of lane (col, g), row k: column col of
-            // [s_k (d), 0.., 1, x_k (d), 0..] -- S8 row for col < 8 (its column
-            // 7 holds 1), X8 row for col >= 8; lane col = 15 reads column 0
-            // (finite; output row 15 is unused)
-            const float *vbase = (col < 8 ? S8 + col : X8 + (col < 15 ? col - 8 : 0)) + (long)(4 * g) * 8;
+            const float *vbase = S8 + (long)(4 * g) * 8 + (lane & 3);
             // Gram tiles: A rows (x_k, n_k in K-column 7)
             auto gram = [&](int kt, f32x4 (&Go)[kTilesPerWave]) {
                 const float *xr = X8 + (long)(kt * 16 + col) * 8;
@@ -954,9 +980,11 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             // buffers alternate
             auto tile = [&](int kt, f32x4 (&G)[kTilesPerWave], f32x4 (&Gn)[kTilesPerWave]) {
                 const float *vb = vbase + (long)(kt * 16) * 8;
-                float av[4];
+                float av[4][NG];
 #pragma unroll
-                for (int mm = 0; mm < 4; ++mm) av[mm] = vb[mm * 8];
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int gg = 0; gg < NG; ++gg) av[r][gg] = vb[r * 8 + 4 * gg];
                 gram(min(kt + 1, nkt - 1), Gn);
 #pragma unroll
                 for (int q = 0; q < kTilesPerWave; ++q)
@@ -964,9 +992,12 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                     for (int r = 0; r < 4; ++r) G[q][r] = R::exp2_(G[q][r]);
                 // independent accumulators back to back
 #pragma unroll
-                for (int mm = 0; mm < 4; ++mm)
+                for (int r = 0; r < 4; ++r)
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q) O[q] = mfma16(av[mm], G[q][mm], O[q]);
+                    for (int q = 0; q < kTilesPerWave; ++q)
+#pragma unroll
+                        for (int gg = 0; gg < NG; ++gg)
+                            O4[gg][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[r][gg], G[q][r], O4[gg][q], 0, 0, 0);
             };
             f32x4 GA[kTilesPerWave], GB[kTilesPerWave];
             gram(0, GA);
@@ -975,28 +1006,26 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 tile(kt, GA, GB);
                 if (kt + 1 < nkt) tile(kt + 1, GB, GA);
             }
-            // O[q] lane l register r = (c = 4g + r, target ibase + 16 q + col):
-            // c < d: sum kappa s_k; c = 7: sum kappa; 8 + c: sum kappa x_k
+            // lane (col, g): target ibase + 16 q + col, coordinates g, 4 + g
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) scr[(4 * g + r) * 16 + col] = O[q][r];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int gg = 0; gg < NG; ++gg)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) O4[gg][q][i] = sum_row_quarters(O4[gg][q][i]);
                 const int ii = ibase + 16 * q + col;
-                const float ksum = scr[7 * 16 + col];
+                const float ksum = O4[NG - 1][q][kOne - 4 * (NG - 1)];
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2) {
                     const int c = g + 4 * h2;
                     float v = 0.f;
-                    if (c < D)
-                        v = (scr[c * 16 + col] + c2 * (X8[(long)ii * 8 + c] * ksum - scr[(8 + c) * 16 + col])) * inv_n;
+                    if (h2 < NG && c < D) {
+                        const f32x4 &o = O4[h2 < NG ? h2 : 0][q];
+                        const float sv = g == 0 ? o[0] : g == 1 ? o[1] : g == 2 ? o[2] : o[3];
+                        v = (sv + c2 * X8[(long)ii * 8 + c] * ksum) * inv_n;
+                    }
                     phi[ts][q][h2] = v;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
         __builtin_amdgcn_s_setprio(0);

@@ -561,6 +561,20 @@ __device__ __forceinline__ float sum_row_quarters(float v)
     return __uint_as_float(s[0]) + __uint_as_float(s[1]);
 }
 
+// Given four values v0..v3 of a wave, lane l in 16-lane row w receives the
+// sum of v_w over the four rows, in that lane's column (a transpose of rows
+// against values, then a sum): two rounds of lane swaps.
+__device__ __forceinline__ float sum_quarters_scatter(float v0, float v1, float v2, float v3)
+{
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v2), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v1), __float_as_uint(v3), false, false);
+    // lanes 0..31: v0 (resp. v1) over rows r, r + 2; lanes 32..63: v2 (v3)
+    const float s0 = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const float s1 = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+    auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(s0), __float_as_uint(s1), false, false);
+    return __uint_as_float(c[0]) + __uint_as_float(c[1]);
+}
+
 template <int KIND, int D, int TS>
 __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const int b)
 {
@@ -742,18 +756,21 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                     bx1[q] = kd1 < D ? X8[(long)kk * 8 + kd1] * rs[kd1] : (kd1 == 7 ? 1.f : 0.f);
                     cm[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-                // Sums on the 4x4x1 (16-block) MFMA with one particle per lane:
-                // lane l holds rows c = 4 ch + i of particle kbase + l in
-                // O4[ch][par] register i (two accumulators per half, for
-                // alternating j); block b = l / 4 takes A = VT[4 ch + l % 4][j]
-                // from its lanes and B = e_j of its four particles.
-                f32x4 O4[2][2];
+                // Sums on the 4x4x1 (16-block) MFMA straight from the logit
+                // tile layout: register r of lane l holds e of source
+                // 16 jt + 4 (l / 16) + r and particle kbase + 16 q + l % 16, so
+                // block b = l / 4 takes B = that register and A = table rows
+                // 4 ch + l % 4 of its source; lane l of O4[ch][q] accumulates
+                // rows 4 ch + i (register i) of particle kbase + 16 q + l % 16
+                // over the source quarter l / 16.
+                f32x4 O4[2][kTilesPerWave];
 #pragma unroll
                 for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                    for (int par = 0; par < 2; ++par) O4[ch][par] = f32x4{0.f, 0.f, 0.f, 0.f};
-                const float *vt0 = VT + (long)(lane & 3) * nppad;        // rows c = l % 4
-                const float *vt1 = VT + (long)(4 + (lane & 3)) * nppad;  // rows c = 4 + l % 4
+                    for (int q = 0; q < kTilesPerWave; ++q) O4[ch][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+                // four consecutive sources 4 (l / 16) + r of rows l % 4, 4 + l % 4
+                const float *vt0 = VT + (long)(lane & 3) * nppad + 4 * g;
+                const float *vt1 = VT + (long)(4 + (lane & 3)) * nppad + 4 * g;
                 // logit A operands: K-row g (2 mh), K-row 4 + g (row 7 of the
                 // table, the 1, becomes c'_j in K-row 7)
                 const float *am0p = VT + (long)g * nppad + col;
@@ -790,88 +807,83 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                             cm[q] -= shq[q];
                         }
                         if (!first) {
-                            // lane l's particle is column col of tile q = l / 16
-                            const float sh = g == 0 ? shq[0] : g == 1 ? shq[1] : g == 2 ? shq[2] : shq[3];
-                            const float sc = R::exp2_(-sh);
 #pragma unroll
-                            for (int ch = 0; ch < 2; ++ch)
-#pragma unroll
-                                for (int par = 0; par < 2; ++par) O4[ch][par] *= sc;
+                            for (int q = 0; q < kTilesPerWave; ++q) {
+                                const float sc = R::exp2_(-shq[q]);
+                                O4[0][q] *= sc;
+                                O4[1][q] *= sc;
+                            }
                         }
                     }
                 };
-                // exponentials of a relative logit tile, moved to one particle
-                // per lane: afterwards register T[m][r] of lane l holds e for
-                // j = 16 jt + 4 m + r and particle kbase + l (a 4x4 transpose
-                // of lane groups against tiles, two rounds of lane swaps)
-                auto exp_transpose = [&](f32x4 (&T)[kTilesPerWave]) {
-#pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) T[q][r] = R::exp2_(T[q][r]);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(T[q][r]),
-                                                                             __float_as_uint(T[q + 2][r]), false, false);
-                            T[q][r] = __uint_as_float(sw[0]);
-                            T[q + 2][r] = __uint_as_float(sw[1]);
-                        }
-#pragma unroll
-                        for (int q = 0; q < 4; q += 2) {
-                            const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(T[q][r]),
-                                                                             __float_as_uint(T[q + 1][r]), false, false);
-                            T[q][r] = __uint_as_float(sw[0]);
-                            T[q + 1][r] = __uint_as_float(sw[1]);
-                        }
-                    }
-                };
-                // One logit tile per step, software-pipelined: the logits of
-                // tile jt + 1 are issued (and checked) around the exponentials
-                // and sums of tile jt; with WALK, two tiles of the median
+                // One logit tile per step; with WALK, two tiles of the median
                 // window pass ride along.
                 auto score_loop = [&](auto walk_tag) {
                     constexpr bool WALK = decltype(walk_tag)::value;
-                    auto tile = [&](int jt, f32x4 (&T)[kTilesPerWave], f32x4 (&Tn)[kTilesPerWave]) {
-                        logits(min(jt + 1, njt - 1), Tn);
+                    // exponentials and sums of a relative logit tile; the
+                    // median walk's tiles ride along
+                    auto body = [&](int jt, f32x4 (&T)[kTilesPerWave]) {
                         f32x4 W0, W1;
                         if (WALK) walker.issue(X8, g, col, W0, W1);
-                        exp_transpose(T);
+                        const f32x4 va0 = *(const f32x4 *)(vt0 + jt * 16);
+                        const f32x4 va1 = *(const f32x4 *)(vt1 + jt * 16);
 #pragma unroll
-                        for (int mq = 0; mq < 4; ++mq) {
-                            const f32x4 va0 = *(const f32x4 *)(vt0 + jt * 16 + 4 * mq);
-                            const f32x4 va1 = *(const f32x4 *)(vt1 + jt * 16 + 4 * mq);
+                        for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                O4[0][r & 1] = __builtin_amdgcn_mfma_f32_4x4x1f32(va0[r], T[mq][r], O4[0][r & 1], 0, 0, 0);
-                                O4[1][r & 1] = __builtin_amdgcn_mfma_f32_4x4x1f32(va1[r], T[mq][r], O4[1][r & 1], 0, 0, 0);
+                            for (int r = 0; r < 4; ++r) T[q][r] = R::exp2_(T[q][r]);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int q = 0; q < kTilesPerWave; ++q) {
+                                O4[0][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(va0[r], T[q][r], O4[0][q], 0, 0, 0);
+                                O4[1][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(va1[r], T[q][r], O4[1][q], 0, 0, 0);
                             }
-                        }
                         if (WALK && !walker.done()) {
                             tracker.visit(W0, false, wregion);
                             if (walker.second()) tracker.visit(W1, false, wregion);
                             walker.advance(X8, g, col);
                         }
-                        rebase(Tn, false);
                     };
-                    f32x4 TA[kTilesPerWave], TB[kTilesPerWave];
-                    logits(0, TA);
-                    rebase(TA, true);
-                    for (int jt = 0; jt < njt; jt += 2) {
-                        progress_priority(jt, njt);
-                        tile(jt, TA, TB);
-                        if (jt + 1 < njt) tile(jt + 1, TB, TA);
+                    if (WALK) {
+                        // one buffer: the walk's registers leave no room for two
+                        f32x4 T[kTilesPerWave];
+                        logits(0, T);
+                        rebase(T, true);
+                        body(0, T);
+                        for (int jt = 1; jt < njt; ++jt) {
+                            if ((jt & 1) == 0) progress_priority(jt, njt);
+                            logits(jt, T);
+                            rebase(T, false);
+                            body(jt, T);
+                        }
+                    } else {
+                        // the logits of tile jt + 1 are issued (and checked)
+                        // around the exponentials and sums of tile jt
+                        auto tile = [&](int jt, f32x4 (&T)[kTilesPerWave], f32x4 (&Tn)[kTilesPerWave]) {
+                            logits(min(jt + 1, njt - 1), Tn);
+                            body(jt, T);
+                            rebase(Tn, false);
+                        };
+                        f32x4 TA[kTilesPerWave], TB[kTilesPerWave];
+                        logits(0, TA);
+                        rebase(TA, true);
+                        for (int jt = 0; jt < njt; jt += 2) {
+                            progress_priority(jt, njt);
+                            tile(jt, TA, TB);
+                            if (jt + 1 < njt) tile(jt + 1, TB, TA);
+                        }
                     }
                 };
                 if (tracker.active && !walker.done())
                     score_loop(std::true_type{});
                 else
                     score_loop(std::false_type{});
+                // lane l takes particle kbase + l: tile q = l / 16, summed
+                // over the four source quarters
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    osum[i] = O4[0][0][i] + O4[0][1][i];
-                    osum[4 + i] = O4[1][0][i] + O4[1][1][i];
+                    osum[i] = sum_quarters_scatter(O4[0][0][i], O4[0][1][i], O4[0][2][i], O4[0][3][i]);
+                    osum[4 + i] = sum_quarters_scatter(O4[1][0][i], O4[1][1][i], O4[1][2][i], O4[1][3][i]);
                 }
             }
             {
@@ -1009,20 +1021,17 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             // lane (col, g): target ibase + 16 q + col, coordinates g, 4 + g
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
-#pragma unroll
-                for (int gg = 0; gg < NG; ++gg)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) O4[gg][q][i] = sum_row_quarters(O4[gg][q][i]);
                 const int ii = ibase + 16 * q + col;
-                const float ksum = O4[NG - 1][q][kOne - 4 * (NG - 1)];
+                const float ksum = sum_row_quarters(O4[NG - 1][q][kOne - 4 * (NG - 1)]);
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2) {
                     const int c = g + 4 * h2;
                     float v = 0.f;
-                    if (h2 < NG && c < D) {
+                    if (h2 < NG) {
+                        // row c = 4 h2 + g: register g of the lane's row
                         const f32x4 &o = O4[h2 < NG ? h2 : 0][q];
-                        const float sv = g == 0 ? o[0] : g == 1 ? o[1] : g == 2 ? o[2] : o[3];
-                        v = (sv + c2 * X8[(long)ii * 8 + c] * ksum) * inv_n;
+                        const float sv = sum_quarters_scatter(o[0], o[1], o[2], o[3]);
+                        if (c < D) v = (sv + c2 * X8[(long)ii * 8 + c] * ksum) * inv_n;
                     }
                     phi[ts][q][h2] = v;
                 }

@@ -430,11 +430,49 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
     const T *row = A + (long)i * n_prev;
     ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};
     bool nan_seen = false;
-    for (int j = lane; j < n_prev; j += kWave) {
-        const T c = row[j] + phi_prev[j];
-        nan_seen |= (c != c);
-        if (j == lane) { ab.best = c; ab.arg = j; }
-        else argbest_push(ab, c, j);
+    // 16-byte loads, four per lane in flight (4 KB per wave), when the rows
+    // allow; each lane still visits its indices in ascending order, so the
+    // first maximum wins within a lane and the merge keeps the lowest index
+    constexpr int V = 16 / (int)sizeof(T);
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    const bool vec = n_prev % V == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)phi_prev % 16) == 0;
+    if (vec) {
+        const int nv = n_prev / V;
+        const vec_t *rv = (const vec_t *)row;
+        const vec_t *pv = (const vec_t *)phi_prev;
+        bool first = true;
+        for (int v0 = lane; v0 < nv; v0 += 4 * kWave) {
+            vec_t a4[4], p4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = v0 + u * kWave;
+                if (v < nv) {
+                    a4[u] = __builtin_nontemporal_load(rv + v);
+                    p4[u] = pv[v];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = v0 + u * kWave;
+                if (v < nv) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const T c = a4[u][e] + p4[u][e];
+                        const int j = v * V + e;
+                        nan_seen |= (c != c);
+                        if (first) { ab.best = c; ab.arg = j; first = false; }
+                        else argbest_push(ab, c, j);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int j = lane; j < n_prev; j += kWave) {
+            const T c = row[j] + phi_prev[j];
+            nan_seen |= (c != c);
+            if (j == lane) { ab.best = c; ab.arg = j; }
+            else argbest_push(ab, c, j);
+        }
     }
     ab = wave_argbest(ab);
     if (lane == 0) {

@@ -49,7 +49,7 @@ def announce(*what):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,n_prev", [(1, 1), (7, 1), (64, 64), (100, 37), (130, 257), (1024, 1024),
-                                      (1500, 700)])
+                                      (1500, 700), (50, 2050)])
 def test_viterbi_lattice_f64_bit_exact(n, n_prev):
     announce("viterbi lattice f64", n, n_prev)
     rng = np.random.default_rng(n * 1000 + n_prev)
@@ -73,23 +73,29 @@ def test_viterbi_lattice_f64_bit_exact(n, n_prev):
     assert smsq.device_status(ws) == smsq.OK
 
 
-def test_viterbi_lattice_nan_sets_status():
-    announce("viterbi lattice nan")
-    A = np.zeros((3, 5))
-    A[1, 3] = np.nan
+@pytest.mark.parametrize("n_prev", [5, 8])
+def test_viterbi_lattice_nan_sets_status(n_prev):
+    announce("viterbi lattice nan", n_prev)
+    A = np.zeros((3, n_prev))
+    A[1, n_prev - 2] = np.nan
     ws = smsq.workspace()
-    smsq.viterbi_step(None, "f64", 1, dev(np.zeros(5), torch.float64), lattice=dev(A, torch.float64),
+    smsq.viterbi_step(None, "f64", 1, dev(np.zeros(n_prev), torch.float64), lattice=dev(A, torch.float64),
                       loglik=dev(np.zeros(3), torch.float64), ws=ws)
     assert smsq.device_status(ws) == smsq.ERR_NONFINITE
 
 
-@pytest.mark.parametrize("n,n_prev", [(33, 65), (512, 512)])
+@pytest.mark.parametrize("n,n_prev", [(33, 65), (512, 512), (64, 4096), (300, 1028)])
 def test_viterbi_lattice_f32(n, n_prev):
     announce("viterbi lattice f32", n, n_prev)
     rng = np.random.default_rng(7 + n)
     A = (rng.normal(size=(n, n_prev)) * 5).astype(np.float32)
     ell = rng.normal(size=n).astype(np.float32)
     phi_prev = (rng.normal(size=n_prev) * 10).astype(np.float32)
+    # an exact tie across two lanes' vectors in row 0: the lower index wins
+    tie = n_prev > 260
+    if tie:
+        A[0, 3] = A[0, 260] = A[0].max() + 50.0
+        phi_prev[3] = phi_prev[260] = phi_prev.max()
     phi_o, psi_o, fl_o, _ = O.viterbi_lattice(A.astype(np.float64), ell.astype(np.float64),
                                               phi_prev.astype(np.float64), tie_tol=TIE_F32)
     phi, psi, fl = smsq.viterbi_step(None, "f32", 1, dev(phi_prev, torch.float32),
@@ -103,6 +109,8 @@ def test_viterbi_lattice_f32(n, n_prev):
     chosen = c[np.arange(n), psi]
     assert np.all(chosen >= best - 4 * TIE_F32 * np.maximum(1, np.abs(best)))
     assert np.allclose(phi, phi_o, rtol=1e-6, atol=1e-5)
+    if tie:
+        assert psi[0] == 3
 
 
 def _particle_case(name, n, n_prev, seed):

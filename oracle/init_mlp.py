@@ -25,7 +25,6 @@ from . import grad_loglik, loglik, transition_mean
 FEAT, HID, K, COMP = 64, 256, 8, 15
 OUT = K * COMP
 RHO_MIN, RHO_MAX = -7.0, 3.0
-FAMILY_SCALE = {0: 0.05, 1: 0.1, 2: 0.05, 3: 0.5}   # growth1d, range2d, cv4d, arm7
 
 # flattened parameter layout
 OFF_W1 = 0
@@ -61,7 +60,10 @@ def features(desc, t, x_prev, phi_prev, z, mask, n):
 
     best = lowest index of max phi_prev; a = f_t(x_prev[best]); M_j =
     f_t(x_prev[j]); population mean and variance of M over j; g and ll the
-    observation log-likelihood gradient and value at a."""
+    observation log-likelihood gradient and value at a.  No feature holds
+    the absolute position (only offsets from a, spreads and the likelihood
+    around a), so the proposal, placed relative to a, does not depend on
+    how far a sequence has moved."""
     d = desc.d
     x_prev = np.asarray(x_prev, dtype=np.float64).reshape(-1, d)
     phi = np.asarray(phi_prev, dtype=np.float64)
@@ -78,9 +80,8 @@ def features(desc, t, x_prev, phi_prev, z, mask, n):
     F[4] = np.log(n) / 7.0
     F[5:5 + d] = (mu - a) / s
     F[12:12 + d] = np.log(var / s ** 2 + 1e-6) / 8.0
-    F[19:19 + d] = a * FAMILY_SCALE[int(desc.kind)]
-    F[26:26 + d] = np.arcsinh(s * g) / 4.0
-    F[33] = np.arcsinh(ll) / 8.0
+    F[19:19 + d] = np.arcsinh(s * g) / 4.0
+    F[26] = np.arcsinh(ll) / 8.0
     av = np.zeros(8)
     sv = np.ones(8)
     av[:d] = a

@@ -73,11 +73,6 @@ struct InitExample {
     uint64_t seed;
 };
 
-__device__ __forceinline__ float family_scale(int code)
-{
-    return code == GROWTH1D ? 0.05f : code == RANGE2D ? 0.1f : code == CV4D ? 0.05f : 0.5f;
-}
-
 // Features of examples [0, count): one wave each.  Also the anchor a and
 // scale s per example ([8] each).
 template <int KIND, int D>
@@ -127,20 +122,19 @@ __device__ void init_features_one(const InitExample &e, float *F, uint16_t *Fb, 
     float g[D];
     Fm::grad(e.m, e.z, e.mask, a, g);
     const float ll = Fm::loglik(e.m, e.z, e.mask, a);
-    const float fs = family_scale(KIND);
-    // lane f writes feature f
+    // lane f writes feature f; none holds the absolute position (offsets
+    // from the anchor, spreads and the likelihood around it only)
     float v = 0.f;
     const int f = lane;
     if (f < 4) v = f == KIND ? 1.f : 0.f;
     else if (f == 4) v = logf((float)e.n) / 7.f;
-    else if (f == 33) v = asinhf(ll) / 8.f;
+    else if (f == 26) v = asinhf(ll) / 8.f;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const float s = e.m.sqrt_q[k];
         if (f == 5 + k) v = (mu[k] - a[k]) / s;
         if (f == 12 + k) v = logf(var[k] / (s * s) + 1e-6f) / 8.f;
-        if (f == 19 + k) v = a[k] * fs;
-        if (f == 26 + k) v = asinhf(s * g[k]) / 4.f;
+        if (f == 19 + k) v = asinhf(s * g[k]) / 4.f;
     }
     F[f] = v;
     Fb[f] = to_bf16(v);

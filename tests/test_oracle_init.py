@@ -105,9 +105,26 @@ def test_features_of_identical_particles():
     assert F[4] == pytest.approx(np.log(128) / 7.0, abs=1e-15)
     assert np.allclose(F[5:5 + d], 0.0, atol=1e-12)
     assert np.allclose(F[12:12 + d], np.log(1e-6) / 8.0, atol=1e-9)
-    assert np.allclose(F[19:19 + d], a_ref * 0.5, atol=0)
     g = O.grad_loglik(desc, wl.z[0, 1], None, a_ref)
-    assert np.allclose(F[26:26 + d], np.arcsinh(sq * g) / 4.0, atol=0)
+    assert np.allclose(F[19:19 + d], np.arcsinh(sq * g) / 4.0, atol=0)
+    ll = O.loglik(desc, wl.z[0, 1], None, a_ref)
+    assert F[26] == pytest.approx(np.arcsinh(ll) / 8.0, abs=1e-15)
     assert np.allclose(a[:d], a_ref, atol=0) and np.all(a[d:] == 0)
     assert np.allclose(s[:d], sq, atol=0)
-    assert np.all(F[34:] == 0.0)
+    assert np.all(F[27:] == 0.0)
+
+
+def test_features_do_not_depend_on_position():
+    """A rigid shift of the previous set moves the anchor but changes no
+    feature: range2d's transition mean commutes with the shift, and with every
+    observation masked out the likelihood summaries are zero at any anchor."""
+    wl = S.make_workload("range2d", B=1, seed=0, T=3)
+    desc = wl.model
+    rng = np.random.default_rng(2)
+    x = wl.truth[0, 1] + 0.1 * rng.normal(size=(8, desc.d))
+    phi = rng.normal(size=8)
+    mask = np.zeros(desc.n_obs, dtype=np.uint8)     # every observation masked out: g = 0, ll = 0
+    F1, a1, _ = M.features(desc, 2, x, phi, wl.z[0, 1], mask, 64)
+    F2, a2, _ = M.features(desc, 2, x + np.array([30.0, -12.0]), phi, wl.z[0, 1], mask, 64)
+    assert not np.allclose(a1, a2)
+    assert np.allclose(F1, F2, atol=1e-12)

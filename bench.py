@@ -57,7 +57,44 @@ def parse():
     p.add_argument("--lattice-batch", type=int, default=16)
     p.add_argument("--batched-seqs", type=int, default=1024, help="ragged-mix sequences (0: skip)")
     p.add_argument("--train-steps", type=int, default=4000)
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="first copy this many MiB device to device three times (calibrates HBM byte counters)")
     return p.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_mfma_arm7_n1024_d7_b256_traffic.md")
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 over the kernel sources (every file under csrc, by name)."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2312_08684_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hpp", ".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name: str, B: int, n: int, dt: str):
+    """HBM bytes per steady-state launch from the committed counter summary,
+    or None when it was taken on other kernel sources or another workload."""
+    if (name, B, n, dt) != ("arm7", 256, 1024, "f32") or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel sources sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(name: str):
@@ -164,6 +201,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     smsq.load()
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy probe: %d bytes read and written, 3 copies" % nbytes, file=sys.stderr, flush=True)
+        del src, dst
     name = args.workload
     wl = S.make_workload(name, B=args.batch, seed=0, T=args.T)
     desc, o = wl.model, wl.opts
@@ -238,7 +285,7 @@ def main():
         "sequences_per_s": B / (ms / 1e3),
         "counted_tflops": flops_total / (ms / 1e3) / 1e12,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(name, B, n, dt),
                      "kernel": ("k_step_mfma (fused SVGD iterations + forward recursion, FP32 matrix cores)"
                                 if dt == "f32" else "k_step (fused SVGD iterations + forward recursion, FP64)")
                      + ", steady-state launch",

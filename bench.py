@@ -11,10 +11,12 @@ whole-job Viterbi edge rate, the roofline of the dominant kernel (the fused
 step kernel, timed per launch with HIP events on the launch stream), a
 lattice-mode forward-recursion bandwidth figure, the CPU oracle timed on a
 bounded sample of the same workload, and (``batched``) a ragged mix of all
-four model families with uneven N and T run as batched plans: plain, plain
-at half the SVGD iterations, and the learned initialisation at half the
-iterations (trained first on plain runs of a separate mix), each against the
-full plain run's MAP log-posterior.
+four model families with uneven N and T (4096 sequences) run as batched
+plans: the plain method at the full iteration count (the reference MAP
+log-posterior of every sequence), then the plain method and the learned
+initialisation (trained first on plain runs of a separate, shorter mix) at
+fractions of the iterations, with the iterations each needs to match the
+reference.
 """
 from __future__ import annotations
 
@@ -55,8 +57,9 @@ def parse():
     p.add_argument("--cpu-baseline", type=int, default=1)
     p.add_argument("--lattice-n", type=int, default=4096)
     p.add_argument("--lattice-batch", type=int, default=16)
-    p.add_argument("--batched-seqs", type=int, default=1024, help="ragged-mix sequences (0: skip)")
+    p.add_argument("--batched-seqs", type=int, default=4096, help="ragged-mix sequences (0: skip)")
     p.add_argument("--train-steps", type=int, default=4000)
+    p.add_argument("--train-seqs", type=int, default=700, help="plain sequences whose steps train the proposal")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="first copy this many MiB device to device three times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -144,48 +147,71 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
             "bytes_per_launch": nbytes}
 
 
-def batched_mix(torch, smsq, count: int, train_steps: int):
+def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
     """Ragged mix (family uniform over the four, N from {32..1024}, T in
-    [50, 200]) as one batched plan per run, hipGraph replay, autotuned."""
+    [50, 200]) as one batched plan per run, hipGraph replay, autotuned.  The
+    plain method at the full iteration count gives the reference J of every
+    sequence; the plain method and the learned initialisation then run at
+    1/4, 1/2, 3/4 (and the learned one at all) of the iterations, and each
+    sequence's L' is the smallest fraction whose J matches the reference."""
     from paper_2312_08684_amd import learned as LI
     from paper_2312_08684_amd import scenarios as S
     spec = LI.mix(count, seed=11, T_lo=50, T_hi=200)
+    mx = LI.Mix(spec)
     pi = sum(n * T * S.PRESETS[f][2] for (f, n, T, _) in spec)   # particle-iterations at full L
-    plan, Jfull, t_full, _, _ = LI.run(spec, 1.0, tune=True)
+    plan, Jfull, t_full, _, _ = LI.run(mx, 1.0, tune=True)
     info = plan.info()
     del plan
-    _, Jhalf, t_half, _, _ = LI.run(spec, 0.5)
+    fracs = (0.25, 0.5, 0.75)
+    plain = {1.0: (Jfull, t_full)}
+    for f in fracs:
+        _, J, t, _, _ = LI.run(mx, f, warm=False)
+        plain[f] = (J, t)
     # proposal: trained on plain runs of a separate, shorter mix; gated per
     # family on a validation mix
     t0 = time.perf_counter()
-    tspec = LI.mix(320, seed=1, T_lo=20, T_hi=40)
-    tplan, _, _, tmodels, tseqs = LI.run(tspec, 1.0)
+    tspec = LI.mix(train_seqs, seed=1, T_lo=20, T_hi=40)
+    tplan, _, _, tmodels, tseqs = LI.run(tspec, 1.0, warm=False)
     ex = LI.examples(tplan, tspec, tseqs)
+    n_examples = len(ex)
     mlp = smsq.InitMLP(seed=5, max_batch=max(4096, count))
     losses = LI.train(mlp, tmodels, ex, steps=train_steps, batch=512, lr=1e-3, log_every=train_steps // 4)
     del tplan, ex
     gain = LI.choose_gate(mlp, LI.mix(64, seed=3, T_lo=50, T_hi=200), 0.5)
     gate = {f: g["use"] for f, g in gain.items()}
     t_train = time.perf_counter() - t0
-    _, Jl, t_l, _, _ = LI.run(spec, 0.5, mlp=mlp, gate=gate)
-    seqs = float(count)
+    learned = {}
+    for f in fracs + (1.0,):
+        _, J, t, _, _ = LI.run(mx, f, mlp=mlp, gate=gate, warm=False)
+        learned[f] = (J, t)
+    Lp = LI.iterations_to_match({f: v[0] for f, v in plain.items()}, Jfull, spec)
+    Ll = LI.iterations_to_match({f: v[0] for f, v in learned.items()}, Jfull, spec)
+    fam = np.array([sp[0] for sp in spec])
 
     def row(J, t, frac_L):
         per = {}
         for f in LI.FAMILIES:
-            idx = [i for i, sp in enumerate(spec) if sp[0] == f]
+            idx = np.flatnonzero(fam == f)
             per[f] = {"matched_frac": float(np.mean(LI.matched(J[idx], Jfull[idx], [spec[i] for i in idx]))),
                       "mean_J_gap": float(np.mean(J[idx] - Jfull[idx]))}
-        return {"seconds": t, "sequences_per_s": seqs / t, "particle_iters_per_s": pi * frac_L / t,
+        return {"seconds": t, "sequences_per_s": count / t, "particle_iters_per_s": pi * frac_L / t,
                 "matched_frac": float(np.mean(LI.matched(J, Jfull, spec))), "mean_J_gap": float(np.mean(J - Jfull)),
                 "per_family": per}
 
+    def lprime(Lx):
+        ok = ~np.isnan(Lx)
+        per = {f: {"mean": float(np.mean(Lx[(fam == f) & ok])) if np.any((fam == f) & ok) else None,
+                   "reached": float(np.mean(ok[fam == f]))} for f in LI.FAMILIES}
+        return {"mean": float(np.mean(Lx[ok])), "reached": float(np.mean(ok)), "per_family": per}
+
     return {"sequences": count, "families": "growth1d range2d cv4d arm7", "N": "32..1024", "T": "50..200",
             "workgroup_waves": info["waves"], "tuned_ms_per_step": info["tuned_ms"],
-            "plain_full_L": row(Jfull, t_full, 1.0), "plain_half_L": row(Jhalf, t_half, 0.5),
-            "learned_half_L": row(Jl, t_l, 0.5),
-            "learned": {"train_sequences": len(tspec), "train_T": "20..40", "train_steps": train_steps,
-                        "train_nll": losses, "gate_per_family": gain, "setup_seconds": t_train},
+            "plain": {str(f): row(J, t, f) for f, (J, t) in sorted(plain.items())},
+            "learned": {str(f): row(J, t, f) for f, (J, t) in sorted(learned.items())},
+            "iterations_to_match": {"fractions": [0.25, 0.5, 0.75, 1.0], "plain": lprime(Lp), "learned": lprime(Ll)},
+            "proposal": {"train_sequences": len(tspec), "train_T": "20..40", "train_examples": n_examples,
+                         "train_steps": train_steps, "train_nll": losses, "gate_per_family": gain,
+                         "setup_seconds": t_train},
             "match_rule": "J >= J_plain_full - 1e-3 max(|J_plain_full|, T)"}
 
 
@@ -293,7 +319,7 @@ def main():
         "viterbi_lattice": lat,
     }
     if args.batched_seqs > 0:
-        out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps)
+        out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(out), flush=True)

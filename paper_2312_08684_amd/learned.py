@@ -38,28 +38,47 @@ def mix(count: int, seed: int, T_lo: int, T_hi: int, n_choices: Sequence[int] = 
              int(rng.integers(T_lo, T_hi + 1)), int(seed) * 100000 + i) for i in range(count)]
 
 
+class Mix:
+    """Synthetic workloads of a mix with their models and device arrays,
+    built once and shared by every run of the mix."""
+
+    def __init__(self, spec):
+        self.spec = list(spec)
+        self.wls, self.models, self.data = [], [], []
+        for fam, n, T, sd in self.spec:
+            wl = S.make_workload(fam, B=1, seed=sd, n=n, T=T)
+            self.wls.append(wl)
+            self.models.append(smsq.Model(wl.model))
+            self.data.append({
+                "x0": torch.tensor(wl.x0[0], dtype=torch.float32, device="cuda"),
+                "z": torch.tensor(wl.z[0], dtype=torch.float32, device="cuda"),
+                "z_mask": (torch.tensor(wl.mask[0], dtype=torch.uint8, device="cuda")
+                           if wl.mask is not None else None)})
+
+    def __len__(self):
+        return len(self.spec)
+
+
 def build(spec, L_scale: float = 1.0, gate: Optional[Dict[str, bool]] = None):
-    """Models, options and sequence dicts of a mix; each family keeps its own
-    iteration count L (scaled by L_scale) and step size."""
-    models, opts, seqs = [], [], []
-    for i, (fam, n, T, sd) in enumerate(spec):
-        wl = S.make_workload(fam, B=1, seed=sd, n=n, T=T)
-        models.append(smsq.Model(wl.model))
+    """Models, options and sequence dicts of a mix (a spec list or a Mix);
+    each family keeps its own iteration count L (scaled by L_scale) and step
+    size."""
+    mx = spec if isinstance(spec, Mix) else Mix(spec)
+    opts, seqs = [], []
+    for i, ((fam, n, T, sd), wl) in enumerate(zip(mx.spec, mx.wls)):
         L = max(1, int(round(wl.opts.n_iter * L_scale)))
         opts.append(smsq.opts(L, wl.opts.step, wl.opts.bw_scale, 0, 0))
-        seqs.append({"model": i, "n": n, "seed": sd + 7,
-                     "use_proposal": 1 if (gate is None or gate.get(fam, False)) else 0,
-                     "x0": torch.tensor(wl.x0[0], dtype=torch.float32, device="cuda"),
-                     "z": torch.tensor(wl.z[0], dtype=torch.float32, device="cuda"),
-                     "z_mask": (torch.tensor(wl.mask[0], dtype=torch.uint8, device="cuda")
-                                if wl.mask is not None else None)})
-    return models, opts, seqs
+        seqs.append(dict(mx.data[i], model=i, n=n, seed=sd + 7,
+                         use_proposal=1 if (gate is None or gate.get(fam, False)) else 0))
+    return mx.models, opts, seqs
 
 
 def run(spec, L_scale: float = 1.0, mlp: Optional[smsq.InitMLP] = None, gate=None, use_graph: bool = True,
-        tune: bool = False):
-    """One timed run of a mix (after one untimed run that builds the graph).
-    Returns (plan, J [count], seconds, models, seqs)."""
+        tune: bool = False, warm: bool = True):
+    """One timed run of a mix (a spec list or a Mix), after one untimed run
+    that builds the graph (without `warm`, the timed run also captures it:
+    host work of milliseconds against seconds of GPU work).  Returns (plan,
+    J [count], seconds, models, seqs)."""
     models, opts, seqs = build(spec, L_scale, gate)
     plan = smsq.BatchPlan(models, opts, seqs)
     if tune:
@@ -67,8 +86,9 @@ def run(spec, L_scale: float = 1.0, mlp: Optional[smsq.InitMLP] = None, gate=Non
     if mlp is not None:
         plan.set_init(mlp)
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        plan.run(use_graph=use_graph, stream=stream)
+    if warm:
+        with torch.cuda.stream(stream):
+            plan.run(use_graph=use_graph, stream=stream)
     stream.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
@@ -84,7 +104,7 @@ def run(spec, L_scale: float = 1.0, mlp: Optional[smsq.InitMLP] = None, gate=Non
 def examples(plan: smsq.BatchPlan, spec, seqs) -> List[dict]:
     """Training examples (steps t >= 2) of a finished plain run."""
     ex = []
-    for i, (fam, n, T, sd) in enumerate(spec):
+    for i, (fam, n, T, sd) in enumerate(spec.spec if isinstance(spec, Mix) else spec):
         parts, phi, _ = plan.storage(i)
         for t in range(2, T + 1):
             ex.append({"model": i, "t": t, "x_prev": parts[t - 2], "phi_prev": phi[t - 2],
@@ -122,16 +142,17 @@ def choose_gate(mlp: smsq.InitMLP, spec, L_scale: float) -> Dict[str, dict]:
     the full-iteration plain J.  ``use`` = median gain > 0 and no loss of
     matched share; the median keeps a few far-drifted sequences from
     deciding for a family."""
+    spec = spec if isinstance(spec, Mix) else Mix(spec)
     _, Jf, _, _, _ = run(spec, 1.0)
     _, Jp, _, _, _ = run(spec, L_scale)
     _, Jl, _, _, _ = run(spec, L_scale, mlp=mlp, gate={f: True for f in FAMILIES})
     out = {}
     for f in FAMILIES:
-        idx = [i for i, sp in enumerate(spec) if sp[0] == f]
+        idx = [i for i, sp in enumerate(spec.spec) if sp[0] == f]
         if not idx:
             out[f] = {"use": False}
             continue
-        sub = [spec[i] for i in idx]
+        sub = [spec.spec[i] for i in idx]
         mp = float(np.mean(matched(Jp[idx], Jf[idx], sub)))
         ml = float(np.mean(matched(Jl[idx], Jf[idx], sub)))
         d = Jl[idx] - Jp[idx]
@@ -140,7 +161,16 @@ def choose_gate(mlp: smsq.InitMLP, spec, L_scale: float) -> Dict[str, dict]:
     return out
 
 
+def iterations_to_match(J_by_frac: Dict[float, np.ndarray], J_ref, spec) -> np.ndarray:
+    """Per sequence, the smallest fraction of the full iteration count whose
+    run matches the reference J (NaN where none of the runs does)."""
+    out = np.full(len(J_ref), np.nan)
+    for f in sorted(J_by_frac, reverse=True):
+        out[matched(J_by_frac[f], J_ref, spec)] = f
+    return out
+
+
 def matched(J, J_ref, spec, rel: float = 1e-3) -> np.ndarray:
     """J within rel * max(|J_ref|, T) of the reference (or above it)."""
-    T = np.array([sp[2] for sp in spec], dtype=np.float64)
+    T = np.array([sp[2] for sp in (spec.spec if isinstance(spec, Mix) else spec)], dtype=np.float64)
     return J >= J_ref - rel * np.maximum(np.abs(J_ref), T)

@@ -81,6 +81,7 @@ constexpr int kWinCap = 8192;     // capacity of the median window buffer (float
 constexpr int kWinRegion = kWinCap / kMaxWaves; // per-wave share of the window buffer
 constexpr int kWinTarget = 512;   // aimed-for number of distances in the window
 constexpr float kRescaleGap = 8.f; // log2 headroom before the softmax reference moves
+constexpr int kProgSlot = 48;      // first of the 16 wave-progress words in the reduction slots
 
 // LDS byte layout of the MFMA step workgroup.
 struct MfmaLds {
@@ -102,7 +103,7 @@ struct MfmaLds {
         off_win = o; o += (long)(kWinCap + 256) * 4;       // window buffer + its histogram
         off_z = o; o += align16((long)kMaxObs * 4);
         off_mask = o; o += 64;
-        off_red = o; o += 512;  // uint slots 0..63, float slots from byte 256
+        off_red = o; o += 512;  // uint slots 0..63 (48..63: wave progress), float slots from byte 256
         total = o;
     }
 };
@@ -535,20 +536,42 @@ struct MedianTracker {
     }
 };
 
-// Wave priority from progress through a pass of n tile steps (called every
-// second step): 3 in the first quarter down to 0 in the last.  The SIMD
-// arbiter otherwise favours the oldest wave, which then finishes a pass far
-// ahead of the others and leaves the tail of the pass to few waves.
-__device__ __forceinline__ void progress_priority(int step, int n)
-{
-    const int q = (step * 4) / n;
-    if (step == 0) __builtin_amdgcn_s_setprio(3);
-    else if (q != ((step - 2) * 4) / n) {
-        if (q == 1) __builtin_amdgcn_s_setprio(2);
-        else if (q == 2) __builtin_amdgcn_s_setprio(1);
-        else __builtin_amdgcn_s_setprio(0);
+// Wave priority from progress relative to the waves that share the SIMD
+// (waves w, w + 4, w + 8, w + 12 of a workgroup).  The SIMD arbiter serves
+// the oldest wave first among equal priorities, so without this a pass ends
+// in age order and its tail runs on one or two waves, too few to hide
+// latency.  Every second tile step a wave publishes its running count of
+// steps in LDS and reads its mates' counts; the read is only used at the
+// next call, so it never waits.  A wave ahead of its slowest mate yields:
+// priority 3 within 2 steps of it, 2 within 4, 1 within 8, else 0.
+struct ProgressBalance {
+    uint32_t *row, *own;  // the SIMD's four counts; this wave's count
+    uint32_t done;        // steps of this wave so far (all passes)
+    uint32_t s0, s1, s2, s3;
+
+    // prog: 16 LDS words set to ~0 (absent waves never lag) before a barrier
+    __device__ void init(uint32_t *prog, int wave)
+    {
+        row = prog + (wave & 3) * 4;
+        own = row + (wave >> 2);
+        done = 0;
+        s0 = s1 = s2 = s3 = 0;
     }
-}
+    __device__ void step()
+    {
+        done += 2;
+        const uint32_t mn = __builtin_amdgcn_readfirstlane(min(min(s0, s1), min(s2, s3)));
+        const uint32_t ahead = done - min(mn, done);
+        if (ahead <= 2) __builtin_amdgcn_s_setprio(3);
+        else if (ahead <= 4) __builtin_amdgcn_s_setprio(2);
+        else if (ahead <= 8) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+        *(volatile uint32_t *)own = done;
+        typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+        const u32x4_t p = *(const volatile u32x4_t *)row;
+        s0 = p[0]; s1 = p[1]; s2 = p[2]; s3 = p[3];
+    }
+};
 
 // One sequence's time step (b: its index in the strided batch of `a`).  The
 // workgroup owns the sequence: all state in LDS, every barrier block-wide.
@@ -606,6 +629,9 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     float *xg = a.x + (long)b * a.x_stride;
     const float inf = R::inf();
 
+    for (int o = tid; o < 16; o += nt) red[kProgSlot + o] = 0xffffffffu;
+    ProgressBalance bal;
+    bal.init(red + kProgSlot, wave);
     for (int o = tid; o < m.obs_dim; o += nt) sz[o] = a.z[(long)b * a.z_stride + o];
     const uint8_t *mk = nullptr;
     if (a.mask) {
@@ -851,7 +877,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         rebase(T, true);
                         body(0, T);
                         for (int jt = 1; jt < njt; ++jt) {
-                            if ((jt & 1) == 0) progress_priority(jt, njt);
+                            if ((jt & 1) == 0) bal.step();
                             logits(jt, T);
                             rebase(T, false);
                             body(jt, T);
@@ -868,7 +894,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         logits(0, TA);
                         rebase(TA, true);
                         for (int jt = 0; jt < njt; jt += 2) {
-                            progress_priority(jt, njt);
+                            bal.step();
                             tile(jt, TA, TB);
                             if (jt + 1 < njt) tile(jt + 1, TB, TA);
                         }
@@ -1014,7 +1040,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             f32x4 GA[kTilesPerWave], GB[kTilesPerWave];
             gram(0, GA);
             for (int kt = 0; kt < nkt; kt += 2) {
-                progress_priority(kt, nkt);
+                bal.step();
                 tile(kt, GA, GB);
                 if (kt + 1 < nkt) tile(kt + 1, GB, GA);
             }

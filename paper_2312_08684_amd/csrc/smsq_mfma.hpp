@@ -263,80 +263,58 @@ __device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregi
 }
 
 // Exact order statistic r of the values kept in the window buffer (same
-// layout as buffer_select), in one histogram pass: the key offsets
-// key - key_lo go to kBins bins (the top bits of the span), one wave finds
-// the bin holding rank r, gathers that bin's values into cand and ranks them
-// by comparison.  hist (kBins counters) must be zero on entry and visible to
-// all waves.  A bin with more than 64 values (heavy ties) falls back to
-// buffer_select.
+// layout as buffer_select).  whist holds their histogram over 256 bins of
+// (key - key_lo) >> shift, counted as the values were appended.  Wave 0
+// finds the bin holding rank r; every wave gathers that bin's values from
+// its own region into cand (positions from an LDS counter: the order does
+// not matter); wave 0 ranks the candidates by comparison.  A bin with more
+// than 64 values (heavy ties) falls back to buffer_select.  cand may alias
+// whist: the histogram is dead once the bin is known.
 __device__ float window_select(const float *buf, const uint32_t *wcnt, int nregions, uint32_t r, uint32_t key_lo,
-                               uint32_t key_hi, uint32_t *hist, uint32_t *red, float *cand, uint32_t *hist_small)
+                               uint32_t key_hi, uint32_t shift, uint32_t *whist, uint32_t *red, float *cand)
 {
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
-    const uint32_t span = key_hi - key_lo;
-    const int bits = span == 0 ? 1 : 32 - __clz(span);
-    constexpr int kBinBits = 11;
-    static_assert(kBins == 1 << kBinBits, "one bin per counter");
-    const int shift = bits > kBinBits ? bits - kBinBits : 0;
-    for (int w = wave; w < nregions; w += nwaves) {
-        const uint32_t c = wcnt[w];
-        for (uint32_t s = lane; s < c; s += kWave)
-            atomicAdd(&hist[(__float_as_uint(buf[w * kWinRegion + s]) - key_lo) >> shift], 1u);
-    }
-    __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
     if (wave == 0) {
-        constexpr int per = kBins / kWave;
-        uint32_t cnt = 0;
-        for (int q = 0; q < per; ++q) cnt += hist[lane * per + q];
+        typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+        const u32x4_t c = *(const u32x4_t *)(whist + lane * 4);
+        const uint32_t cnt = c[0] + c[1] + c[2] + c[3];
         const uint32_t incl = wave_incl_scan(cnt, lane);
         const uint32_t excl = incl - cnt;
         if (r >= excl && r < incl) {
             uint32_t rr = r - excl;
-            for (int q = 0; q < per; ++q) {
-                const uint32_t hq = hist[lane * per + q];
-                if (rr < hq) {
-                    red[2] = (uint32_t)(lane * per + q);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (rr < c[q]) {
+                    red[2] = (uint32_t)(lane * 4 + q);
                     red[3] = rr;
-                    red[4] = hq;
+                    red[4] = c[q];
                     break;
                 }
-                rr -= hq;
+                rr -= c[q];
             }
         }
+        if (lane == 0) red[6] = 0;
     }
     __syncthreads();
     const uint32_t bin = red[2], rr = red[3], cb = red[4];
-    if (cb > (uint32_t)kWave) return buffer_select(buf, wcnt, nregions, r, key_lo, key_hi, hist_small, red);
-    if (wave == 0) {
-        uint32_t base = 0;
-        for (int w = 0; w < nregions; ++w) {
-            const uint32_t c = wcnt[w];
-            for (uint32_t s0 = 0; s0 < c; s0 += kWave) {
-                const uint32_t s = s0 + lane;
-                float v = 0.f;
-                bool in = false;
-                if (s < c) {
-                    v = buf[w * kWinRegion + s];
-                    in = ((__float_as_uint(v) - key_lo) >> shift) == bin;
-                }
-                const unsigned long long mk = __builtin_amdgcn_ballot_w64(in);
-                if (in) cand[base + lanes_below(mk)] = v;
-                base += (uint32_t)__builtin_popcountll(mk);
-            }
+    if (cb > (uint32_t)kWave) return buffer_select(buf, wcnt, nregions, r, key_lo, key_hi, whist, red);
+    for (int w = wave; w < nregions; w += nwaves) {
+        const uint32_t c = wcnt[w];
+        for (uint32_t s = lane; s < c; s += kWave) {
+            const float v = buf[w * kWinRegion + s];
+            if (((__float_as_uint(v) - key_lo) >> shift) == bin) cand[atomicAdd(&red[6], 1u)] = v;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if ((uint32_t)lane < cb) {
-            const float v = cand[lane];
-            uint32_t less = 0, leq = 0;
-            for (uint32_t t = 0; t < cb; ++t) {
-                const float u = cand[t];
-                less += u < v ? 1u : 0u;
-                leq += u <= v ? 1u : 0u;
-            }
-            if (less <= rr && rr < leq) red[5] = __float_as_uint(v);
+    }
+    __syncthreads();
+    if (wave == 0 && (uint32_t)lane < cb) {
+        const float v = cand[lane];
+        uint32_t less = 0, leq = 0;
+        for (uint32_t t = 0; t < cb; ++t) {
+            const float u = cand[t];
+            less += u < v ? 1u : 0u;
+            leq += u <= v ? 1u : 0u;
         }
+        if (less <= rr && rr < leq) red[5] = __float_as_uint(v);
     }
     __syncthreads();
     return __uint_as_float(red[5]);
@@ -428,6 +406,8 @@ struct MedianTracker {
     float lo, hi;    // the window
     uint32_t below;  // per lane: distances below lo
     uint32_t kept;   // per wave: distances kept (kOverflow once the region is full)
+    uint32_t wshift; // window histogram bin of a kept distance: (key - key(lo)) >> wshift
+    uint32_t *whist; // its 256 counters (zero before the walk)
 
     __device__ void reset()
     {
@@ -437,8 +417,9 @@ struct MedianTracker {
     }
 
     // window of this iteration (active only with a previous median)
-    __device__ void plan()
+    __device__ void plan(uint32_t *hist256)
     {
+        whist = hist256;
         active = have >= 1 && med1 > 0.f;
         below = 0;
         kept = 0;
@@ -450,6 +431,9 @@ struct MedianTracker {
         w = fmax_(w, 2e-5f * med1);
         lo = uniform(fmax_(pred - w, 0.f));
         hi = uniform(pred + w);
+        const uint32_t span = __float_as_uint(hi) - __float_as_uint(lo);
+        const int bits = span == 0 ? 1 : 32 - __clz(span);
+        wshift = bits > 8 ? bits - 8 : 0;
     }
 
     static constexpr uint32_t kOverflow = 0x40000000u;
@@ -482,7 +466,10 @@ struct MedianTracker {
                 const unsigned long long mk = __builtin_amdgcn_ballot_w64(u[r] < span);
                 const uint32_t cnt = (uint32_t)__builtin_popcountll(mk);
                 const bool fits = kept + cnt <= (uint32_t)kWinRegion;  // kOverflow stays
-                if (fits && u[r] < span) region[kept + lanes_below(mk)] = Dv[r] + 0.f;  // no -0
+                if (fits && u[r] < span) {
+                    region[kept + lanes_below(mk)] = Dv[r] + 0.f;  // no -0
+                    atomicAdd(&whist[u[r] >> wshift], 1u);
+                }
                 kept = fits ? kept + cnt : kOverflow;
             }
         }
@@ -490,14 +477,13 @@ struct MedianTracker {
 
     // After every wave has visited its tiles (no barrier needed before the
     // call).  Returns the exact lower median.
-    __device__ float finish(const float *X8, int n, int npad, float *buf, uint32_t *hist_small,
-                            uint32_t *hist, uint32_t *red)
+    __device__ float finish(const float *X8, int n, int npad, float *buf, uint32_t *hist, uint32_t *red)
     {
         const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
         if (M == 0) return __builtin_nanf("");
         const uint32_t rank = (M - 1) / 2;
         const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id(), nwaves = nt >> 6;
-        // red[0..1] radix selection, red[2..5] window_select, red[8..9]
+        // red[0..1] radix selection, red[2..6] window_select, red[8..9]
         // buffer_select
         uint32_t *wcnt = red + 10;    // per-wave kept counts (red[10..25])
         uint32_t *wbelow = red + 26;  // per-wave below counts (red[26..41])
@@ -509,7 +495,6 @@ struct MedianTracker {
                 wbelow[wave] = bw;
                 wcnt[wave] = kept;
             }
-            for (int q = tid; q < kBins; q += nt) hist[q] = 0;
             __syncthreads();
             uint32_t cnt_lo = 0, n_in = 0;
             bool overflow = false;
@@ -520,8 +505,8 @@ struct MedianTracker {
             }
             density = uniform((float)n_in / (hi - lo));
             if (!overflow && rank >= cnt_lo && rank < cnt_lo + n_in) {
-                med = window_select(buf, wcnt, nwaves, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi),
-                                    hist, red, (float *)hist_small, hist_small);
+                med = window_select(buf, wcnt, nwaves, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi), wshift,
+                                    whist, red, (float *)whist);
                 done = true;
             }
             __syncthreads();
@@ -755,7 +740,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         // distances of the current particles; its window pass is spread over
         // the score pass, which leaves the particles unchanged
         const bool need_median = a.bw_mode == 0 || it == 0;
-        if (need_median) tracker.plan();
+        if (need_median) tracker.plan(whist);
         TileWalker walker;
         if (tracker.active) walker.start(X8, npad, g, col);
         float *wregion = WIN + wave * kWinRegion;
@@ -952,7 +937,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         }
         __syncthreads();
         if (need_median) {
-            const float med = tracker.finish(X8, n, npad, WIN, whist, hist, red);
+            const float med = tracker.finish(X8, n, npad, WIN, hist, red);
             h = uniform(bandwidth_from_median(med, n, a.bw_scale));
         }
         if (a.h_out && tid == 0) a.h_out[(long)b * a.h_stride + it] = h;
@@ -1065,6 +1050,9 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         }
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
+        // the window histogram starts the next walk at zero (the barrier at
+        // the end of the iteration orders this before it)
+        for (int q = tid; q < 256; q += nt) whist[q] = 0;
         // synchronous update, then unscaled squared norms for the next median
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {

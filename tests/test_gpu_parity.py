@@ -253,8 +253,13 @@ def test_svgd_step_vector_alu_kernel(name, n, n_prev, L, step, monkeypatch):
 
 
 @pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "one_particle",
-                                     "two_particles", "ragged_1025"])
+                                     "two_particles", "ragged_1025", "ties_16x16", "ties_4x64"])
 def test_svgd_step_variants(variant):
+    """Option and shape variants.  ties_GxC: C copies of each of G distinct
+    particles (identical particles stay identical under the update), so the
+    median distance has hundreds (16x16) or thousands (4x64) of exact copies:
+    the window selection meets a candidate bin over its limit or an
+    overflowing window buffer and takes its fallbacks."""
     announce("svgd variant", variant)
     name, n, n_prev, L, step = "range2d", 96, 50, 15, 0.005
     log_w, bw_scale, bw_mode, trans_mode = None, 1.0, 0, 0
@@ -264,7 +269,12 @@ def test_svgd_step_variants(variant):
         n = 2
     if variant == "ragged_1025":
         name, n, n_prev, L, step = "cv4d", 1025, 300, 3, 0.005
+    if variant.startswith("ties_"):
+        n, L = 256, 6
     wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 4, "f32")
+    if variant.startswith("ties_"):
+        groups, copies = (int(v) for v in variant[5:].split("x"))
+        x = np.repeat(x[:groups], copies, axis=0)
     if variant == "weights":
         rng = np.random.default_rng(3)
         log_w = np.log(rng.dirichlet(np.ones(n_prev))).astype(np.float32).astype(np.float64)

@@ -1,12 +1,14 @@
-// FP32 step kernel on the matrix cores (v_mfma_f32_16x16x4f32, wave64).
+// FP32 step kernel on the matrix cores (v_mfma_f32_16x16x4f32 and
+// v_mfma_f32_4x4x1f32, wave64).
 //
 // Same computation as k_step (one workgroup per sequence, state in LDS), with
 // the pairwise work of every SVGD iteration (eq. SVGD_newupdate) on MFMA:
 //   * bandwidth: the squared distances D_ik = n_i + n_k - 2 x_i . x_k come
 //     from 16x16 Gram tiles; the exact lower median is found by one pass that
 //     counts the distances below a window predicted from the previous
-//     iterations' medians and keeps those inside it, followed by a radix
-//     selection among the kept values (full radix selection as fallback);
+//     iterations' medians and keeps (and bins) those inside it, then a rank
+//     among the kept values of the median's bin (radix selections as
+//     fallbacks);
 //   * scores: the transition-mixture softmax over the previous particles,
 //     logit_kj = 2 mh_j . xh_k + c_j - |mh_j|^2 (log2 units; the common
 //     -|xh_k|^2 drops out), as 16x16 logit tiles [xh_k, 1] . [2 mh_j, c'_j],
@@ -16,7 +18,7 @@
 //   * Stein direction: Gram tiles give the kernel argument
 //     2 beta x_k . x_i - beta n_k (the norm rides in the free eighth
 //     K-column), kappa_ik = exp2(that - beta n_i) with beta = log2(e) / h,
-//     and sum_k kappa_ik [s_k, 1, x_k] is accumulated by MFMA.
+//     and sum_k kappa_ik [s_k - (2/h) x_k, 1] is accumulated by MFMA.
 // Particles are stored centred on the mean of the previous step's transition
 // means, which keeps |x|^2 small next to the squared distances in FP32.
 //
@@ -75,7 +77,6 @@ constexpr int kMaxWaves = 16;
 constexpr int kTilesPerWave = 4;  // register blocking: 64 particles per wave task
 constexpr int kMaxParticles = 1024;  // largest sequence the kernel takes
 // A workgroup of W waves takes up to W * TS tasks (TS task slots per wave).
-constexpr int kWaveScratch = 256; // floats of per-wave LDS scratch (one 16x16 tile)
 constexpr int kVtRows = 9;        // rows of the transition-mean table: 2 mh (7), 1, c'
 constexpr int kWinCap = 8192;     // capacity of the median window buffer (floats)
 constexpr int kWinRegion = kWinCap / kMaxWaves; // per-wave share of the window buffer
@@ -97,9 +98,7 @@ struct MfmaLds {
         off_s = o; o += align16((long)npad * 8 * 4);
         off_m = o; o += align16((long)kVtRows * nppad * 4);
         off_phip = o; o += align16((long)nppad * 4);
-        long scr = (long)nwaves * kWaveScratch * 4;
-        if (scr < (long)kBins * 4) scr = (long)kBins * 4;  // also the radix-selection histogram
-        off_scr = o; o += scr;
+        off_scr = o; o += (long)kBins * 4;  // the radix-selection histogram
         off_win = o; o += (long)(kWinCap + 256) * 4;       // window buffer + its histogram
         off_z = o; o += align16((long)kMaxObs * 4);
         off_mask = o; o += 64;
@@ -597,7 +596,6 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     float *S8 = (float *)(smem + L.off_s);     // [npad][8]  scores
     float *VT = (float *)(smem + L.off_m);     // [9][nppad] rows 2 mh_c (c < 7; 0 for c >= d), 1, c'_j
     float *PHP = (float *)(smem + L.off_phip); // [nppad] previous forward-recursion scores
-    float *SCR = (float *)(smem + L.off_scr);
     uint32_t *hist = (uint32_t *)(smem + L.off_scr);
     float *WIN = (float *)(smem + L.off_win);                    // median window buffer
     uint32_t *whist = (uint32_t *)(smem + L.off_win) + kWinCap;  // its histogram
@@ -731,7 +729,6 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     const int nkt = npad / 16;
     const float inv_n = 1.f / (float)n;
     float h = 1.f;
-    float *scr = SCR + wave * kWaveScratch;
     MedianTracker tracker;
     tracker.reset();
 

@@ -370,7 +370,7 @@ struct smsq_init_mlp_s {
         void *ps[] = {P, G, Mo, Ve, w1b, w2b, w3b, F, anc, scl, Fb, pre1, pre2, out, dout, d2, d1,
                       h1, h2, doutb, d2b, d1b, lossv};
         for (void *q : ps)
-            if (q) hipFree(q);
+            if (q) (void)hipFree(q);
     }
 };
 
@@ -481,13 +481,13 @@ struct smsq_batch_plan_s {
     }
     void free_all()
     {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         void *ps[] = {seqs, lists, items, codes, counters, status, parts, phis, psis, idx, init_ex, init_used};
         for (void *q : ps)
-            if (q) hipFree(q);
+            if (q) (void)hipFree(q);
     }
     // One step launch pair (prep + persistent step) for step t.
     smsq_status_t step(int t, hipStream_t s) const
@@ -850,7 +850,7 @@ smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t p, int steps, hipStream_t s
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return SMSQ_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return SMSQ_ERR_HIP;
     }
     const int shapes[2] = {16, 8};
@@ -871,8 +871,8 @@ smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t p, int steps, hipStream_t s
         }
         p->tuned[c] = ms / (k - 1);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != SMSQ_OK) return st;
     p->waves = p->tuned[1] < p->tuned[0] ? 8 : 16;
     return SMSQ_OK;
@@ -884,8 +884,8 @@ smsq_status_t smsq_batch_run(smsq_batch_plan_t p, int use_graph, hipStream_t str
     if (!use_graph) return p->enqueue(stream);
     if (stream == nullptr) return SMSQ_ERR_INVALID;
     if (!p->exec || p->graph_waves != p->waves || p->graph_mlp != p->mlp) {
-        if (p->exec) hipGraphExecDestroy(p->exec);
-        if (p->graph) hipGraphDestroy(p->graph);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
         p->exec = nullptr;
         p->graph = nullptr;
         if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SMSQ_ERR_HIP;
@@ -893,7 +893,7 @@ smsq_status_t smsq_batch_run(smsq_batch_plan_t p, int use_graph, hipStream_t str
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(stream, &g);
         if (st != SMSQ_OK || e != hipSuccess) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return st != SMSQ_OK ? st : SMSQ_ERR_HIP;
         }
         p->graph = g;
@@ -1062,7 +1062,7 @@ smsq_status_t smsq_init_set_create(const smsq_model_t *models, int n_models, con
     st->max_n = max_n;
     if (hipMalloc((void **)&st->ex, sizeof(InitExample) * count) != hipSuccess ||
         hipMemcpy(st->ex, h.data(), sizeof(InitExample) * count, hipMemcpyHostToDevice) != hipSuccess) {
-        if (st->ex) hipFree(st->ex);
+        if (st->ex) (void)hipFree(st->ex);
         delete st;
         return SMSQ_ERR_HIP;
     }
@@ -1073,7 +1073,7 @@ smsq_status_t smsq_init_set_create(const smsq_model_t *models, int n_models, con
 smsq_status_t smsq_init_set_destroy(smsq_init_set_t st)
 {
     if (!st) return SMSQ_ERR_INVALID;
-    if (st->ex) hipFree(st->ex);
+    if (st->ex) (void)hipFree(st->ex);
     delete st;
     return SMSQ_OK;
 }

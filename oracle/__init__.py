@@ -71,9 +71,12 @@ def lib():
             L.or_bandwidth.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double)]
             L.or_bandwidth.restype = C.c_double
             L.or_scores.argtypes = [M, C.c_int, _dp, _vp, _dp, _vp, C.c_int, _dp, C.c_int, _dp]
-            L.or_stein_phi.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, _dp]
+            L.or_kernel.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
+            L.or_stein_phi.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_int, _dp]
             L.or_svgd_step.argtypes = [M, C.c_int, C.c_int, _dp, _vp, _dp, _vp, C.c_int, _dp,
-                                       C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _vp]
+                                       C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                       _vp]
             L.or_viterbi_lattice.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, C.c_double,
                                              _dp, _ip, _u8]
             L.or_viterbi_particle.argtypes = [M, C.c_int, C.c_int, _dp, _dp, _dp, _vp, C.c_int,
@@ -87,7 +90,8 @@ def lib():
                                              C.c_uint32, _dp]
             L.or_run_sequence.argtypes = [M, C.c_int, C.c_int, _dp, _dp, _vp, C.c_uint64,
                                           C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_int,
-                                          C.c_int, _dp, C.POINTER(C.c_double), _vp, _vp, _vp, _vp]
+                                          C.c_int, C.c_int, _dp, C.POINTER(C.c_double), _vp, _vp,
+                                          _vp, _vp]
             _lib = L
     return _lib
 
@@ -191,16 +195,26 @@ def scores_from_means(desc, means, log_w, z, mask, x, trans_mode=0):
     return s
 
 
-def stein_phi(x, s, h):
+KERNEL_RBF, KERNEL_IMQ, KERNEL_MATERN = 0, 1, 2
+
+
+def kernel(kind, D, h):
+    """(f, w) of a kernel at squared distance D: kappa = f, grad_{x_k} kappa = w (x_i - x_k)."""
+    f, w = C.c_double(0.0), C.c_double(0.0)
+    lib().or_kernel(int(kind), float(D), float(h), C.byref(f), C.byref(w))
+    return f.value, w.value
+
+
+def stein_phi(x, s, h, kernel=KERNEL_RBF):
     x = _f64(x)
     s = _f64(s)
     phi = np.zeros_like(x)
-    lib().or_stein_phi(x.shape[0], x.shape[1], x, s, h, phi)
+    lib().or_stein_phi(x.shape[0], x.shape[1], x, s, h, int(kernel), phi)
     return phi
 
 
 def svgd_step(desc, t, x_prev, log_w, z, mask, x, n_iter, step, bw_scale=1.0,
-              bw_mode=0, trans_mode=0):
+              bw_mode=0, trans_mode=0, kernel=KERNEL_RBF):
     """Returns (updated particles, bandwidth per iteration, status)."""
     x_prev = _f64(x_prev).reshape(-1, desc.d)
     x = _f64(x).reshape(-1, desc.d).copy()
@@ -210,7 +224,7 @@ def svgd_step(desc, t, x_prev, log_w, z, mask, x, n_iter, step, bw_scale=1.0,
     st = lib().or_svgd_step(C.byref(model(desc)), t, x_prev.shape[0], x_prev,
                             None if lw is None else lw.ctypes.data, _f64(z), mp,
                             x.shape[0], x, n_iter, step, bw_scale, bw_mode, trans_mode,
-                            h.ctypes.data)
+                            int(kernel), h.ctypes.data)
     return x, h[:n_iter], st
 
 
@@ -271,7 +285,7 @@ def predictive_init(desc, t, x_prev, n, seed, seq):
 
 
 def run_sequence(desc, T, n, x0, z, mask, seed, seq, n_iter, step, bw_scale=1.0,
-                 bw_mode=0, trans_mode=0, want_tables=False):
+                 bw_mode=0, trans_mode=0, want_tables=False, kernel=KERNEL_RBF):
     """Algorithm 2 for one sequence.  Returns a dict."""
     d = desc.d
     mk, mp = _maskptr(mask)
@@ -282,7 +296,8 @@ def run_sequence(desc, T, n, x0, z, mask, seed, seq, n_iter, step, bw_scale=1.0,
     psi = np.zeros((T, n), dtype=np.int32) if want_tables else None
     idx = np.zeros(T, dtype=np.int32)
     st = lib().or_run_sequence(C.byref(model(desc)), T, n, _f64(x0), _f64(z), mp, seed, seq,
-                               n_iter, step, bw_scale, bw_mode, trans_mode, xmap, C.byref(J),
+                               n_iter, step, bw_scale, bw_mode, trans_mode, int(kernel), xmap,
+                               C.byref(J),
                                None if parts is None else parts.ctypes.data,
                                None if phi is None else phi.ctypes.data,
                                None if psi is None else psi.ctypes.data, idx.ctypes.data)

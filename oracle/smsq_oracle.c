@@ -25,7 +25,9 @@
  *                    eq. SVGD_newupdate; trans_mode 0 takes the gradient of
  *                    log sum_j w_j p(x | x_{t-1}^j), trans_mode 1 the paper's
  *                    literal average of the per-j gradients)
- *   or_stein_phi     Stein direction of eq. SVGD_newupdate / svgd_iterate
+ *   or_stein_phi     Stein direction of eq. SVGD_newupdate / svgd_iterate, with
+ *                    the RBF kernel or the IMQ and Matern kernels of the
+ *                    kernel ablation (Sec. V-E, Table VIII)
  *   or_svgd_step     Algorithm 2 steps 1) and 2): x <- x + eps * phi, L times
  *   or_viterbi_*     forward recursion, eq. forward_recursion
  *   or_backtrack     backtracking of Sec. IV-B / Algorithm 2 step 4)
@@ -416,18 +418,51 @@ void or_scores(const or_model *m, int n_prev, const double *means, const double 
     free(a);
 }
 
+/* Kernels of the Stein direction, functions f(D) of the squared distance
+ * D = |x_i - x_k|^2 and the bandwidth h (Sec. V-E compares the three; the
+ * paper names them and cites their sources without formulas, so the common
+ * forms are taken):
+ *   OR_KERNEL_RBF     f = exp(-D / h)                      (Sec. III)
+ *   OR_KERNEL_IMQ     f = (1 + D / h)^(-1/2)               inverse multiquadric
+ *   OR_KERNEL_MATERN  f = (1 + a) exp(-a), a = sqrt(3 D / h)   Matern, nu = 3/2
+ * The gradient with respect to x_k is f'(D) * 2 (x_k - x_i); or_kernel gives
+ * f and w = -2 f'(D), so that grad_{x_k} f = w (x_i - x_k):
+ *   RBF  w = (2 / h) f;   IMQ  w = (1 / h) f^3;   Matern  w = (3 / h) exp(-a). */
+#define OR_KERNEL_RBF 0
+#define OR_KERNEL_IMQ 1
+#define OR_KERNEL_MATERN 2
+
+void or_kernel(int kernel, double D, double h, double *f, double *w)
+{
+    if (kernel == OR_KERNEL_IMQ) {
+        double v = 1.0 / sqrt(1.0 + D / h);
+        *f = v;
+        *w = v * v * v / h;
+    } else if (kernel == OR_KERNEL_MATERN) {
+        double a = sqrt(3.0 * D / h);
+        double e = exp(-a);
+        *f = (1.0 + a) * e;
+        *w = 3.0 * e / h;
+    } else {
+        double v = exp(-D / h);
+        *f = v;
+        *w = 2.0 * v / h;
+    }
+}
+
 /* phi_i = (1/n) sum_k [ kappa_ik s_k + grad_{x_k} kappa_ik ],
- * kappa_ik = exp(-|x_i - x_k|^2 / h), grad_{x_k} kappa_ik = (2/h) kappa_ik (x_i - x_k). */
-void or_stein_phi(int n, int d, const double *x, const double *s, double h, double *phi)
+ * kappa_ik = f(|x_i - x_k|^2), grad_{x_k} kappa_ik = w_ik (x_i - x_k). */
+void or_stein_phi(int n, int d, const double *x, const double *s, double h, int kernel, double *phi)
 {
     for (int i = 0; i < n; ++i) {
         const double *xi = x + (size_t)i * d;
         double acc[OR_MAXD] = { 0 };
         for (int k = 0; k < n; ++k) {
             const double *xk = x + (size_t)k * d;
-            double kap = exp(-or_sqdist(xi, xk, d) / h);
+            double kap, w;
+            or_kernel(kernel, or_sqdist(xi, xk, d), h, &kap, &w);
             for (int c = 0; c < d; ++c)
-                acc[c] += kap * s[(size_t)k * d + c] + (2.0 / h) * kap * (xi[c] - xk[c]);
+                acc[c] += kap * s[(size_t)k * d + c] + w * (xi[c] - xk[c]);
         }
         for (int c = 0; c < d; ++c) phi[(size_t)i * d + c] = acc[c] / (double)n;
     }
@@ -446,7 +481,7 @@ static int all_finite(const double *v, size_t cnt)
 int or_svgd_step(const or_model *m, int t, int n_prev, const double *x_prev, const double *log_w,
                  const double *z, const uint8_t *mask, int n, double *x,
                  int n_iter, double step, double bw_scale, int bw_mode, int trans_mode,
-                 double *h_out)
+                 int kernel, double *h_out)
 {
     if (n <= 0 || n_prev <= 0 || n_iter < 0) return OR_INVALID;
     int d = m->d;
@@ -461,7 +496,7 @@ int or_svgd_step(const or_model *m, int t, int n_prev, const double *x_prev, con
         if (bw_mode == 0 || l == 0) h = or_bandwidth(x, n, d, bw_scale, NULL);
         if (h_out) h_out[l] = h;
         or_scores(m, n_prev, means, log_w, z, mask, n, x, trans_mode, s);
-        or_stein_phi(n, d, x, s, h, phi);
+        or_stein_phi(n, d, x, s, h, kernel, phi);
         for (size_t q = 0; q < nd; ++q) x[q] += step * phi[q];
     }
     free(means); free(s); free(phi);
@@ -607,7 +642,7 @@ void or_predictive_init(const or_model *m, int t, int n_prev, const double *x_pr
 int or_run_sequence(const or_model *m, int T, int n, const double *x0, const double *z,
                     const uint8_t *mask, uint64_t seed, uint32_t seq,
                     int n_iter, double step, double bw_scale, int bw_mode, int trans_mode,
-                    double *xmap, double *J, double *particles_out, double *phi_out,
+                    int kernel, double *xmap, double *J, double *particles_out, double *phi_out,
                     int32_t *psi_out, int32_t *idx_out)
 {
     if (T <= 0 || n <= 0) return OR_INVALID;
@@ -627,7 +662,7 @@ int or_run_sequence(const or_model *m, int T, int n, const double *x0, const dou
         double *xt = parts + nd * (size_t)(t - 1);
         or_predictive_init(m, t, n_prev, xprev, n, seed, seq, xt);
         int st = or_svgd_step(m, t, n_prev, xprev, NULL, zt, mt, n, xt, n_iter, step, bw_scale,
-                              bw_mode, trans_mode, NULL);
+                              bw_mode, trans_mode, kernel, NULL);
         if (st != OR_OK) status = st;
         st = or_viterbi_particle(m, t, n_prev, xprev, phiprev, zt, mt, n, xt, 0.0,
                                  phi + (size_t)n * (t - 1), psi + (size_t)n * (t - 1), NULL);

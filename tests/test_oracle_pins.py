@@ -266,6 +266,78 @@ def test_stein_repulsion_conserves_mean_and_is_equivariant():
     assert np.allclose(O.stein_phi(x @ R.T, np.zeros_like(x), h), phi @ R.T, atol=1e-13)
 
 
+KERNELS = [O.KERNEL_RBF, O.KERNEL_IMQ, O.KERNEL_MATERN]
+
+
+def test_kernel_special_values():
+    """Closed-form values of the three kernels of the kernel ablation
+    (Sec. V-E): every kernel is 1 at zero distance; RBF exp(-1) at D = h;
+    IMQ (1 + 3)^(-1/2) = 1/2 at D = 3h; Matern-3/2 2/e where
+    sqrt(3 D / h) = 1; the gradient weights at zero distance are the
+    curvatures 2/h, 1/h, 3/h."""
+    h = 0.8
+    for k, w0 in zip(KERNELS, (2 / h, 1 / h, 3 / h)):
+        f, w = O.kernel(k, 0.0, h)
+        assert f == 1.0 and w == pytest.approx(w0, rel=1e-15)
+    assert O.kernel(O.KERNEL_RBF, h, h)[0] == pytest.approx(math.exp(-1), rel=1e-15)
+    assert O.kernel(O.KERNEL_IMQ, 3 * h, h)[0] == pytest.approx(0.5, rel=1e-15)
+    assert O.kernel(O.KERNEL_MATERN, h / 3, h)[0] == pytest.approx(2 / math.e, rel=1e-15)
+
+
+@pytest.mark.parametrize("kind", KERNELS)
+def test_kernel_gradient_matches_finite_differences(kind):
+    """grad_{x_k} kappa(x_i, x_k) = w (x_i - x_k): against central finite
+    differences of the kernel value itself, in three dimensions."""
+    rng = np.random.default_rng(31 + kind)
+    h = 1.3
+    for _ in range(5):
+        xi, xk = rng.normal(size=3), rng.normal(size=3)
+        D = float(((xi - xk) ** 2).sum())
+        f, w = O.kernel(kind, D, h)
+        eps = 1e-6
+        fd = np.zeros(3)
+        for c in range(3):
+            e = np.zeros(3)
+            e[c] = eps
+            fp = O.kernel(kind, float(((xi - xk - e) ** 2).sum()), h)[0]
+            fm = O.kernel(kind, float(((xi - xk + e) ** 2).sum()), h)[0]
+            fd[c] = (fp - fm) / (2 * eps)
+        assert np.allclose(w * (xi - xk), fd, rtol=1e-7, atol=1e-10), (kind, w * (xi - xk), fd)
+
+
+@pytest.mark.parametrize("kind", KERNELS)
+def test_stein_kernels_conserve_mean_and_reduce_to_scores(kind):
+    """For every kernel: with zero scores the repulsion sums to zero over the
+    particles (the pair terms are antisymmetric); one particle moves along its
+    own score; coincident particles move along the mean score."""
+    rng = np.random.default_rng(40 + kind)
+    x = rng.normal(size=(25, 3))
+    phi = O.stein_phi(x, np.zeros_like(x), 0.9, kind)
+    assert np.abs(phi.sum(0)).max() < 1e-12 and np.abs(phi).max() > 1e-3
+    s = rng.normal(size=(1, 3))
+    assert np.array_equal(O.stein_phi(x[:1], s, 0.9, kind), s)
+    xs = np.ones((5, 3))
+    s = rng.normal(size=(5, 3))
+    assert np.allclose(O.stein_phi(xs, s, 0.9, kind), np.broadcast_to(s.mean(0), s.shape), rtol=1e-14)
+
+
+def test_stein_kernels_small_distance_limits():
+    """Near zero distance IMQ(h) ~ exp(-D / (2h)) and Matern-3/2(h) ~
+    exp(-3D / (2h)) to first order, so their repulsion matches the RBF
+    kernel's at bandwidth 2h and 2h/3 up to O(D/h) (IMQ) and O(sqrt(D/h))
+    (Matern: its expansion in a = sqrt(3D/h) has an a^3 term)."""
+    rng = np.random.default_rng(50)
+    h = 10.0
+    for scale in (1e-3, 1e-6):
+        x = scale * rng.normal(size=(12, 2))
+        rep = lambda kind, hh: O.stein_phi(x, np.zeros_like(x), hh, kind)
+        r = math.sqrt(3 * 8 * scale ** 2 / h)   # a bound on a over these pairs (|x| < 4 scale)
+        for kind, h_rbf, tol in ((O.KERNEL_IMQ, 2 * h, r * r), (O.KERNEL_MATERN, 2 * h / 3, r)):
+            a, b = rep(kind, h), rep(O.KERNEL_RBF, h_rbf)
+            err = np.abs(a - b).max() / np.abs(b).max()
+            assert err <= 4 * tol, (kind, scale, err, tol)
+
+
 def test_stein_kernel_weighted_score_term():
     # With all particles at one point kappa = 1 and the repulsion vanishes:
     # phi_i = mean_k s_k.

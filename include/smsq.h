@@ -87,6 +87,16 @@ typedef struct {
 
 typedef struct smsq_model_s *smsq_model_t;
 
+/* Kernel of the Stein direction (Sec. V-E ablation), functions of the squared
+ * distance D = |x_i - x_k|^2 and the bandwidth h:
+ *   SMSQ_KERNEL_RBF       exp(-D / h)                  (Sec. III; default)
+ *   SMSQ_KERNEL_IMQ       (1 + D / h)^(-1/2)           inverse multiquadric
+ *   SMSQ_KERNEL_MATERN32  (1 + a) exp(-a), a = sqrt(3 D / h)   Matern, nu = 3/2
+ * The paper names the three and cites their sources without formulas; these
+ * are the common forms (its printed nu = 2/3 read as 3/2).  IMQ and Matern
+ * run on the vector-ALU step kernel; batched plans take RBF only. */
+typedef enum { SMSQ_KERNEL_RBF = 0, SMSQ_KERNEL_IMQ = 1, SMSQ_KERNEL_MATERN32 = 2 } smsq_kernel_t;
+
 /* SVGD options (Sec. V set-up: fixed iteration count and step size).
  *  n_iter      iterations per time step (>= 0)
  *  step        step size epsilon of x <- x + epsilon phi (finite)
@@ -96,13 +106,15 @@ typedef struct smsq_model_s *smsq_model_t;
  *              1: h computed once from the initial particles of the step
  *  trans_mode  0: transition term of the score is grad_x log sum_j w_j
  *              p(x | x_{t-1}^j) (log-sum-exp over the previous particles);
- *              1: the equation's literal average of the per-j gradients. */
+ *              1: the equation's literal average of the per-j gradients.
+ *  kernel      smsq_kernel_t (0 = RBF; zero-initialised options keep RBF). */
 typedef struct {
     int n_iter;
     double step;
     double bw_scale;
     int bw_mode;
     int trans_mode;
+    int kernel;
 } smsq_svgd_opts_t;
 
 /* Validates a model description and copies it into an immutable handle.

@@ -181,7 +181,9 @@ smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int 
 template <>
 smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
 {
-    if (use_mfma(a.n, a.n_prev)) {
+    // the matrix-core kernel runs the RBF kernel; IMQ and Matern take the
+    // vector-ALU kernel
+    if (a.kernel == 0 && use_mfma(a.n, a.n_prev)) {
         switch (d.kind) {
         case SMSQ_MODEL_GROWTH1D: return launch_mfma_kd<GROWTH1D, 1>(a, batch, s);
         case SMSQ_MODEL_RANGE2D: return launch_mfma_kd<RANGE2D, 2>(a, batch, s);
@@ -235,7 +237,8 @@ smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<dou
 bool opts_ok(const smsq_svgd_opts_t *o)
 {
     return o && o->n_iter >= 0 && std::isfinite(o->step) && finite_pos(o->bw_scale) &&
-           (o->bw_mode == 0 || o->bw_mode == 1) && (o->trans_mode == 0 || o->trans_mode == 1);
+           (o->bw_mode == 0 || o->bw_mode == 1) && (o->trans_mode == 0 || o->trans_mode == 1) &&
+           o->kernel >= SMSQ_KERNEL_RBF && o->kernel <= SMSQ_KERNEL_MATERN32;
 }
 
 uint32_t *status_ptr(void *ws) { return reinterpret_cast<uint32_t *>(ws); }
@@ -269,6 +272,7 @@ smsq_status_t step_typed(const smsq_model_desc_t &d, int batch, int t, int n_pre
     a.n_iter = opts ? opts->n_iter : 0;
     a.bw_mode = opts ? opts->bw_mode : 0;
     a.trans_mode = opts ? opts->trans_mode : 0;
+    a.kernel = opts ? opts->kernel : 0;
     a.init_given = init_given;
     a.do_svgd = do_svgd ? 1 : 0;
     a.do_viterbi = do_viterbi ? 1 : 0;
@@ -735,8 +739,10 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     if (!out) return SMSQ_ERR_INVALID;
     *out = nullptr;
     if (!models || !opts || n_models < 1 || !seqs || count < 1) return SMSQ_ERR_INVALID;
-    for (int k = 0; k < n_models; ++k)
+    for (int k = 0; k < n_models; ++k) {
         if (!models[k] || !opts_ok(&opts[k])) return SMSQ_ERR_INVALID;
+        if (opts[k].kernel != SMSQ_KERNEL_RBF) return SMSQ_ERR_UNSUPPORTED;  // the plan's step body is RBF
+    }
     long lds = 0;
     int T_max = 0, max_n = 0;
     size_t n_parts = 0, n_phi = 0, n_T = 0;

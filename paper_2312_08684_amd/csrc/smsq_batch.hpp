@@ -65,6 +65,7 @@ __global__ void k_batch_prep(const SeqDesc *__restrict__ seqs, const int *__rest
     a.bw_mode = s.bw_mode;
     a.trans_mode = s.trans_mode;
     a.init_given = 0;  // the learned proposal, when used, sets it per step
+    a.kernel = 0;
     a.do_svgd = 1;
     a.do_viterbi = 1;
     a.step = s.step;

@@ -8,8 +8,10 @@
 //   (2) per-particle score: observation gradient plus the log-sum-exp
 //       transition-mixture gradient, with an online (running-max) softmax
 //       over the previous particles,
-//   (3) Stein direction phi_i = (1/N) sum_k kappa_ik [s_k + (2/h)(x_i - x_k)],
-//       then x_i += eps phi_i for all i at once,
+//   (3) Stein direction phi_i = (1/N) sum_k [kappa_ik s_k + w_ik (x_i - x_k)]
+//       with the RBF kernel kappa = exp(-D/h), w = (2/h) kappa, or the IMQ
+//       and Matern-3/2 kernels of the kernel ablation (stein_kernel), then
+//       x_i += eps phi_i for all i at once,
 // and after the iterations the forward-recursion row of every particle
 // (eq. forward_recursion) is a max-plus reduction over the previous step.
 #pragma once
@@ -20,6 +22,27 @@ namespace smsq {
 
 constexpr int kBins = 2048;          // radix-select histogram (11-bit digits)
 constexpr int kMaxRowsPerThread = 2; // particles owned by one thread in the Stein pass
+
+// IMQ (kernel 1) and Matern-3/2 (kernel 2) kernels of the kernel ablation
+// (Sec. V-E) at squared distance dd: kap = f(dd), and w with
+// grad_{x_k} kappa(x_i, x_k) = w (x_i - x_k), i.e. w = -2 f'(dd):
+//   IMQ     f = (1 + dd/h)^(-1/2),                w = f^3 / h
+//   Matern  f = (1 + a) e^(-a), a = sqrt(3 dd/h),  w = 3 e^(-a) / h
+template <typename T>
+__device__ __forceinline__ void stein_kernel(int kernel, T dd, T inv_h, T &kap, T &w)
+{
+    using R = RealOps<T>;
+    if (kernel == 1) {
+        const T v = (T)1 / R::sqrt_((T)1 + dd * inv_h);
+        kap = v;
+        w = v * v * v * inv_h;
+    } else {
+        const T av = R::sqrt_((T)3 * dd * inv_h);
+        const T e = R::exp_(-av);
+        kap = ((T)1 + av) * e;
+        w = (T)3 * e * inv_h;
+    }
+}
 constexpr int kMaxObs = 32;
 
 enum : uint32_t { STATUS_NONFINITE = 4u };
@@ -39,6 +62,7 @@ template <typename T> struct StepArgs {
     T *h_out; long h_stride;                // may be null
     uint32_t *status;
     int n_prev, n, t, n_iter, bw_mode, trans_mode, init_given, do_svgd, do_viterbi;
+    int kernel;  // Stein kernel: 0 RBF, 1 IMQ, 2 Matern-3/2 (the matrix-core kernel takes 0 only)
     T step, bw_scale, tie_tol;
     uint64_t seed; uint32_t seq_offset;
 };
@@ -328,6 +352,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
         // (3) Stein direction and synchronous update
         const T beta = (T)kLog2e / h;
         const T c2 = (T)2 / h;
+        const T inv_h = (T)1 / h;
         T phi[kMaxRowsPerThread][D];
 #pragma unroll
         for (int r = 0; r < kMaxRowsPerThread; ++r) {
@@ -345,12 +370,19 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
                 T df[D], dd = 0;
 #pragma unroll
                 for (int c = 0; c < D; ++c) { df[c] = xi[c] - xk[c]; dd += df[c] * df[c]; }
-                const T kap = R::exp2_(-beta * dd);
+                T kap, w;
+                if (a.kernel == 0) {
+                    kap = R::exp2_(-beta * dd);
+                    w = kap;  // times 2/h below
+                } else {
+                    stein_kernel<T>(a.kernel, dd, inv_h, kap, w);
+                }
 #pragma unroll
-                for (int c = 0; c < D; ++c) { as[c] += kap * sk[c]; ar[c] += kap * df[c]; }
+                for (int c = 0; c < D; ++c) { as[c] += kap * sk[c]; ar[c] += w * df[c]; }
             }
+            const T cw = a.kernel == 0 ? c2 : (T)1;
 #pragma unroll
-            for (int c = 0; c < D; ++c) phi[r][c] = (as[c] + c2 * ar[c]) * inv_n;
+            for (int c = 0; c < D; ++c) phi[r][c] = (as[c] + cw * ar[c]) * inv_n;
         }
         __syncthreads();
 #pragma unroll

@@ -143,3 +143,7 @@ def test_batch_plan_argument_errors():
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan(lg, [smsq.opts_from(wl.opts)], [q])
     assert e.value.status == smsq.ERR_UNSUPPORTED
+    imq = [smsq.opts(o.n_iter, o.step, o.bw_scale, kernel="imq") for o in opts]   # plans run the RBF kernel
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.BatchPlan(models, imq, seqs)
+    assert e.value.status == smsq.ERR_UNSUPPORTED

@@ -202,9 +202,9 @@ def _svgd_case(name, n, n_prev, seed, dt):
     return wl, desc, xp, x, z, mask
 
 
-def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mode=0, trans_mode=0):
+def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mode=0, trans_mode=0, kernel=0):
     td = tdt(dt)
-    xo, ho, st = O.svgd_step(desc, 2, xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode)
+    xo, ho, st = O.svgd_step(desc, 2, xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode, kernel)
     assert st == O.OK
     model = smsq.Model(desc)
     xg = dev(x, td)
@@ -212,7 +212,7 @@ def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mod
     ws = smsq.workspace()
     smsq.svgd_step(model, dt, 2, dev(xp, td), None if log_w is None else dev(log_w, td), dev(z, td),
                    None if mask is None else dev(mask, torch.uint8), xg,
-                   smsq.opts(L, step, bw_scale, bw_mode, trans_mode), h_out=hg, ws=ws)
+                   smsq.opts(L, step, bw_scale, bw_mode, trans_mode, kernel), h_out=hg, ws=ws)
     assert smsq.device_status(ws) == smsq.OK
     xg, hg = host(xg).astype(np.float64), host(hg).astype(np.float64)[:L]
     rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
@@ -287,6 +287,28 @@ def test_svgd_step_variants(variant):
     _compare_svgd(desc, "f32", xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode)
 
 
+KERNEL_CASES = [
+    ("growth1d", 32, 32, 100, 0.05, "f64"),
+    ("growth1d", 10, 10, 100, 0.05, "f64"),
+    ("growth1d", 40, 40, 100, 0.05, "f32"),
+    ("range2d", 257, 200, 20, 0.005, "f32"),
+    ("cv4d", 130, 64, 20, 0.005, "f64"),
+    ("arm7", 200, 129, 20, 1e-5, "f32"),
+]
+
+
+@pytest.mark.parametrize("kernel", ["imq", "matern32"])
+@pytest.mark.parametrize("name,n,n_prev,L,step,dt", KERNEL_CASES)
+def test_svgd_step_kernel_ablation(kernel, name, n, n_prev, L, step, dt):
+    """The IMQ and Matern-3/2 kernels of the kernel ablation (vector-ALU step
+    kernel) against the oracle, at the ablation's particle counts and larger."""
+    announce("svgd step kernel", kernel, name, n, n_prev, L, dt)
+    wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 23, dt)
+    k = smsq.KERNELS[kernel]
+    for bw_scale in (0.5, 3.0) if name == "growth1d" else (1.0,):
+        _compare_svgd(desc, dt, xp, None, z, mask, x, L, step, bw_scale=bw_scale, kernel=k)
+
+
 def test_svgd_step_full_arm7_shape():
     """N = 1024, d = 7, 100 iterations: the arm workload's step at full size."""
     announce("svgd step full arm7 1024x7 L=100")
@@ -323,6 +345,25 @@ def test_run_sequence_growth1d_full_f64():
     xmap, J = host(xmap), float(host(J)[0])
     dJ = abs(J - res["J"]) / max(abs(res["J"]), wl.T)
     print("J gpu %.10f oracle %.10f rel %.3e  max|dx| %.3e" % (J, res["J"], dJ, np.abs(xmap - res["xmap"]).max()))
+    assert dJ <= TOL_J
+    assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("kernel", ["imq", "matern32"])
+def test_run_sequence_growth1d_kernels_f64(kernel):
+    """Algorithm 2 with the ablation's kernels, 1-D growth model at N = 10."""
+    announce("run_sequence growth1d f64", kernel)
+    wl = S.make_workload("growth1d", B=1, seed=1003, n=10, T=30)
+    desc = wl.model
+    o = wl.opts
+    k = smsq.KERNELS[kernel]
+    res = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 78, 0, o.n_iter, o.step, kernel=k)
+    model = smsq.Model(desc)
+    xmap, J = smsq.run_sequence(model, "f64", dev(wl.x0[0], torch.float64), dev(wl.z[0], torch.float64),
+                                None, wl.n, smsq.opts(o.n_iter, o.step, kernel=k), 78)
+    xmap, J = host(xmap), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), wl.T)
+    print("J gpu %.10f oracle %.10f rel %.3e" % (J, res["J"], dJ))
     assert dJ <= TOL_J
     assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
 
@@ -425,3 +466,7 @@ def test_argument_errors():
     bad.d = 3
     with pytest.raises(smsq.SmsqError):
         smsq.Model(bad)
+    with pytest.raises(smsq.SmsqError) as e:   # no such kernel
+        smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None, x,
+                       smsq.opts(2, 0.1, kernel=3))
+    assert e.value.status == smsq.ERR_INVALID

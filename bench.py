@@ -10,7 +10,8 @@ Printed as one JSON line: SVGD particle-iterations per second (value), the
 whole-job Viterbi edge rate, the roofline of the dominant kernel (the fused
 step kernel, timed per launch with HIP events on the launch stream), a
 lattice-mode forward-recursion bandwidth figure, the CPU oracle timed on a
-bounded sample of the same workload, and (``batched``) a ragged mix of all
+bounded sample of the same workload, the kernel / bandwidth / particle-count
+ablation grid on the 1-D growth model (``kernel_ablation``), and (``batched``) a ragged mix of all
 four model families with uneven N and T (4096 sequences) run as batched
 plans: the plain method at the full iteration count (the reference MAP
 log-posterior of every sequence), then the plain method and the learned
@@ -60,6 +61,7 @@ def parse():
     p.add_argument("--batched-seqs", type=int, default=4096, help="ragged-mix sequences (0: skip)")
     p.add_argument("--train-steps", type=int, default=4000)
     p.add_argument("--train-seqs", type=int, default=700, help="plain sequences whose steps train the proposal")
+    p.add_argument("--ablation-mc", type=int, default=50, help="sequences per kernel-ablation row (0: skip)")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="first copy this many MiB device to device three times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -145,6 +147,42 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
     return {"n": n, "lattices": batch, "edges_per_s": n * n / sec, "us_per_launch": sec * 1e6,
             "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM,
             "bytes_per_launch": nbytes}
+
+
+# Kernel / bandwidth / particle-count grid of the kernel ablation (Sec. V-E,
+# Table VIII) on the 1-D growth model: (kernel, bandwidth scale, N).
+ABLATION_GRID = [("rbf", 1.0, 10), ("imq", 1.0, 10), ("matern32", 1.0, 10),
+                 ("rbf", 0.5, 10), ("rbf", 3.0, 10), ("rbf", 0.5, 40), ("rbf", 3.0, 40),
+                 ("rbf", 1.0, 20), ("rbf", 1.0, 40), ("imq", 1.0, 20), ("imq", 1.0, 40),
+                 ("matern32", 1.0, 20), ("matern32", 1.0, 40)]
+
+
+def kernel_ablation(torch, smsq, mc: int):
+    """The ablation grid on synthetic 1-D growth sequences (FP64, T = 50,
+    L = 100, eps = 0.05), mc Monte-Carlo sequences per row in one batched
+    run: RMSE of the MAP trajectory against the simulated truth, mean J, and
+    the GPU rate."""
+    from paper_2312_08684_amd import scenarios as S
+    rows = []
+    for kernel, bw, n in ABLATION_GRID:
+        wl = S.make_workload("growth1d", B=mc, seed=3000, n=n)
+        o = wl.opts
+        model = smsq.Model(wl.model)
+        x0 = torch.tensor(wl.x0, dtype=torch.float64, device="cuda")
+        z = torch.tensor(wl.z, dtype=torch.float64, device="cuda")
+        so = smsq.opts(o.n_iter, o.step, bw, kernel=kernel)
+        smsq.run_batch(model, "f64", x0, z, None, n, so, 5)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xmap, J = smsq.run_batch(model, "f64", x0, z, None, n, so, 5)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = xmap.cpu().numpy()[:, 1:] - wl.truth[:, 1:]
+        rows.append({"kernel": kernel, "bw_scale": bw, "N": n, "rmse": float(np.sqrt(np.mean(err ** 2))),
+                     "mean_J": float(J.mean().item()), "seconds": dt,
+                     "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
+    return {"model": "growth1d (1-D nonstationary growth), FP64, T=50, L=100, eps=0.05",
+            "sequences_per_row": mc, "rows": rows}
 
 
 def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
@@ -318,6 +356,8 @@ def main():
                      "kernel_avg_ms": k_avg_ms, "flops_per_launch": flops_launch},
         "viterbi_lattice": lat,
     }
+    if args.ablation_mc > 0:
+        out["kernel_ablation"] = kernel_ablation(torch, smsq, args.ablation_mc)
     if args.batched_seqs > 0:
         out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs)
     if args.cpu_baseline:

@@ -107,7 +107,14 @@ typedef enum { SMSQ_KERNEL_RBF = 0, SMSQ_KERNEL_IMQ = 1, SMSQ_KERNEL_MATERN32 = 
  *  trans_mode  0: transition term of the score is grad_x log sum_j w_j
  *              p(x | x_{t-1}^j) (log-sum-exp over the previous particles);
  *              1: the equation's literal average of the per-j gradients.
- *  kernel      smsq_kernel_t (0 = RBF; zero-initialised options keep RBF). */
+ *  kernel      smsq_kernel_t (0 = RBF; zero-initialised options keep RBF).
+ *  weights     mixture weights w_j of the previous particles in the
+ *              transition term (trans_mode 0): 0 uniform (or log_w_prev where
+ *              a call takes it); 1 w_j proportional to exp(phi_{t-1}(j)), the
+ *              previous step's forward-recursion scores, in the drivers that
+ *              hold them (smsq_batch_step, smsq_run_batch, smsq_run_sequence,
+ *              batched plans): the step's target is conditioned on the MAP
+ *              recursion so far.  smsq_svgd_step takes log_w_prev as given. */
 typedef struct {
     int n_iter;
     double step;
@@ -115,6 +122,7 @@ typedef struct {
     int bw_mode;
     int trans_mode;
     int kernel;
+    int weights;
 } smsq_svgd_opts_t;
 
 /* Validates a model description and copies it into an immutable handle.

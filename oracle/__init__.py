@@ -90,8 +90,8 @@ def lib():
                                              C.c_uint32, _dp]
             L.or_run_sequence.argtypes = [M, C.c_int, C.c_int, _dp, _dp, _vp, C.c_uint64,
                                           C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_int,
-                                          C.c_int, C.c_int, _dp, C.POINTER(C.c_double), _vp, _vp,
-                                          _vp, _vp]
+                                          C.c_int, C.c_int, C.c_int, _dp, C.POINTER(C.c_double), _vp,
+                                          _vp, _vp, _vp]
             _lib = L
     return _lib
 
@@ -285,8 +285,10 @@ def predictive_init(desc, t, x_prev, n, seed, seq):
 
 
 def run_sequence(desc, T, n, x0, z, mask, seed, seq, n_iter, step, bw_scale=1.0,
-                 bw_mode=0, trans_mode=0, want_tables=False, kernel=KERNEL_RBF):
-    """Algorithm 2 for one sequence.  Returns a dict."""
+                 bw_mode=0, trans_mode=0, want_tables=False, kernel=KERNEL_RBF, weights=0):
+    """Algorithm 2 for one sequence.  Returns a dict.  weights 1: the previous
+    step's forward-recursion scores are the mixture log-weights of the next
+    step's target (w_j proportional to exp(phi_{t-1}(j)))."""
     d = desc.d
     mk, mp = _maskptr(mask)
     xmap = np.zeros((T + 1, d))
@@ -296,8 +298,8 @@ def run_sequence(desc, T, n, x0, z, mask, seed, seq, n_iter, step, bw_scale=1.0,
     psi = np.zeros((T, n), dtype=np.int32) if want_tables else None
     idx = np.zeros(T, dtype=np.int32)
     st = lib().or_run_sequence(C.byref(model(desc)), T, n, _f64(x0), _f64(z), mp, seed, seq,
-                               n_iter, step, bw_scale, bw_mode, trans_mode, int(kernel), xmap,
-                               C.byref(J),
+                               n_iter, step, bw_scale, bw_mode, trans_mode, int(kernel), int(weights),
+                               xmap, C.byref(J),
                                None if parts is None else parts.ctypes.data,
                                None if phi is None else phi.ctypes.data,
                                None if psi is None else psi.ctypes.data, idx.ctypes.data)

@@ -32,7 +32,9 @@
  *   or_viterbi_*     forward recursion, eq. forward_recursion
  *   or_backtrack     backtracking of Sec. IV-B / Algorithm 2 step 4)
  *   or_path_score    trajectory score J(s) of Theorem IV.1
- *   or_run_sequence  Algorithm 2 end to end
+ *   or_run_sequence  Algorithm 2 end to end (weights 1: the previous step's
+ *                    forward-recursion scores as the mixture log-weights,
+ *                    w_j proportional to exp(phi_{t-1}(j)))
  */
 #include <math.h>
 #include <stdint.h>
@@ -642,7 +644,7 @@ void or_predictive_init(const or_model *m, int t, int n_prev, const double *x_pr
 int or_run_sequence(const or_model *m, int T, int n, const double *x0, const double *z,
                     const uint8_t *mask, uint64_t seed, uint32_t seq,
                     int n_iter, double step, double bw_scale, int bw_mode, int trans_mode,
-                    int kernel, double *xmap, double *J, double *particles_out, double *phi_out,
+                    int kernel, int weights, double *xmap, double *J, double *particles_out, double *phi_out,
                     int32_t *psi_out, int32_t *idx_out)
 {
     if (T <= 0 || n <= 0) return OR_INVALID;
@@ -661,7 +663,8 @@ int or_run_sequence(const or_model *m, int T, int n, const double *x0, const dou
         const uint8_t *mt = mask ? mask + (size_t)(t - 1) * m->n_obs : NULL;
         double *xt = parts + nd * (size_t)(t - 1);
         or_predictive_init(m, t, n_prev, xprev, n, seed, seq, xt);
-        int st = or_svgd_step(m, t, n_prev, xprev, NULL, zt, mt, n, xt, n_iter, step, bw_scale,
+        const double *lw = (weights == 1 && t > 1) ? phiprev : NULL;
+        int st = or_svgd_step(m, t, n_prev, xprev, lw, zt, mt, n, xt, n_iter, step, bw_scale,
                               bw_mode, trans_mode, kernel, NULL);
         if (st != OR_OK) status = st;
         st = or_viterbi_particle(m, t, n_prev, xprev, phiprev, zt, mt, n, xt, 0.0,

@@ -238,7 +238,7 @@ bool opts_ok(const smsq_svgd_opts_t *o)
 {
     return o && o->n_iter >= 0 && std::isfinite(o->step) && finite_pos(o->bw_scale) &&
            (o->bw_mode == 0 || o->bw_mode == 1) && (o->trans_mode == 0 || o->trans_mode == 1) &&
-           o->kernel >= SMSQ_KERNEL_RBF && o->kernel <= SMSQ_KERNEL_MATERN32;
+           o->kernel >= SMSQ_KERNEL_RBF && o->kernel <= SMSQ_KERNEL_MATERN32 && (o->weights == 0 || o->weights == 1);
 }
 
 uint32_t *status_ptr(void *ws) { return reinterpret_cast<uint32_t *>(ws); }
@@ -259,6 +259,11 @@ smsq_status_t step_typed(const smsq_model_desc_t &d, int batch, int t, int n_pre
     a.m = make_dev_model<T>(d);
     a.x_prev = (const T *)x_prev; a.x_prev_stride = x_prev_stride;
     a.log_w = (const T *)log_w; a.log_w_stride = log_w_stride;
+    if (!log_w && opts && opts->weights == 1 && phi_prev) {
+        // mixture weights from the previous step's forward-recursion scores
+        a.log_w = (const T *)phi_prev;
+        a.log_w_stride = phi_prev_stride;
+    }
     a.phi_prev = (const T *)phi_prev; a.phi_prev_stride = phi_prev_stride;
     a.z = (const T *)z; a.z_stride = z_stride;
     a.mask = mask; a.mask_stride = mask_stride;
@@ -829,6 +834,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
         sd.n_iter = o.n_iter;
         sd.bw_mode = o.bw_mode;
         sd.trans_mode = o.trans_mode;
+        sd.weights = o.weights;
         sd.use_proposal = q.use_proposal;
         sd.step = (float)o.step;
         sd.bw_scale = (float)o.bw_scale;

@@ -30,7 +30,7 @@ struct SeqDesc {
     float *logpost;         // [1] J out
     int32_t *idx;           // [T] MAP indices (plan storage)
     int n, T, d, code;
-    int n_iter, bw_mode, trans_mode, use_proposal;
+    int n_iter, bw_mode, trans_mode, use_proposal, weights;  // weights 1: log w_j = phi_{t-1}(j)
     float step, bw_scale;
     uint64_t seed;
 };
@@ -47,8 +47,8 @@ __global__ void k_batch_prep(const SeqDesc *__restrict__ seqs, const int *__rest
     const long nd = (long)s.n * s.d;
     a.x_prev = t == 1 ? s.x0 : s.parts + (long)(t - 2) * nd;
     a.x_prev_stride = 0;
-    a.log_w = nullptr; a.log_w_stride = 0;
     a.phi_prev = t == 1 ? nullptr : s.phis + (long)(t - 2) * s.n;
+    a.log_w = s.weights == 1 ? a.phi_prev : nullptr; a.log_w_stride = 0;
     a.phi_prev_stride = 0;
     a.z = s.z + (long)(t - 1) * s.m.obs_dim; a.z_stride = 0;
     a.mask = s.mask ? s.mask + (long)(t - 1) * s.m.n_obs : nullptr; a.mask_stride = 0;

@@ -64,7 +64,7 @@ class InitExample(C.Structure):
 
 class SvgdOpts(C.Structure):
     _fields_ = [("n_iter", C.c_int), ("step", C.c_double), ("bw_scale", C.c_double),
-                ("bw_mode", C.c_int), ("trans_mode", C.c_int), ("kernel", C.c_int)]
+                ("bw_mode", C.c_int), ("trans_mode", C.c_int), ("kernel", C.c_int), ("weights", C.c_int)]
 
 
 KERNELS = {"rbf": 0, "imq": 1, "matern32": 2}
@@ -172,14 +172,16 @@ def _stream(stream=None) -> int:
 
 
 def opts(n_iter: int, step: float, bw_scale: float = 1.0, bw_mode: int = 0,
-         trans_mode: int = 0, kernel=0) -> SvgdOpts:
-    """SVGD options; kernel: 0/"rbf", 1/"imq", 2/"matern32"."""
+         trans_mode: int = 0, kernel=0, weights: int = 0) -> SvgdOpts:
+    """SVGD options; kernel: 0/"rbf", 1/"imq", 2/"matern32"; weights 1: mixture
+    weights from the previous step's forward-recursion scores (in the drivers)."""
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-    return SvgdOpts(int(n_iter), float(step), float(bw_scale), int(bw_mode), int(trans_mode), k)
+    return SvgdOpts(int(n_iter), float(step), float(bw_scale), int(bw_mode), int(trans_mode), k, int(weights))
 
 
 def opts_from(o) -> SvgdOpts:
-    return opts(o.n_iter, o.step, o.bw_scale, o.bw_mode, o.trans_mode, getattr(o, "kernel", 0))
+    return opts(o.n_iter, o.step, o.bw_scale, o.bw_mode, o.trans_mode, getattr(o, "kernel", 0),
+                getattr(o, "weights", 0))
 
 
 class Model:

@@ -62,14 +62,14 @@ def _single(models, opts, q):
 REL = 1e-5
 
 
-def _check_equal(plan, models, opts, seqs):
+def _check_equal(plan, models, opts, seqs, mix=MIX):
     for i, q in enumerate(seqs):
         xmap, J, parts = _single(models, opts, q)
         p_parts, _, _ = plan.storage(i)
         a, b = p_parts.cpu().double().numpy(), parts.cpu().double().numpy()
         scale = max(1.0, np.abs(b).max())
         err = np.abs(a - b).max() / scale
-        print("sequence %d %s: particles rel err %.2e, J %.7g vs %.7g" % (i, MIX[i] if i < len(MIX) else "",
+        print("sequence %d %s: particles rel err %.2e, J %.7g vs %.7g" % (i, mix[i] if i < len(mix) else "",
               err, plan.J[i].item(), J.item()), flush=True)
         assert err <= REL, "sequence %d particles differ: %.3e" % (i, err)
         xa, xb = plan.xmap[i].cpu().double().numpy(), xmap.cpu().double().numpy()
@@ -88,6 +88,23 @@ def test_batch_matches_single_sequences_16_waves():
     _check_equal(plan, models, opts, seqs)
     for J in plan.J:
         assert np.isfinite(J.item())
+
+
+def test_batch_with_map_conditioned_weights():
+    """weights = 1 (mixture weights from the previous forward-recursion
+    scores) in a plan matches the single-sequence path with the same option."""
+    models, opts, seqs = _build(MIX[1:6], base_seed=70)
+    opts = [smsq.opts(o.n_iter, o.step, o.bw_scale, o.bw_mode, o.trans_mode, weights=1) for o in opts]
+    plan = smsq.BatchPlan(models, opts, seqs)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == smsq.OK
+    _check_equal(plan, models, opts, seqs, MIX[1:6])
+    # and the weights change the result
+    plain = smsq.BatchPlan(models, [smsq.opts(o.n_iter, o.step, o.bw_scale) for o in opts], seqs)
+    plain.run()
+    torch.cuda.synchronize()
+    assert any(abs(a.item() - b.item()) > 1e-3 * max(1.0, abs(b.item())) for a, b in zip(plan.J, plain.J))
 
 
 def test_batch_autotuner_and_8_wave_shape():

@@ -368,6 +368,30 @@ def test_run_sequence_growth1d_kernels_f64(kernel):
     assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
 
 
+@pytest.mark.parametrize("name,n,T,L,dt", [("growth1d", 32, 30, 100, "f64"), ("range2d", 64, 12, 10, "f32"),
+                                           ("cv4d", 80, 8, 10, "f32")])
+def test_run_sequence_map_conditioned_weights(name, n, T, L, dt):
+    """Mixture weights w_j proportional to exp(phi_{t-1}(j)) (weights = 1)."""
+    announce("run_sequence weights from scores", name, n, T, L, dt)
+    wl = S.make_workload(name, B=1, seed=1004, T=T, n=n, n_iter=L)
+    desc = wl.model
+    o = wl.opts
+    mask = None if wl.mask is None else wl.mask[0]
+    res = O.run_sequence(desc, T, n, wl.x0[0], wl.z[0], mask, 6, 0, o.n_iter, o.step, weights=1)
+    base = O.run_sequence(desc, T, n, wl.x0[0], wl.z[0], mask, 6, 0, o.n_iter, o.step)
+    model = smsq.Model(desc)
+    td = tdt(dt)
+    xmap, J = smsq.run_sequence(model, dt, dev(wl.x0[0], td), dev(wl.z[0], td),
+                                None if mask is None else dev(mask, torch.uint8), n,
+                                smsq.opts(o.n_iter, o.step, weights=1), 6)
+    xmap, J = host(xmap).astype(np.float64), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), T)
+    print("J gpu %.8f oracle %.8f (uniform weights %.8f) rel %.3e" % (J, res["J"], base["J"], dJ))
+    assert dJ <= TOL_J
+    if dt == "f64":
+        assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+
+
 @pytest.mark.parametrize("name,n,T,L", [("range2d", 64, 12, 10), ("cv4d", 80, 8, 10), ("arm7", 96, 6, 10),
                                         ("lingauss", 48, 10, 20)])
 def test_run_sequence_f32_free_running(name, n, T, L):

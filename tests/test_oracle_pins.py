@@ -338,6 +338,29 @@ def test_stein_kernels_small_distance_limits():
             assert err <= 4 * tol, (kind, scale, err, tol)
 
 
+def test_map_conditioned_weights_enter_the_score_as_log_weights():
+    """Mixture weights w_j proportional to exp(phi_{t-1}(j)) (weights = 1):
+    a score computed with those log-weights equals, for a previous score
+    that singles out one particle j (others -inf), the score of the single
+    Gaussian transition from m_j, and adding a constant to every phi_{t-1}
+    changes nothing (the softmax is shift-invariant)."""
+    wl = S.make_workload("range2d", B=1, seed=3, T=3, n=16)
+    desc = wl.model
+    rng = np.random.default_rng(12)
+    xp = wl.truth[0, 1] + 0.3 * rng.normal(size=(8, 2))
+    x = wl.truth[0, 2] + 0.3 * rng.normal(size=(16, 2))
+    means = np.stack([O.transition_mean(desc, 2, xj) for xj in xp])
+    phi = np.full(8, -np.inf)
+    phi[5] = -3.0
+    s1 = O.scores_from_means(desc, means, phi, wl.z[0, 1], None, x)
+    s5 = O.scores_from_means(desc, means[5:6], None, wl.z[0, 1], None, x)
+    assert np.allclose(s1, s5, rtol=1e-12, atol=1e-12)
+    phi = rng.normal(size=8) * 4
+    a = O.scores_from_means(desc, means, phi, wl.z[0, 1], None, x)
+    b = O.scores_from_means(desc, means, phi + 123.0, wl.z[0, 1], None, x)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
 def test_stein_kernel_weighted_score_term():
     # With all particles at one point kappa = 1 and the repulsion vanishes:
     # phi_i = mean_k s_k.

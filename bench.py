@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--train-steps", type=int, default=4000)
     p.add_argument("--train-seqs", type=int, default=700, help="plain sequences whose steps train the proposal")
     p.add_argument("--ablation-mc", type=int, default=50, help="sequences per kernel-ablation row (0: skip)")
+    p.add_argument("--sweep", action="store_true",
+                   help="print the batch / N / workload sweeps as one JSON line instead of the benchmark")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="first copy this many MiB device to device three times (calibrates HBM byte counters)")
     return p.parse_args()
@@ -150,11 +152,13 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
 
 
 # Kernel / bandwidth / particle-count grid of the kernel ablation (Sec. V-E,
-# Table VIII) on the 1-D growth model: (kernel, bandwidth scale, N).
-ABLATION_GRID = [("rbf", 1.0, 10), ("imq", 1.0, 10), ("matern32", 1.0, 10),
-                 ("rbf", 0.5, 10), ("rbf", 3.0, 10), ("rbf", 0.5, 40), ("rbf", 3.0, 40),
-                 ("rbf", 1.0, 20), ("rbf", 1.0, 40), ("imq", 1.0, 20), ("imq", 1.0, 40),
-                 ("matern32", 1.0, 20), ("matern32", 1.0, 40)]
+# Table VIII) on the 1-D growth model: (kernel, bandwidth scale, N, weights),
+# plus the mixture weights from the previous forward-recursion scores.
+ABLATION_GRID = [("rbf", 1.0, 10, 0), ("imq", 1.0, 10, 0), ("matern32", 1.0, 10, 0),
+                 ("rbf", 0.5, 10, 0), ("rbf", 3.0, 10, 0), ("rbf", 0.5, 40, 0), ("rbf", 3.0, 40, 0),
+                 ("rbf", 1.0, 20, 0), ("rbf", 1.0, 40, 0), ("imq", 1.0, 20, 0), ("imq", 1.0, 40, 0),
+                 ("matern32", 1.0, 20, 0), ("matern32", 1.0, 40, 0),
+                 ("rbf", 1.0, 10, 1), ("rbf", 1.0, 40, 1)]
 
 
 def kernel_ablation(torch, smsq, mc: int):
@@ -164,13 +168,13 @@ def kernel_ablation(torch, smsq, mc: int):
     the GPU rate."""
     from paper_2312_08684_amd import scenarios as S
     rows = []
-    for kernel, bw, n in ABLATION_GRID:
+    for kernel, bw, n, weights in ABLATION_GRID:
         wl = S.make_workload("growth1d", B=mc, seed=3000, n=n)
         o = wl.opts
         model = smsq.Model(wl.model)
         x0 = torch.tensor(wl.x0, dtype=torch.float64, device="cuda")
         z = torch.tensor(wl.z, dtype=torch.float64, device="cuda")
-        so = smsq.opts(o.n_iter, o.step, bw, kernel=kernel)
+        so = smsq.opts(o.n_iter, o.step, bw, kernel=kernel, weights=weights)
         smsq.run_batch(model, "f64", x0, z, None, n, so, 5)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -178,11 +182,130 @@ def kernel_ablation(torch, smsq, mc: int):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         err = xmap.cpu().numpy()[:, 1:] - wl.truth[:, 1:]
-        rows.append({"kernel": kernel, "bw_scale": bw, "N": n, "rmse": float(np.sqrt(np.mean(err ** 2))),
+        rows.append({"kernel": kernel, "bw_scale": bw, "N": n,
+                     "weights": "exp(phi_prev)" if weights else "uniform", "rmse": float(np.sqrt(np.mean(err ** 2))),
                      "mean_J": float(J.mean().item()), "seconds": dt,
                      "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
     return {"model": "growth1d (1-D nonstationary growth), FP64, T=50, L=100, eps=0.05",
             "sequences_per_row": mc, "rows": rows}
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def sweep(torch, smsq):
+    """Sweeps of the measurement plan: the arm7 SVGD step against the batch
+    size, the forward recursion against N (lattice mode FP32 / FP64, particle
+    mode), and Algorithm 2 end to end per workload at one sequence and at a
+    Monte-Carlo batch."""
+    from paper_2312_08684_amd import scenarios as S
+    out = {}
+    # (1) teacher-forced arm7 step t = 2, N = N_p = 1024, L = 100, HIP events
+    rows = []
+    for B in (1, 8, 32, 128, 256, 1024):
+        wl = S.make_workload("arm7", B=B, seed=0, T=2)
+        o, d, n = wl.opts, wl.model.d, wl.n
+        model = smsq.Model(wl.model)
+        rng = np.random.default_rng(0)
+        xp = torch.tensor(wl.truth[:, 1][:, None, :] + 0.02 * rng.normal(size=(B, n, d)), dtype=torch.float32,
+                          device="cuda")
+        x = torch.empty((B, n, d), dtype=torch.float32, device="cuda")
+        z = torch.tensor(wl.z[:, 1], dtype=torch.float32, device="cuda")
+        php = torch.zeros((B, n), dtype=torch.float32, device="cuda")
+        ws = smsq.workspace()
+        so = smsq.opts_from(o)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            smsq.batch_step(model, "f32", 2, xp, php, z, None, x, so, seed=1, ws=ws)
+        reps = 10 if B <= 256 else 4
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(reps):
+            smsq.batch_step(model, "f32", 2, xp, php, z, None, x, so, seed=1, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        fl = B * o.n_iter * flops_per_iteration(n, n, d, "arm7")
+        rows.append({"B": B, "ms_per_launch": ms, "tflops": fl / ms / 1e9, "frac": fl / (ms / 1e3) / PEAK_FP32,
+                     "particle_iters_per_s": B * n * o.n_iter / (ms / 1e3)})
+    out["svgd_step_arm7_vs_batch"] = rows
+    # (2) forward recursion against N
+    rows = []
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    for dt, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        for n in (32, 256, 512, 1024, 4096):
+            es = 4 if dt == "f32" else 8
+            # distinct lattices, up to 1 GiB together (above the 256 MB last-level cache at N = 4096)
+            nlat = max(1, min(16, (1 << 30) // (n * n * es)))
+            As = [torch.randn((n, n), generator=gen, device="cuda", dtype=tdt) for _ in range(nlat)]
+            ell = torch.randn(n, generator=gen, device="cuda", dtype=tdt)
+            php = torch.randn(n, generator=gen, device="cuda", dtype=tdt)
+            ws = smsq.workspace()
+            for A in As[:3]:
+                smsq.viterbi_step(None, dt, 2, php, lattice=A, loglik=ell, want_flags=False, ws=ws)
+            reps = 48
+            e0, e1 = _events(torch)
+            e0.record()
+            for r in range(reps):
+                smsq.viterbi_step(None, dt, 2, php, lattice=As[r % nlat], loglik=ell, want_flags=False, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3 / reps
+            nbytes = n * n * es + 3 * n * es + 4 * n
+            del As
+            rows.append({"mode": "lattice", "dtype": dt, "N": n, "us_per_launch": sec * 1e6,
+                         "edges_per_s": n * n / sec, "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM})
+    for name, n in (("range2d", 256), ("cv4d", 512), ("arm7", 1024)):
+        wl = S.make_workload(name, B=1, seed=0, T=2, n=n)
+        model = smsq.Model(wl.model)
+        d = wl.model.d
+        rng = np.random.default_rng(1)
+        xp = torch.tensor(wl.truth[0, 1] + 0.02 * rng.normal(size=(n, d)), dtype=torch.float32, device="cuda")
+        x = torch.tensor(wl.truth[0, 2] + 0.02 * rng.normal(size=(n, d)), dtype=torch.float32, device="cuda")
+        z = torch.tensor(wl.z[0, 1], dtype=torch.float32, device="cuda")
+        mk = torch.tensor(wl.mask[0, 1], dtype=torch.uint8, device="cuda") if wl.mask is not None else None
+        php = torch.zeros(n, dtype=torch.float32, device="cuda")
+        ws = smsq.workspace()
+        for _ in range(3):
+            smsq.viterbi_step(model, "f32", 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
+        reps = 50
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            smsq.viterbi_step(model, "f32", 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        rows.append({"mode": "particle (one sequence, one workgroup)", "model": name, "dtype": "f32", "N": n,
+                     "us_per_launch": sec * 1e6, "edges_per_s": n * n / sec})
+    out["viterbi_vs_n"] = rows
+    # (3) Algorithm 2 end to end per workload: one sequence and a batch
+    rows = []
+    for name, batches in (("growth1d", (1, 50, 256)), ("range2d", (1, 20, 256)), ("cv4d", (1, 20, 256)),
+                          ("arm7", (1, 20, 256))):
+        for B in batches:
+            T = 20 if name == "arm7" and B == 256 else None
+            wl = S.make_workload(name, B=B, seed=7, T=T)
+            o, dt = wl.opts, wl.dtype
+            td = smsq.torch_dtype(dt)
+            model = smsq.Model(wl.model)
+            x0 = torch.tensor(wl.x0, dtype=td, device="cuda")
+            z = torch.tensor(wl.z, dtype=td, device="cuda")
+            mk = torch.tensor(wl.mask, dtype=torch.uint8, device="cuda") if wl.mask is not None else None
+            so = smsq.opts_from(o)
+            smsq.run_batch(model, dt, x0, z, mk, wl.n, so, 3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            smsq.run_batch(model, dt, x0, z, mk, wl.n, so, 3)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            rows.append({"workload": name, "dtype": dt, "B": B, "N": wl.n, "T": wl.T, "L": o.n_iter,
+                         "seconds": sec, "sequences_per_s": B / sec,
+                         "particle_iters_per_s": B * wl.T * wl.n * o.n_iter / sec,
+                         "edges_per_s": B * (wl.n + (wl.T - 1) * wl.n * wl.n) / sec})
+    out["run_batch_per_workload"] = rows
+    return out
 
 
 def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
@@ -265,6 +388,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     smsq.load()
+    if args.sweep:
+        print(json.dumps(sweep(torch, smsq)), flush=True)
+        return
     if args.copy_probe_mib > 0:
         nbytes = args.copy_probe_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

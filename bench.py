@@ -152,7 +152,7 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
 
 
 # Kernel / bandwidth / particle-count grid of the kernel ablation (Sec. V-E,
-# Table VIII) on the 1-D growth model: (kernel, bandwidth scale, N, weights),
+# Table VIII) on Scenario A: (kernel, bandwidth scale, N, weights),
 # plus the mixture weights from the previous forward-recursion scores.
 ABLATION_GRID = [("rbf", 1.0, 10, 0), ("imq", 1.0, 10, 0), ("matern32", 1.0, 10, 0),
                  ("rbf", 0.5, 10, 0), ("rbf", 3.0, 10, 0), ("rbf", 0.5, 40, 0), ("rbf", 3.0, 40, 0),
@@ -162,14 +162,14 @@ ABLATION_GRID = [("rbf", 1.0, 10, 0), ("imq", 1.0, 10, 0), ("matern32", 1.0, 10,
 
 
 def kernel_ablation(torch, smsq, mc: int):
-    """The ablation grid on synthetic 1-D growth sequences (FP64, T = 50,
-    L = 100, eps = 0.05), mc Monte-Carlo sequences per row in one batched
-    run: RMSE of the MAP trajectory against the simulated truth, mean J, and
-    the GPU rate."""
+    """The ablation grid on the paper's Scenario A model (Sec. V-A constants,
+    FP64, T = 100, L = 100, eps = 0.5), mc synthetic Monte-Carlo sequences
+    per row in one batched run: RMSE of the MAP trajectory against the
+    simulated truth, mean J, and the GPU rate."""
     from paper_2312_08684_amd import scenarios as S
     rows = []
     for kernel, bw, n, weights in ABLATION_GRID:
-        wl = S.make_workload("growth1d", B=mc, seed=3000, n=n)
+        wl = S.make_workload("scenario_a", B=mc, seed=3000, n=n)
         o = wl.opts
         model = smsq.Model(wl.model)
         x0 = torch.tensor(wl.x0, dtype=torch.float64, device="cuda")
@@ -186,7 +186,7 @@ def kernel_ablation(torch, smsq, mc: int):
                      "weights": "exp(phi_prev)" if weights else "uniform", "rmse": float(np.sqrt(np.mean(err ** 2))),
                      "mean_J": float(J.mean().item()), "seconds": dt,
                      "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
-    return {"model": "growth1d (1-D nonstationary growth), FP64, T=50, L=100, eps=0.05",
+    return {"model": "scenario_a (Sec. V-A 1-D benchmark constants), FP64, T=100, L=100, eps=0.5",
             "sequences_per_row": mc, "rows": rows}
 
 

@@ -349,6 +349,24 @@ def test_run_sequence_growth1d_full_f64():
     assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
 
 
+@pytest.mark.parametrize("kernel", ["rbf", "imq", "matern32"])
+def test_run_sequence_scenario_a_f64(kernel):
+    """The paper's Scenario A model (Sec. V-A constants), N = 10, T = 100,
+    L = 100: Algorithm 2 against the oracle for each kernel."""
+    announce("run_sequence scenario_a f64", kernel)
+    wl = S.make_workload("scenario_a", B=1, seed=1005)
+    desc, o, k = wl.model, wl.opts, smsq.KERNELS[kernel]
+    res = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 79, 0, o.n_iter, o.step, kernel=k)
+    model = smsq.Model(desc)
+    xmap, J = smsq.run_sequence(model, "f64", dev(wl.x0[0], torch.float64), dev(wl.z[0], torch.float64),
+                                None, wl.n, smsq.opts(o.n_iter, o.step, kernel=k), 79)
+    xmap, J = host(xmap), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), wl.T)
+    print("J gpu %.10f oracle %.10f rel %.3e" % (J, res["J"], dJ))
+    assert dJ <= TOL_J
+    assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+
+
 @pytest.mark.parametrize("kernel", ["imq", "matern32"])
 def test_run_sequence_growth1d_kernels_f64(kernel):
     """Algorithm 2 with the ablation's kernels, 1-D growth model at N = 10."""

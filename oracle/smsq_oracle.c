@@ -14,7 +14,8 @@
  * floating-point operation is a single IEEE double operation in source order.
  *
  * Section / equation map (paper numbering):
- *   models           Sec. II, eq. (SSM); scenario models of Sec. V
+ *   models           Sec. II, eq. (SSM); scenario models of Sec. V (the
+ *                    SE(2) pose with unknown landmark identity is Sec. V-B)
  *   or_philox*       counter-based RNG (Salmon et al., SC'11), used only for
  *                    the predictive initial particles
  *   or_bandwidth     RBF kernel with the median-heuristic bandwidth (Sec. V
@@ -43,7 +44,7 @@
 
 #define OR_MAXD 8
 
-enum { OR_GROWTH1D = 0, OR_RANGE2D = 1, OR_CV4D = 2, OR_ARM7 = 3, OR_LINGAUSS = 4 };
+enum { OR_GROWTH1D = 0, OR_RANGE2D = 1, OR_CV4D = 2, OR_ARM7 = 3, OR_LINGAUSS = 4, OR_SE2 = 5 };
 enum { OR_OK = 0, OR_INVALID = 1, OR_NONFINITE = 4 };
 
 typedef struct {
@@ -126,6 +127,15 @@ void or_transition_mean(const or_model *m, int t, const double *x, double *out)
             out[a] = s;
         }
         break;
+    case OR_SE2: {
+        /* Sec. V-B pose model: the heading turns by omega dt, then the
+         * position moves v dt along the new heading theta_t */
+        double th = x[2] + p[2] * p[0];
+        out[0] = x[0] + p[1] * p[0] * cos(th);
+        out[1] = x[1] + p[1] * p[0] * sin(th);
+        out[2] = th;
+        break;
+    }
     default: /* random walks: range2d, arm7 */
         for (int a = 0; a < d; ++a) out[a] = x[a];
     }
@@ -183,6 +193,28 @@ void or_arm_fk(const or_model *m, const double *q, double *pos)
 
 static int obs_on(const uint8_t *mask, int o) { return mask == NULL || mask[o] != 0; }
 
+/* Angle mapped into [-pi, pi): a - 2 pi floor((a + pi) / (2 pi)). */
+double or_wrap_angle(double a) { return a - 2.0 * OR_PI * floor((a + OR_PI) / (2.0 * OR_PI)); }
+
+/* Sec. V-B association-marginalised likelihood.  For landmark l at Gamma_l:
+ * term_l = log p(l) + log N(z_r; |P - Gamma_l|, r_var)
+ *        + log N(wrap(z_b - atan2(y - Gamma_l,y, x - Gamma_l,x)); 0, b_var),
+ * p(l) = 1 / n_l.  Fills terms[l] and the offsets and residuals per landmark. */
+static void se2_terms(const double *p, const double *z, const double *x, double *terms,
+                      double *dx, double *dy, double *rho, double *er, double *eb)
+{
+    int nl = (int)p[5];
+    for (int l = 0; l < nl; ++l) {
+        dx[l] = x[0] - p[6 + 2 * l];
+        dy[l] = x[1] - p[7 + 2 * l];
+        rho[l] = sqrt(dx[l] * dx[l] + dy[l] * dy[l]);
+        er[l] = z[0] - rho[l];
+        eb[l] = or_wrap_angle(z[1] - atan2(dy[l], dx[l]));
+        terms[l] = -log((double)nl) - 0.5 * er[l] * er[l] / p[3] - 0.5 * log(2.0 * OR_PI * p[3])
+                   - 0.5 * eb[l] * eb[l] / p[4] - 0.5 * log(2.0 * OR_PI * p[4]);
+    }
+}
+
 double or_loglik(const or_model *m, const double *z, const uint8_t *mask, const double *x)
 {
     const double *p = m->params;
@@ -233,6 +265,17 @@ double or_loglik(const or_model *m, const double *z, const uint8_t *mask, const 
         double q = 0.0;
         for (int c = 0; c < 3; ++c) { double e = z[c] - pos[c]; q += e * e; }
         return -0.5 * q / p[0] - 1.5 * log(2.0 * OR_PI * p[0]);
+    }
+    case OR_SE2: {
+        if (!obs_on(mask, 0)) return 0.0;
+        int nl = (int)p[5];
+        double terms[8], dx[8], dy[8], rho[8], er[8], eb[8];
+        se2_terms(p, z, x, terms, dx, dy, rho, er, eb);
+        double mx = terms[0];
+        for (int l = 1; l < nl; ++l) if (terms[l] > mx) mx = terms[l];
+        double s = 0.0;
+        for (int l = 0; l < nl; ++l) s += exp(terms[l] - mx);
+        return mx + log(s);
     }
     case OR_LINGAUSS: {
         if (!obs_on(mask, 0)) return 0.0;
@@ -316,6 +359,26 @@ void or_grad_loglik(const or_model *m, const double *z, const uint8_t *mask, con
                               za[2] * v[0] - za[0] * v[2],
                               za[0] * v[1] - za[1] * v[0] };
             g[i] = col[0] * e[0] + col[1] * e[1] + col[2] * e[2];
+        }
+        break;
+    }
+    case OR_SE2: {
+        /* gradient of the log of the mixture: responsibilities times the
+         * per-landmark gradients; d atan2(dy, dx) = (-dy, dx) / rho^2 */
+        if (!obs_on(mask, 0)) break;
+        int nl = (int)p[5];
+        double terms[8], dx[8], dy[8], rho[8], er[8], eb[8];
+        se2_terms(p, z, x, terms, dx, dy, rho, er, eb);
+        double mx = terms[0];
+        for (int l = 1; l < nl; ++l) if (terms[l] > mx) mx = terms[l];
+        double s = 0.0;
+        for (int l = 0; l < nl; ++l) s += exp(terms[l] - mx);
+        for (int l = 0; l < nl; ++l) {
+            if (rho[l] < 1e-12) continue;
+            double w = exp(terms[l] - mx) / s;
+            double gr = er[l] / p[3] / rho[l], gb = eb[l] / p[4] / (rho[l] * rho[l]);
+            g[0] += w * (gr * dx[l] - gb * dy[l]);
+            g[1] += w * (gr * dy[l] + gb * dx[l]);
         }
         break;
     }

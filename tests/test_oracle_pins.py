@@ -59,7 +59,9 @@ def test_box_muller_normals_moments():
 # ---------------------------------------------------------------------------
 
 def _all_models():
-    return {name: S._model_for(name, 0) for name in ("growth1d", "range2d", "cv4d", "arm7", "lingauss")}
+    m = {name: S._model_for(name, 0) for name in ("growth1d", "range2d", "cv4d", "arm7", "lingauss")}
+    m["se2"] = S.se2_model()
+    return m
 
 
 def _independent_loglik(desc, z, mask, x):
@@ -88,6 +90,19 @@ def _independent_loglik(desc, z, mask, x):
         d, o = desc.d, desc.obs_dim
         Cm = p[16:16 + o * d].reshape(o, d)
         return float(np.sum(stats.norm.logpdf(z, Cm @ x, np.sqrt(p[32:32 + o])))) if on(0) else 0.0
+    if desc.kind == S.SE2:
+        # Sec. V-B: equal-weight mixture over the landmarks of a range and a
+        # bearing Gaussian; the bearing residual is taken on the circle
+        if not on(0):
+            return 0.0
+        lm = p[6:6 + 2 * int(p[5])].reshape(-1, 2)
+        terms = []
+        for gx, gy in lm:
+            rng_ = math.hypot(x[0] - gx, x[1] - gy)
+            resid = float(np.angle(np.exp(1j * (z[1] - math.atan2(x[1] - gy, x[0] - gx)))))
+            terms.append(math.log(1.0 / len(lm)) + stats.norm.logpdf(z[0], rng_, math.sqrt(p[3]))
+                         + stats.norm.logpdf(resid, 0.0, math.sqrt(p[4])))
+        return float(logsumexp(terms))
     raise ValueError
 
 
@@ -96,6 +111,8 @@ def _random_state(desc, rng):
         return rng.uniform(0, 20, size=2)
     if desc.kind == S.ARM7:
         return rng.uniform(-1, 1, size=7)
+    if desc.kind == S.SE2:
+        return np.array([rng.uniform(-15, 15), rng.uniform(-15, 15), rng.uniform(-7, 7)])
     return rng.normal(0, 2, size=desc.d)
 
 
@@ -107,10 +124,12 @@ def _random_obs(desc, rng, x):
     if desc.kind == S.ARM7:
         return S.dh_forward_kinematics(x, desc.params[1:8], desc.params[8:15], desc.params[15:22]) \
             + rng.normal(0, 0.02, size=3)
+    if desc.kind == S.SE2:
+        return np.array([rng.uniform(0, 30), rng.uniform(-math.pi, math.pi)])
     return rng.normal(0, 5, size=desc.obs_dim) + (10 if desc.kind == S.RANGE2D else 0)
 
 
-@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "se2"])
 def test_loglik_matches_scipy_densities(name):
     desc = _all_models()[name]
     rng = np.random.default_rng(1)
@@ -125,7 +144,7 @@ def test_loglik_matches_scipy_densities(name):
         assert got == pytest.approx(want, rel=1e-10, abs=1e-9)
 
 
-@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "se2"])
 def test_grad_loglik_matches_finite_differences(name):
     desc = _all_models()[name]
     rng = np.random.default_rng(2)
@@ -162,6 +181,44 @@ def test_transition_means_match_model_definitions():
     lg = m["lingauss"]
     x2 = rng.normal(size=2)
     assert np.allclose(O.transition_mean(lg, 1, x2), np.array([[1.0, 0.1], [0.0, 0.95]]) @ x2)
+
+
+def test_se2_pose_model_closed_forms():
+    """Sec. V-B pose model: one step turns the heading by omega dt and moves
+    v dt along the new heading; with omega dt = 2 pi / T the noise-free poses
+    walk a closed regular T-gon (the step vectors sum to zero) and come back
+    to the start with the heading advanced by 2 pi.  The likelihood sees the
+    bearing on the circle (z_b and z_b + 2 pi agree), does not depend on the
+    heading, and with one landmark visible it is a product of two Gaussians."""
+    desc = S.se2_model()
+    p = desc.params
+    x = np.array([3.0, -2.0, 0.4])
+    th = 0.4 + p[2] * p[0]
+    want = [3.0 + p[1] * p[0] * math.cos(th), -2.0 + p[1] * p[0] * math.sin(th), th]
+    assert np.allclose(O.transition_mean(desc, 7, x), want, rtol=0, atol=1e-15)
+    T = 630
+    assert p[2] * p[0] == pytest.approx(2 * math.pi / T, rel=1e-15)
+    pose = np.array([S.SE2_RADIUS, 0.0, math.pi / 2])
+    start = pose.copy()
+    for t in range(1, T + 1):
+        pose = O.transition_mean(desc, t, pose)
+    assert np.allclose(pose[:2], start[:2], atol=1e-10)
+    assert pose[2] == pytest.approx(start[2] + 2 * math.pi, abs=1e-12)
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        xs = np.array([rng.uniform(-15, 15), rng.uniform(-15, 15), rng.uniform(-3, 3)])
+        z = np.array([rng.uniform(0, 30), rng.uniform(-math.pi, math.pi)])
+        base = O.loglik(desc, z, None, xs)
+        assert O.loglik(desc, z + [0, 2 * math.pi], None, xs) == pytest.approx(base, abs=1e-9)
+        assert O.loglik(desc, z, None, xs + [0, 0, 1.3]) == base
+        assert O.loglik(desc, z, np.zeros(1, np.uint8), xs) == 0.0
+        assert np.array_equal(O.grad_loglik(desc, z, None, xs)[2:], [0.0])
+    one = S.se2_model(landmarks=[[4.0, 1.0]])
+    xs = np.array([1.0, 5.0, 0.0])
+    rr, bb = math.hypot(-3.0, 4.0), math.atan2(4.0, -3.0)
+    z = np.array([4.2, bb - 0.3])
+    want = stats.norm.logpdf(4.2, rr, 1.0) + stats.norm.logpdf(-0.3, 0.0, 0.44)
+    assert O.loglik(one, z, None, xs) == pytest.approx(want, rel=1e-12)
 
 
 def test_log_transition_matches_scipy():

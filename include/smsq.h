@@ -67,13 +67,21 @@ typedef enum { SMSQ_F32 = 0, SMSQ_F64 = 1 } smsq_dtype_t;
  *             Rx(alpha_i) + N(0, p0 I); a_i = p[1+i], alpha_i = p[8+i], d_i = p[15+i].
  *   LINGAUSS  d<=4, obs_dim<=4, n_obs=1.  f(x) = A x with A = p[0..d*d) row-major;
  *             z = C x + N(0, diag r), C = p[16..16+obs_dim*d), r = p[32..32+obs_dim).
+ *   SE2       d=3 (px, py, heading), obs_dim=2, n_obs=1 (Sec. V-B).  With
+ *             dt=p0, v=p1, omega=p2: th' = th + omega dt, f(x) = (px + v dt
+ *             cos th', py + v dt sin th', th').  z = (range, bearing) from one
+ *             of n_l = p5 <= 8 landmarks (p[6+2l], p[7+2l]) of unknown
+ *             identity: p(z|x) = (1/n_l) sum_l N(z_r; |P - G_l|, p3)
+ *             N(wrap(z_b - atan2(py - G_l,y, px - G_l,x)); 0, p4), the bearing
+ *             residual mapped into [-pi, pi).  Batched plans reject it.
  */
 typedef enum {
     SMSQ_MODEL_GROWTH1D = 0,
     SMSQ_MODEL_RANGE2D = 1,
     SMSQ_MODEL_CV4D = 2,
     SMSQ_MODEL_ARM7 = 3,
-    SMSQ_MODEL_LINGAUSS = 4
+    SMSQ_MODEL_LINGAUSS = 4,
+    SMSQ_MODEL_SE2 = 5
 } smsq_model_kind_t;
 
 typedef struct {

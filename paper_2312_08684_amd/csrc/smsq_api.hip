@@ -57,6 +57,15 @@ smsq_status_t check_desc(const smsq_model_desc_t *d)
     case SMSQ_MODEL_ARM7:
         if (d->d != 7 || d->obs_dim != 3 || d->n_obs != 1 || !finite_pos(d->params[0])) return SMSQ_ERR_INVALID;
         return SMSQ_OK;
+    case SMSQ_MODEL_SE2: {
+        const int nl = (int)d->params[5];
+        if (d->d != 3 || d->obs_dim != 2 || d->n_obs != 1 || nl < 1 || nl > 8 || (double)nl != d->params[5])
+            return SMSQ_ERR_INVALID;
+        if (!finite_pos(d->params[3]) || !finite_pos(d->params[4])) return SMSQ_ERR_INVALID;
+        for (int c = 0; c < 6 + 2 * nl; ++c)
+            if (!std::isfinite(d->params[c])) return SMSQ_ERR_INVALID;
+        return SMSQ_OK;
+    }
     case SMSQ_MODEL_LINGAUSS:
         if (d->d < 1 || d->d > 4 || d->obs_dim < 1 || d->obs_dim > 4 || d->n_obs != 1) return SMSQ_ERR_INVALID;
         for (int r = 0; r < d->obs_dim; ++r)
@@ -94,6 +103,12 @@ template <typename T> DevModel<T> make_dev_model(const smsq_model_desc_t &d)
             m.aux[i] = (T)std::cos(d.params[8 + i]);
             m.aux[7 + i] = (T)std::sin(d.params[8 + i]);
         }
+    if (d.kind == SMSQ_MODEL_SE2) {
+        m.aux[0] = (T)(1.0 / d.params[3]);
+        m.aux[1] = (T)(1.0 / d.params[4]);
+        m.aux[2] = (T)(-std::log(d.params[5]) - 0.5 * std::log(2.0 * kPi * d.params[3]) -
+                       0.5 * std::log(2.0 * kPi * d.params[4]));
+    }
     if (d.kind == SMSQ_MODEL_GROWTH1D) {
         m.grow[0] = d.params[2];
         m.grow[1] = d.params[3];
@@ -189,6 +204,7 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
         case SMSQ_MODEL_RANGE2D: return launch_mfma_kd<RANGE2D, 2>(a, batch, s);
         case SMSQ_MODEL_CV4D: return launch_mfma_kd<CV4D, 4>(a, batch, s);
         case SMSQ_MODEL_ARM7: return launch_mfma_kd<ARM7, 7>(a, batch, s);
+        case SMSQ_MODEL_SE2: return launch_mfma_kd<SE2, 3>(a, batch, s);
         case SMSQ_MODEL_LINGAUSS:
             switch (d.d) {
             case 1: return launch_mfma_kd<LINGAUSS, 1>(a, batch, s);
@@ -204,6 +220,7 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
     case SMSQ_MODEL_RANGE2D: return launch_step_kd<float, RANGE2D, 2>(a, batch, s);
     case SMSQ_MODEL_CV4D: return launch_step_kd<float, CV4D, 4>(a, batch, s);
     case SMSQ_MODEL_ARM7: return launch_step_kd<float, ARM7, 7>(a, batch, s);
+    case SMSQ_MODEL_SE2: return launch_step_kd<float, SE2, 3>(a, batch, s);
     case SMSQ_MODEL_LINGAUSS:
         switch (d.d) {
         case 1: return launch_step_kd<float, LINGAUSS, 1>(a, batch, s);
@@ -223,6 +240,7 @@ smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<dou
     case SMSQ_MODEL_RANGE2D: return launch_step_kd<double, RANGE2D, 2>(a, batch, s);
     case SMSQ_MODEL_CV4D: return launch_step_kd<double, CV4D, 4>(a, batch, s);
     case SMSQ_MODEL_ARM7: return launch_step_kd<double, ARM7, 7>(a, batch, s);
+    case SMSQ_MODEL_SE2: return launch_step_kd<double, SE2, 3>(a, batch, s);
     case SMSQ_MODEL_LINGAUSS:
         switch (d.d) {
         case 1: return launch_step_kd<double, LINGAUSS, 1>(a, batch, s);

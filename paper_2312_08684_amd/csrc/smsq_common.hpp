@@ -24,6 +24,8 @@ template <> struct RealOps<float> {
     static __device__ __forceinline__ float log_(float x) { return __logf(x); }
     static __device__ __forceinline__ float sqrt_(float x) { return __fsqrt_rn(x); }
     static __device__ __forceinline__ void sincos_(float x, float *s, float *c) { sincosf(x, s, c); }
+    static __device__ __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
+    static __device__ __forceinline__ float floor_(float x) { return floorf(x); }
     static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
     static __device__ __forceinline__ bool finite(float x) { return __builtin_isfinite(x); }
 };
@@ -34,6 +36,8 @@ template <> struct RealOps<double> {
     static __device__ __forceinline__ double log_(double x) { return log(x); }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
     static __device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
+    static __device__ __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
+    static __device__ __forceinline__ double floor_(double x) { return floor(x); }
     static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
     static __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 };

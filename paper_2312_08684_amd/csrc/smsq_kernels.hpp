@@ -210,8 +210,19 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
         for (int o = tid; o < m.n_obs; o += nt) smask[o] = a.mask[(long)b * a.mask_stride + o];
         mk = smask;
     }
-    // transition means of the previous particles, scaled to log2 units, and
-    // their log-weights (log2 units)
+    // Particles and transition means are kept relative to a centre, the
+    // transition mean of the first previous particle, so that the updates
+    // and pairwise differences keep their precision when the cloud sits far
+    // from the origin; the model densities see centre + offset.
+    T cen[D];
+    {
+        T xp[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) xp[c] = xprev[c];
+        F::mean(m, a.t, xp, cen);
+    }
+    // transition means of the previous particles, centred and scaled to log2
+    // units, and their log-weights (log2 units)
     T rs[DP];
 #pragma unroll
     for (int c = 0; c < DP; ++c) rs[c] = c < D ? m.rs[c] : (T)0;
@@ -221,7 +232,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
         for (int c = 0; c < D; ++c) xp[c] = xprev[(long)j * D + c];
         F::mean(m, a.t, xp, mu);
 #pragma unroll
-        for (int c = 0; c < DP; ++c) sm[(long)j * DP + c] = c < D ? mu[c] * rs[c] : (T)0;
+        for (int c = 0; c < DP; ++c) sm[(long)j * DP + c] = c < D ? (mu[c] - cen[c]) * rs[c] : (T)0;
         const T lw = a.log_w ? a.log_w[(long)b * a.log_w_stride + j] : -R::log_((T)np);
         sc[j] = lw * (T)kLog2e;
     }
@@ -230,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
         T xi[D];
         if (a.init_given) {
 #pragma unroll
-            for (int c = 0; c < D; ++c) xi[c] = xg[(long)i * D + c];
+            for (int c = 0; c < D; ++c) xi[c] = xg[(long)i * D + c] - cen[c];
         } else {
             T xp[D], mu[D];
             const int j = i % np;
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
             double nz[8];
             normals8(a.seed, a.seq_offset + (uint32_t)b, (uint32_t)a.t, (uint32_t)i, D, nz);
 #pragma unroll
-            for (int c = 0; c < D; ++c) xi[c] = mu[c] + m.sqrt_q[c] * (T)nz[c];
+            for (int c = 0; c < D; ++c) xi[c] = (mu[c] - cen[c]) + m.sqrt_q[c] * (T)nz[c];
         }
 #pragma unroll
         for (int c = 0; c < DP; ++c) sx[(long)i * DP + c] = c < D ? xi[c] : (T)0;
@@ -277,10 +288,12 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
 
         // (2) scores
         for (int k = tid; k < n; k += nt) {
-            T xk[DP];
+            T xk[DP], xa[D];
             lds_load<T, DP>(sx + (long)k * DP, xk);
+#pragma unroll
+            for (int c = 0; c < D; ++c) xa[c] = xk[c] + cen[c];
             T g[D];
-            F::grad(m, sz, mk, xk, g);
+            F::grad(m, sz, mk, xa, g);
             T mb[D];
             if (a.trans_mode == 0) {
                 T xs[DP];
@@ -400,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
     for (int i = tid; a.do_svgd && i < n; i += nt) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const T v = sx[(long)i * DP + c];
+            const T v = sx[(long)i * DP + c] + cen[c];
             bad |= !R::finite(v);
             xg[(long)i * D + c] = v;
         }
@@ -430,7 +443,10 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
                 if (j == 0) { ab.best = cij; ab.arg = 0; }
                 else argbest_push(ab, cij, j);
             }
-            const T ell = F::loglik(m, sz, mk, xi);
+            T xa[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) xa[c] = xi[c] + cen[c];
+            const T ell = F::loglik(m, sz, mk, xa);
             const T ph = ab.best + ell;
             nan_seen |= (ph != ph);
             bad |= nan_seen;

@@ -8,7 +8,7 @@
 
 namespace smsq {
 
-enum Kind { GROWTH1D = 0, RANGE2D = 1, CV4D = 2, ARM7 = 3, LINGAUSS = 4 };
+enum Kind { GROWTH1D = 0, RANGE2D = 1, CV4D = 2, ARM7 = 3, LINGAUSS = 4, SE2 = 5 };
 
 // Per-launch model constants, precomputed on the host in the kernel's type.
 template <typename T> struct DevModel {
@@ -19,7 +19,8 @@ template <typename T> struct DevModel {
     T rs[8];       // sqrt(log2(e) / (2 q)): x * rs puts -(x-m)^2/(2q) in log2 units
     T log_z;       // -1/2 sum_d log(2 pi q_d)
     T p[64];       // family parameters
-    T aux[16];     // family constants (RANGE2D: 1/r_var; ARM7: cos alpha_i, sin alpha_i)
+    T aux[16];     // family constants (RANGE2D: 1/r_var; ARM7: cos alpha_i, sin alpha_i;
+                   // SE2: 1/r_var, 1/b_var, log-density constant of one landmark)
     double grow[3]; // GROWTH1D cosine term c, omega, phase, kept in double
 };
 
@@ -232,6 +233,80 @@ template <typename T> struct Family<T, ARM7, 7> {
             g[i] = c0 * e0 + c1 * e1 + c2 * e2;
             f.advance(ct[i], st[i], m.aux[i], m.aux[7 + i], m.p[1 + i], m.p[15 + i]);
         }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SE(2) pose (px, py, heading) of Sec. V-B: the heading turns by omega dt and
+// the position moves v dt along the new heading.  One range-bearing
+// measurement per step from one of n_l landmarks whose identity is unknown:
+// the likelihood is the equal-weight mixture over the landmarks, evaluated as
+// a running-max log-sum-exp in one pass (the gradient is the
+// responsibility-weighted sum of the per-landmark gradients, accumulated in
+// the same pass).  The bearing residual is mapped into [-pi, pi).
+template <typename T> struct Family<T, SE2, 3> {
+    static __device__ void mean(const DevModel<T> &m, int, const T *x, T *out)
+    {
+        const T th = x[2] + m.p[2] * m.p[0];
+        T s, c;
+        RealOps<T>::sincos_(th, &s, &c);
+        const T vdt = m.p[1] * m.p[0];
+        out[0] = x[0] + vdt * c;
+        out[1] = x[1] + vdt * s;
+        out[2] = th;
+    }
+    static __device__ T wrap(T a)
+    {
+        const T tau = (T)(2.0 * kPi);
+        return a - tau * RealOps<T>::floor_((a + (T)kPi) / tau);
+    }
+    // log-mixture and, with g != nullptr, its gradient in (px, py)
+    static __device__ T mixture(const DevModel<T> &m, const T *z, const T *x, T *g)
+    {
+        const int nl = (int)m.p[5];
+        T mx = -RealOps<T>::inf(), s = 0, g0 = 0, g1 = 0;
+        for (int l = 0; l < nl; ++l) {
+            const T dx = x[0] - m.p[6 + 2 * l], dy = x[1] - m.p[7 + 2 * l];
+            const T r2 = dx * dx + dy * dy;
+            const T rho = RealOps<T>::sqrt_(r2);
+            const T er = z[0] - rho;
+            const T eb = wrap(z[1] - RealOps<T>::atan2_(dy, dx));
+            const T tl = (T)-0.5 * (er * er * m.aux[0] + eb * eb * m.aux[1]);
+            T l0 = 0, l1 = 0;
+            if (g && rho >= (T)1e-12) {
+                const T gr = er * m.aux[0] / rho, gb = eb * m.aux[1] / r2;
+                l0 = gr * dx - gb * dy;
+                l1 = gr * dy + gb * dx;
+            }
+            if (tl > mx) {
+                const T sc = RealOps<T>::exp_(mx - tl);
+                s = s * sc + (T)1;
+                g0 = g0 * sc + l0;
+                g1 = g1 * sc + l1;
+                mx = tl;
+            } else {
+                const T w = RealOps<T>::exp_(tl - mx);
+                s += w;
+                g0 += w * l0;
+                g1 += w * l1;
+            }
+        }
+        if (g) {
+            g[0] = g0 / s;
+            g[1] = g1 / s;
+        }
+        return mx + RealOps<T>::log_(s) + m.aux[2];
+    }
+    static __device__ T loglik(const DevModel<T> &m, const T *z, const uint8_t *mask, const T *x)
+    {
+        if (mask && !mask[0]) return (T)0;
+        return mixture(m, z, x, nullptr);
+    }
+    static __device__ void grad(const DevModel<T> &m, const T *z, const uint8_t *mask, const T *x, T *g)
+    {
+        g[0] = g[1] = g[2] = (T)0;
+        if (mask && !mask[0]) return;
+        mixture(m, z, x, g);
     }
 };
 

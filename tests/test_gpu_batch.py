@@ -160,6 +160,11 @@ def test_batch_plan_argument_errors():
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan(lg, [smsq.opts_from(wl.opts)], [q])
     assert e.value.status == smsq.ERR_UNSUPPORTED
+    se2 = S.make_workload("scenario_b", B=1, seed=0, T=3)     # the pose family runs outside plans
+    q2 = dict(q, x0=torch.zeros(3, device="cuda"), z=torch.zeros((3, 2), device="cuda"))
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.BatchPlan([smsq.Model(se2.model)], [smsq.opts_from(se2.opts)], [q2])
+    assert e.value.status == smsq.ERR_UNSUPPORTED
     imq = [smsq.opts(o.n_iter, o.step, o.bw_scale, kernel="imq") for o in opts]   # plans run the RBF kernel
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan(models, imq, seqs)

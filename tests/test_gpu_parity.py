@@ -124,7 +124,7 @@ def _particle_case(name, n, n_prev, seed):
     return wl, desc, xp, x
 
 
-@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss"])
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "scenario_b"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_viterbi_particle_mode(name, dt):
     announce("viterbi particle", name, dt)
@@ -232,6 +232,8 @@ SVGD_CASES = [
     ("cv4d", 130, 64, 20, 0.005),
     ("arm7", 200, 129, 20, 1e-5),
     ("lingauss", 70, 70, 30, 0.01),
+    ("scenario_b", 20, 20, 100, 1e-4),
+    ("scenario_b", 300, 130, 30, 1e-4),
 ]
 
 
@@ -367,6 +369,24 @@ def test_run_sequence_scenario_a_f64(kernel):
     assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
 
 
+def test_run_sequence_scenario_b_f64():
+    """The Sec. V-B pose scenario at its full length: N = 20, T = 630, L = 100,
+    one range-bearing measurement per step from an unknown landmark, with
+    outliers in the simulated data.  Algorithm 2 against the oracle."""
+    announce("run_sequence scenario_b f64")
+    wl = S.make_workload("scenario_b", B=1, seed=1006)
+    desc, o = wl.model, wl.opts
+    res = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 81, 0, o.n_iter, o.step)
+    model = smsq.Model(desc)
+    xmap, J = smsq.run_sequence(model, "f64", dev(wl.x0[0], torch.float64), dev(wl.z[0], torch.float64),
+                                None, wl.n, smsq.opts_from(o), 81)
+    xmap, J = host(xmap), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), wl.T)
+    print("J gpu %.10f oracle %.10f rel %.3e" % (J, res["J"], dJ))
+    assert dJ <= TOL_J
+    assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+
+
 @pytest.mark.parametrize("kernel", ["imq", "matern32"])
 def test_run_sequence_growth1d_kernels_f64(kernel):
     """Algorithm 2 with the ablation's kernels, 1-D growth model at N = 10."""
@@ -411,7 +431,7 @@ def test_run_sequence_map_conditioned_weights(name, n, T, L, dt):
 
 
 @pytest.mark.parametrize("name,n,T,L", [("range2d", 64, 12, 10), ("cv4d", 80, 8, 10), ("arm7", 96, 6, 10),
-                                        ("lingauss", 48, 10, 20)])
+                                        ("lingauss", 48, 10, 20), ("scenario_b", 20, 120, 100)])
 def test_run_sequence_f32_free_running(name, n, T, L):
     announce("run_sequence f32", name, n, T, L)
     wl = S.make_workload(name, B=1, seed=1001, T=T, n=n, n_iter=L)
@@ -508,6 +528,12 @@ def test_argument_errors():
     bad.d = 3
     with pytest.raises(smsq.SmsqError):
         smsq.Model(bad)
+    for field, value in ((5, 0.0), (5, 9.0), (5, 2.5), (3, 0.0), (4, -1.0), (6, float("nan"))):
+        pose = S.se2_model()          # landmark count 1..8, positive variances, finite constants
+        pose.params[field] = value
+        with pytest.raises(smsq.SmsqError) as e:
+            smsq.Model(pose)
+        assert e.value.status == smsq.ERR_INVALID
     with pytest.raises(smsq.SmsqError) as e:   # no such kernel
         smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None, x,
                        smsq.opts(2, 0.1, kernel=3))

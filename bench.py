@@ -11,7 +11,9 @@ whole-job Viterbi edge rate, the roofline of the dominant kernel (the fused
 step kernel, timed per launch with HIP events on the launch stream), a
 lattice-mode forward-recursion bandwidth figure, the CPU oracle timed on a
 bounded sample of the same workload, the kernel / bandwidth / particle-count
-ablation grid on the 1-D growth model (``kernel_ablation``), and (``batched``) a ragged mix of all
+ablation grid on the 1-D growth model (``kernel_ablation``), the SE(2) pose
+scenario with unknown landmark association (``scenario_b``), and
+(``batched``) a ragged mix of all
 four model families with uneven N and T (4096 sequences) run as batched
 plans: the plain method at the full iteration count (the reference MAP
 log-posterior of every sequence), then the plain method and the learned
@@ -62,6 +64,7 @@ def parse():
     p.add_argument("--train-steps", type=int, default=4000)
     p.add_argument("--train-seqs", type=int, default=700, help="plain sequences whose steps train the proposal")
     p.add_argument("--ablation-mc", type=int, default=50, help="sequences per kernel-ablation row (0: skip)")
+    p.add_argument("--scenario-b-mc", type=int, default=10, help="pose-scenario sequences per row (0: skip)")
     p.add_argument("--sweep", action="store_true",
                    help="print the batch / N / workload sweeps as one JSON line instead of the benchmark")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -161,6 +164,14 @@ ABLATION_GRID = [("rbf", 1.0, 10, 0), ("imq", 1.0, 10, 0), ("matern32", 1.0, 10,
                  ("rbf", 1.0, 10, 1), ("rbf", 1.0, 40, 1)]
 
 
+def mean_run_rmse(err, per_vector=False):
+    """err [runs, T, d]: the RMSE of each run over its steps and coordinates
+    (per_vector: the root mean squared Euclidean error of the vectors),
+    averaged over the runs."""
+    sq = np.sum(err ** 2, -1) if per_vector else np.mean(err ** 2, -1)
+    return float(np.mean(np.sqrt(np.mean(sq, 1))))
+
+
 def kernel_ablation(torch, smsq, mc: int):
     """The ablation grid on the paper's Scenario A model (Sec. V-A constants,
     FP64, T = 100, L = 100, eps = 0.5), mc synthetic Monte-Carlo sequences
@@ -183,11 +194,51 @@ def kernel_ablation(torch, smsq, mc: int):
         dt = time.perf_counter() - t0
         err = xmap.cpu().numpy()[:, 1:] - wl.truth[:, 1:]
         rows.append({"kernel": kernel, "bw_scale": bw, "N": n,
-                     "weights": "exp(phi_prev)" if weights else "uniform", "rmse": float(np.sqrt(np.mean(err ** 2))),
+                     "weights": "exp(phi_prev)" if weights else "uniform", "rmse": mean_run_rmse(err),
                      "mean_J": float(J.mean().item()), "seconds": dt,
                      "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
     return {"model": "scenario_a (Sec. V-A 1-D benchmark constants), FP64, T=100, L=100, eps=0.5",
             "sequences_per_row": mc, "rows": rows}
+
+
+# Stein-MAP-Seq RMSE printed for the Sec. V-B pose scenario (10 runs of 630
+# steps; per particle count).  Other simulator: context, not a target.
+PAPER_SCENARIO_B_RMSE = {10: 0.1121, 20: 0.0971, 40: 0.0983}
+
+
+def scenario_b_runs(torch, smsq, mc: int):
+    """The Sec. V-B pose scenario (SE(2), one range-bearing measurement per
+    step from an unknown landmark, outliers in the simulated data), FP32,
+    T = 630, L = 100, eps = 1e-4, mc Monte-Carlo sequences per particle count
+    in one batched run: RMSE of the MAP trajectory (all three coordinates,
+    and position only) against the simulated truth and against the
+    noise-free reference loop, mean J, wall time and rates."""
+    from paper_2312_08684_amd import scenarios as S
+    rows = []
+    for n in (10, 20, 40):
+        wl = S.make_workload("scenario_b", B=mc, seed=4000, n=n)
+        o = wl.opts
+        model = smsq.Model(wl.model)
+        x0 = torch.tensor(wl.x0, dtype=torch.float32, device="cuda")
+        z = torch.tensor(wl.z, dtype=torch.float32, device="cuda")
+        so = smsq.opts_from(o)
+        smsq.run_batch(model, "f32", x0, z, None, n, so, 6)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xmap, J = smsq.run_batch(model, "f32", x0, z, None, n, so, 6)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xm = xmap.cpu().numpy().astype(np.float64)[:, 1:]
+        err = xm - wl.truth[:, 1:]
+        ref = S.se2_reference(wl.model, wl.T)[None, 1:]
+        rows.append({"N": n, "rmse_state": mean_run_rmse(err),
+                     "rmse_position": mean_run_rmse(err[..., :2], per_vector=True),
+                     "rmse_state_vs_reference": mean_run_rmse(xm - ref),
+                     "paper_rmse": PAPER_SCENARIO_B_RMSE[n],
+                     "mean_J": float(J.mean().item()), "seconds": dt, "ms_per_time_step": dt / wl.T * 1e3,
+                     "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
+    return {"model": "scenario_b (Sec. V-B SE(2) pose, unknown landmark association, outliers), FP32, "
+                     "T=630, L=100, eps=1e-4", "sequences_per_row": mc, "rows": rows}
 
 
 def _events(torch):
@@ -484,6 +535,8 @@ def main():
     }
     if args.ablation_mc > 0:
         out["kernel_ablation"] = kernel_ablation(torch, smsq, args.ablation_mc)
+    if args.scenario_b_mc > 0:
+        out["scenario_b"] = scenario_b_runs(torch, smsq, args.scenario_b_mc)
     if args.batched_seqs > 0:
         out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs)
     if args.cpu_baseline:

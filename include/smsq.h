@@ -89,7 +89,7 @@ typedef struct {
     int d;              /* state dimension */
     int obs_dim;        /* length of one observation vector z_t */
     int n_obs;          /* length of one mask row (beacons / detections / 1) */
-    double q_var[8];    /* diagonal transition variances, first d used, > 0 */
+    double q_var[16];   /* diagonal transition variances, first d used, > 0 */
     double params[64];  /* family constants, layout above */
 } smsq_model_desc_t;
 

@@ -30,7 +30,7 @@ OK, INVALID, NONFINITE = 0, 1, 4
 
 class OrModel(C.Structure):
     _fields_ = [("kind", C.c_int), ("d", C.c_int), ("obs_dim", C.c_int), ("n_obs", C.c_int),
-                ("q_var", C.c_double * 8), ("params", C.c_double * 64)]
+                ("q_var", C.c_double * 16), ("params", C.c_double * 64)]
 
 
 def build(force: bool = False) -> str:
@@ -100,7 +100,7 @@ def model(desc) -> OrModel:
     """OrModel from any object with kind, d, obs_dim, n_obs, q_var, params."""
     m = OrModel()
     m.kind, m.d, m.obs_dim, m.n_obs = int(desc.kind), int(desc.d), int(desc.obs_dim), int(desc.n_obs)
-    q = np.zeros(8)
+    q = np.zeros(16)
     q[:len(desc.q_var)] = desc.q_var
     p = np.zeros(64)
     p[:len(desc.params)] = desc.params
@@ -130,7 +130,7 @@ def philox4x32_10(ctr, key):
 
 
 def normals(seed, seq, t, i, d):
-    out = np.zeros(8)
+    out = np.zeros(16)
     lib().or_normals(seed, seq, t, i, d, out)
     return out[:d].copy()
 

@@ -42,14 +42,14 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_MAXD 8
+#define OR_MAXD 16
 
 enum { OR_GROWTH1D = 0, OR_RANGE2D = 1, OR_CV4D = 2, OR_ARM7 = 3, OR_LINGAUSS = 4, OR_SE2 = 5 };
 enum { OR_OK = 0, OR_INVALID = 1, OR_NONFINITE = 4 };
 
 typedef struct {
     int kind, d, obs_dim, n_obs;
-    double q_var[8];
+    double q_var[16];
     double params[64];
 } or_model;
 
@@ -79,23 +79,26 @@ void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* d standard normals for particle i at step t of sequence seq.  Counter
- * (i, t, seq, block), key (seed low word, seed high word); each uniform is
- * (u + 0.5) * 2^-32 and pairs go through Box-Muller in FP64. */
+/* d (<= 16) standard normals for particle i at step t of sequence seq.
+ * Counter (i, t, seq, block), key (seed low word, seed high word); block b
+ * gives uniforms 4b..4b+3, each (u + 0.5) * 2^-32, and consecutive pairs go
+ * through Box-Muller in FP64.  Blocks are drawn as far as the pairs need, so
+ * the first eight normals are the same for every d. */
 void or_normals(uint64_t seed, uint32_t seq, uint32_t t, uint32_t i, int d, double *out)
 {
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
-    double u[8];
-    for (int blk = 0; blk < 2; ++blk) {
+    double u[16];
+    int pairs = (d + 1) / 2;
+    for (int blk = 0; 4 * blk < 2 * pairs; ++blk) {
         uint32_t ctr[4] = { i, t, seq, (uint32_t)blk };
         uint32_t r[4];
         or_philox4x32_10(ctr, key, r);
         for (int q = 0; q < 4; ++q) u[4 * blk + q] = ((double)r[q] + 0.5) * (1.0 / 4294967296.0);
     }
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < pairs; ++p) {
         double rad = sqrt(-2.0 * log(u[2 * p]));
         double ang = 2.0 * OR_PI * u[2 * p + 1];
-        if (2 * p < d) out[2 * p] = rad * cos(ang);
+        out[2 * p] = rad * cos(ang);
         if (2 * p + 1 < d) out[2 * p + 1] = rad * sin(ang);
     }
 }

@@ -37,7 +37,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 smsq_status_t check_desc(const smsq_model_desc_t *d)
 {
     if (!d) return SMSQ_ERR_INVALID;
-    for (int c = 0; c < d->d && c < 8; ++c)
+    if (d->d < 1 || d->d > 16) return SMSQ_ERR_INVALID;
+    for (int c = 0; c < d->d; ++c)
         if (!finite_pos(d->q_var[c])) return SMSQ_ERR_INVALID;
     switch (d->kind) {
     case SMSQ_MODEL_GROWTH1D:
@@ -85,7 +86,7 @@ template <typename T> DevModel<T> make_dev_model(const smsq_model_desc_t &d)
     m.obs_dim = d.obs_dim;
     m.n_obs = d.n_obs;
     double lz = 0.0;
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < 16; ++c) {
         if (c < d.d) {
             const double q = d.q_var[c];
             m.q[c] = (T)q;
@@ -652,7 +653,7 @@ smsq_status_t smsq_backtrack(smsq_dtype_t dtype, int batch, int T, int n, int d,
     if (!dtype_ok(dtype) || batch < 1 || T < 1 || n < 1 || !psi || !phi_T || !idx_out || !logpost_out)
         return SMSQ_ERR_INVALID;
     const bool gather = particles && x0 && xmap_out;
-    if (gather && (d < 1 || d > 8)) return SMSQ_ERR_INVALID;
+    if (gather && (d < 1 || d > 16)) return SMSQ_ERR_INVALID;
     if (!ws || ws_bytes < kHeader) return SMSQ_ERR_WORKSPACE;
     const long psi_b = (long)T * n, parts_b = (long)T * n * d;
     if (dtype == SMSQ_F64)

@@ -13,7 +13,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 // Padded row length of a d-dimensional particle in LDS: rows of 1, 2, 4 or 8
 // elements so that a row is read with one or two aligned vector loads.
-__host__ __device__ constexpr int dpad(int d) { return d <= 1 ? 1 : d <= 2 ? 2 : d <= 4 ? 4 : 8; }
+__host__ __device__ constexpr int dpad(int d) { return d <= 1 ? 1 : d <= 2 ? 2 : d <= 4 ? 4 : d <= 8 ? 8 : 16; }
 
 // ---- real-type dispatch -----------------------------------------------------
 template <typename T> struct RealOps;
@@ -85,28 +85,32 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
-// Up to 8 standard normals for (seed, sequence, step, particle): counter
-// (i, t, seq, block) for blocks 0 and 1, uniforms (u + 0.5) 2^-32, Box-Muller
-// in double precision.
-__device__ inline void normals8(uint64_t seed, uint32_t seq, uint32_t t, uint32_t i, int d,
-                                double *out)
+// D standard normals (D <= 16) for (seed, sequence, step, particle): counter
+// (i, t, seq, block) for blocks 0, 1, ... (four uniforms each, as many as
+// the D/2 Box-Muller pairs need), uniforms (u + 0.5) 2^-32, Box-Muller in
+// double precision.  The first eight normals do not depend on D.
+template <int D>
+__device__ inline void normals(uint64_t seed, uint32_t seq, uint32_t t, uint32_t i, double (&out)[D])
 {
+    static_assert(D >= 1 && D <= 16, "up to 16 normals");
+    constexpr int kBlocks = (D + 3) / 4;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    double u[8];
-    for (int blk = 0; blk < 2; ++blk) {
-        if (4 * blk >= d + (d & 1)) break;
+    double u[4 * kBlocks];
+#pragma unroll
+    for (int blk = 0; blk < kBlocks; ++blk) {
         U4 r = philox4x32_10(U4{i, t, seq, (uint32_t)blk}, k0, k1);
         u[4 * blk + 0] = ((double)r.x + 0.5) * (1.0 / 4294967296.0);
         u[4 * blk + 1] = ((double)r.y + 0.5) * (1.0 / 4294967296.0);
         u[4 * blk + 2] = ((double)r.z + 0.5) * (1.0 / 4294967296.0);
         u[4 * blk + 3] = ((double)r.w + 0.5) * (1.0 / 4294967296.0);
     }
-    for (int p = 0; 2 * p < d; ++p) {
+#pragma unroll
+    for (int p = 0; 2 * p < D; ++p) {
         const double rad = sqrt(-2.0 * log(u[2 * p]));
         double s, c;
         sincos(2.0 * kPi * u[2 * p + 1], &s, &c);
         out[2 * p] = rad * c;
-        if (2 * p + 1 < d) out[2 * p + 1] = rad * s;
+        if (2 * p + 1 < D) out[2 * p + 1] = rad * s;
     }
 }
 

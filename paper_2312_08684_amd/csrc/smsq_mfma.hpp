@@ -688,8 +688,8 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
 #pragma unroll
                 for (int c = 0; c < D; ++c) xp[c] = xprev[(long)j * D + c];
                 F::mean(m, a.t, xp, mu);
-                double nz[8];
-                normals8(a.seed, a.seq_offset + (uint32_t)b, (uint32_t)a.t, (uint32_t)i, D, nz);
+                double nz[D];
+                normals<D>(a.seed, a.seq_offset + (uint32_t)b, (uint32_t)a.t, (uint32_t)i, nz);
 #pragma unroll
                 for (int c = 0; c < D; ++c) xi[c] = (mu[c] + m.sqrt_q[c] * (float)nz[c]) - ref[c];
             }

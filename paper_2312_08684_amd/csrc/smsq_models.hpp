@@ -13,10 +13,10 @@ enum Kind { GROWTH1D = 0, RANGE2D = 1, CV4D = 2, ARM7 = 3, LINGAUSS = 4, SE2 = 5
 // Per-launch model constants, precomputed on the host in the kernel's type.
 template <typename T> struct DevModel {
     int kind, d, obs_dim, n_obs;
-    T q[8];        // transition variances
-    T inv_q[8];    // 1 / q
-    T sqrt_q[8];   // sqrt(q)
-    T rs[8];       // sqrt(log2(e) / (2 q)): x * rs puts -(x-m)^2/(2q) in log2 units
+    T q[16];       // transition variances
+    T inv_q[16];   // 1 / q
+    T sqrt_q[16];  // sqrt(q)
+    T rs[16];      // sqrt(log2(e) / (2 q)): x * rs puts -(x-m)^2/(2q) in log2 units
     T log_z;       // -1/2 sum_d log(2 pi q_d)
     T p[64];       // family parameters
     T aux[16];     // family constants (RANGE2D: 1/r_var; ARM7: cos alpha_i, sin alpha_i;

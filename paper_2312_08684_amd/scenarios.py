@@ -52,7 +52,7 @@ KIND_NAMES = {GROWTH1D: "growth1d", RANGE2D: "range2d", CV4D: "cv4d",
               ARM7: "arm7", LINGAUSS: "lingauss", SE2: "se2"}
 
 N_PARAMS = 64
-MAX_D = 8
+MAX_D = 16
 
 
 @dataclasses.dataclass
@@ -67,7 +67,7 @@ class ModelDesc:
     d: int
     obs_dim: int
     n_obs: int
-    q_var: np.ndarray          # [8] float64, first d used
+    q_var: np.ndarray          # [16] float64, first d used
     params: np.ndarray         # [64] float64
 
     def copy(self) -> "ModelDesc":

@@ -42,7 +42,7 @@ class SmsqError(RuntimeError):
 
 class ModelDesc(C.Structure):
     _fields_ = [("kind", C.c_int), ("d", C.c_int), ("obs_dim", C.c_int), ("n_obs", C.c_int),
-                ("q_var", C.c_double * 8), ("params", C.c_double * 64)]
+                ("q_var", C.c_double * 16), ("params", C.c_double * 64)]
 
 
 class BatchSeq(C.Structure):
@@ -191,7 +191,7 @@ class Model:
         L = load()
         md = ModelDesc()
         md.kind, md.d, md.obs_dim, md.n_obs = int(desc.kind), int(desc.d), int(desc.obs_dim), int(desc.n_obs)
-        q = np.zeros(8)
+        q = np.zeros(16)
         q[:len(desc.q_var)] = desc.q_var
         p = np.zeros(64)
         p[:len(desc.params)] = desc.params

@@ -54,6 +54,29 @@ def test_box_muller_normals_moments():
     assert not np.allclose(O.normals(1, 0, 1, 0, 4), O.normals(1, 1, 1, 0, 4))
 
 
+def test_box_muller_normals_up_to_sixteen():
+    """Sixteen normals take counter blocks 0..3; the first d of a longer draw
+    equal a draw of d (blocks are addressed by the counter, not by d), and
+    every coordinate is standard normal."""
+    for d in (1, 3, 8, 9, 14):
+        assert np.array_equal(O.normals(77, 2, 5, 11, d), O.normals(77, 2, 5, 11, 16)[:d])
+    zs = np.array([O.normals(99, 0, 3, i, 16) for i in range(3000)])
+    n = zs.shape[0]
+    for c in range(16):
+        assert abs(zs[:, c].mean()) < 5 / math.sqrt(n)
+        assert abs(zs[:, c].var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    assert stats.kstest(zs[:, 8:].reshape(-1), "norm").pvalue > 1e-4
+    # block 2 feeds normals 8..11 through Box-Muller of its four uniforms
+    key = [99, 0]
+    r = O.philox4x32_10([7, 3, 0, 2], key)
+    u = (np.asarray(r, dtype=np.float64) + 0.5) / 2.0 ** 32
+    want = [math.sqrt(-2 * math.log(u[0])) * math.cos(2 * math.pi * u[1]),
+            math.sqrt(-2 * math.log(u[0])) * math.sin(2 * math.pi * u[1]),
+            math.sqrt(-2 * math.log(u[2])) * math.cos(2 * math.pi * u[3]),
+            math.sqrt(-2 * math.log(u[2])) * math.sin(2 * math.pi * u[3])]
+    assert np.allclose(O.normals(99, 0, 3, 7, 12)[8:12], want, rtol=0, atol=1e-15)
+
+
 # ---------------------------------------------------------------------------
 # Models (eq. SSM and the scenario models)
 # ---------------------------------------------------------------------------

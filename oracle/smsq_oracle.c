@@ -15,7 +15,8 @@
  *
  * Section / equation map (paper numbering):
  *   models           Sec. II, eq. (SSM); scenario models of Sec. V (the
- *                    SE(2) pose with unknown landmark identity is Sec. V-B)
+ *                    SE(2) pose with unknown landmark identity is Sec. V-B,
+ *                    the 14-D second-order manipulator Sec. V-D)
  *   or_philox*       counter-based RNG (Salmon et al., SC'11), used only for
  *                    the predictive initial particles
  *   or_bandwidth     RBF kernel with the median-heuristic bandwidth (Sec. V
@@ -44,7 +45,7 @@
 
 #define OR_MAXD 16
 
-enum { OR_GROWTH1D = 0, OR_RANGE2D = 1, OR_CV4D = 2, OR_ARM7 = 3, OR_LINGAUSS = 4, OR_SE2 = 5 };
+enum { OR_GROWTH1D = 0, OR_RANGE2D = 1, OR_CV4D = 2, OR_ARM7 = 3, OR_LINGAUSS = 4, OR_SE2 = 5, OR_ARM14 = 6 };
 enum { OR_OK = 0, OR_INVALID = 1, OR_NONFINITE = 4 };
 
 typedef struct {
@@ -137,6 +138,16 @@ void or_transition_mean(const or_model *m, int t, const double *x, double *out)
         out[0] = x[0] + p[1] * p[0] * cos(th);
         out[1] = x[1] + p[1] * p[0] * sin(th);
         out[2] = th;
+        break;
+    }
+    case OR_ARM14: {
+        /* Sec. V-D second-order joints: q_t = q + qdot dt, qdot_t = qdot +
+         * u_{t-1} dt with u_{t-1,i} = amp sin(freq (t - 1) + phase_step i) */
+        double dt = p[22], amp = p[23], freq = p[24], ph = p[25];
+        for (int a = 0; a < 7; ++a) {
+            out[a] = x[a] + x[7 + a] * dt;
+            out[7 + a] = x[7 + a] + amp * sin(freq * (double)(t - 1) + ph * (double)a) * dt;
+        }
         break;
     }
     default: /* random walks: range2d, arm7 */
@@ -261,7 +272,8 @@ double or_loglik(const or_model *m, const double *z, const uint8_t *mask, const 
         for (int k = 0; k < nt; ++k) s += exp(terms[k] - mx);
         return -(double)(M - 1) * log(V) + mx + log(s);
     }
-    case OR_ARM7: {
+    case OR_ARM7:
+    case OR_ARM14: { /* the end effector depends on the joint angles x[0..7) only */
         if (!obs_on(mask, 0)) return 0.0;
         double pos[3];
         or_arm_fk(m, x, pos);
@@ -348,7 +360,8 @@ void or_grad_loglik(const or_model *m, const double *z, const uint8_t *mask, con
         }
         break;
     }
-    case OR_ARM7: {
+    case OR_ARM7:
+    case OR_ARM14: { /* zero in the joint velocities of the 14-D model */
         if (!obs_on(mask, 0)) break;
         double org[8][3], zax[8][3];
         arm_frames(m, x, org, zax);

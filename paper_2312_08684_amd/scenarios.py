@@ -31,6 +31,10 @@ Scenario shapes (synthetic stand-ins for the paper's workloads):
   measurement per step from one of four landmarks whose identity the
   estimator does not know; the simulated measurements carry heavy-tailed
   outliers that the estimator's likelihood does not model.
+* ``arm14``     -- the 14-D manipulator of Sec. V-D: joint angles and
+  velocities of the 7-joint DH chain under second-order dynamics driven by
+  joint-wise sinusoidal accelerations, observed through the end-effector
+  position.
 """
 from __future__ import annotations
 
@@ -47,9 +51,10 @@ CV4D = 2
 ARM7 = 3
 LINGAUSS = 4
 SE2 = 5
+ARM14 = 6
 
 KIND_NAMES = {GROWTH1D: "growth1d", RANGE2D: "range2d", CV4D: "cv4d",
-              ARM7: "arm7", LINGAUSS: "lingauss", SE2: "se2"}
+              ARM7: "arm7", LINGAUSS: "lingauss", SE2: "se2", ARM14: "arm14"}
 
 N_PARAMS = 64
 MAX_D = 16
@@ -157,6 +162,23 @@ def arm7_model(link_a: np.ndarray, alpha: np.ndarray = ARM7_ALPHA,
                  [sigma_z ** 2] + list(link_a) + list(alpha) + list(link_d))
 
 
+def arm14_model(link_a: np.ndarray, alpha: np.ndarray = ARM7_ALPHA,
+                link_d: Optional[np.ndarray] = None, dt=0.02, q_p=1.0, q_v=5e-3,
+                sigma_z=0.1, amp=0.5, freq=0.2, phase_step=1.0) -> ModelDesc:
+    """Sec. V-D: x = [q; qdot] in R^14, q_t = q + qdot dt, qdot_t = qdot +
+    u_{t-1} dt + noise, u_{t-1,i} = amp sin(freq (t - 1) + phase_step i);
+    Q = diag(q_p dt^2 I_7, q_v I_7); z = end-effector position + N(0, sigma_z^2 I).
+
+    params = [r_var, a_1..a_7, alpha_1..alpha_7, d_1..d_7, dt, amp, freq, phase_step].
+    """
+    link_a = np.asarray(link_a, dtype=np.float64)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    link_d = np.zeros(7) if link_d is None else np.asarray(link_d, dtype=np.float64)
+    assert link_a.shape == (7,) and alpha.shape == (7,) and link_d.shape == (7,)
+    return _desc(ARM14, 14, 3, 1, [q_p * dt * dt] * 7 + [q_v] * 7,
+                 [sigma_z ** 2] + list(link_a) + list(alpha) + list(link_d) + [dt, amp, freq, phase_step])
+
+
 def lingauss_model(A: np.ndarray, C: np.ndarray, q_var, r_var) -> ModelDesc:
     """x_t = A x_{t-1} + N(0, diag q); z = C x + N(0, diag r).
 
@@ -228,6 +250,12 @@ def _se2_f(p, x):
     return np.array([x[0] + p[1] * p[0] * math.cos(th), x[1] + p[1] * p[0] * math.sin(th), th])
 
 
+def _arm14_f(p, t, x):
+    dt, amp, freq, ph = p[22], p[23], p[24], p[25]
+    u = amp * np.sin(freq * (t - 1) + ph * np.arange(7))
+    return np.concatenate([x[:7] + dt * x[7:], x[7:] + dt * u])
+
+
 def _wrap(a):
     return (a + math.pi) % (2.0 * math.pi) - math.pi
 
@@ -262,6 +290,10 @@ def simulate(model: ModelDesc, T: int, B: int, seed: int, *,
             x = rng.uniform(-0.5, 0.5, size=7)
         elif model.kind == SE2:
             x = se2_reference(model, 0)[0] + SE2_SIGMA0 * rng.normal(size=3)
+        elif model.kind == ARM14:
+            # joint angles U[-0.5, 0.5] at rest, then N(0, diag(1 deg^2, 2 deg^2))
+            mu0 = np.concatenate([rng.uniform(-0.5, 0.5, size=7), np.zeros(7)])
+            x = mu0 + np.radians(np.repeat([1.0, 2.0], 7)) * rng.normal(size=14)
         else:
             x = rng.normal(0.0, 1.0, size=d)
         truth[b, 0] = x
@@ -276,6 +308,8 @@ def simulate(model: ModelDesc, T: int, B: int, seed: int, *,
                 m = A @ x
             elif model.kind == SE2:
                 m = _se2_f(p, x)
+            elif model.kind == ARM14:
+                m = _arm14_f(p, t, x)
             else:
                 m = x.copy()
             x = m + sq * rng.normal(size=d)
@@ -304,9 +338,9 @@ def simulate(model: ModelDesc, T: int, B: int, seed: int, *,
                 dx, dy = x[0] - lm[0], x[1] - lm[1]
                 z[b, t - 1, 0] = math.hypot(dx, dy) + sc * math.sqrt(p[3]) * rng.normal()
                 z[b, t - 1, 1] = _wrap(math.atan2(dy, dx) + sc * math.sqrt(p[4]) * rng.normal())
-            elif model.kind == ARM7:
+            elif model.kind in (ARM7, ARM14):
                 la, al, ld = p[1:8], p[8:15], p[15:22]
-                z[b, t - 1] = (dh_forward_kinematics(x, la, al, ld)
+                z[b, t - 1] = (dh_forward_kinematics(x[:7], la, al, ld)
                                + math.sqrt(p[0]) * rng.normal(size=3))
             else:
                 o = model.obs_dim
@@ -345,6 +379,9 @@ def _model_for(name: str, seed: int) -> ModelDesc:
         return growth1d_model(a=0.9, b=10.0, c=8.0, omega=1.2, phase=-1.2, q=5.0, kobs=0.05, r=16.0)
     if name == "scenario_b":
         return se2_model()
+    if name == "scenario_d":
+        # Sec. V-D; the DH chain is not tabulated: the arm7 chain's links
+        return arm14_model(rng.uniform(0.1, 0.4, size=7))
     if name == "lingauss":
         d = 2
         A = np.array([[1.0, 0.1], [0.0, 0.95]])
@@ -368,6 +405,10 @@ PRESETS = {
     # heading's transition precision 1/(0.105 * 0.1)^2 ~ 9e3 makes the
     # stated 0.005 diverge (eps * curvature must stay below 2)
     "scenario_b": (20, 630, 100, 1e-4, "f32"),
+    # Sec. V-D: N_s = 20 (of 10..30), 100 steps (length not stated), 100
+    # iterations; eps = 2e-4 because the joint-angle transition precision
+    # 1/(q_p dt^2) = 2500 makes the stated 0.005 diverge
+    "scenario_d": (20, 100, 100, 2e-4, "f32"),
 }
 
 

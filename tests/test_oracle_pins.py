@@ -84,6 +84,7 @@ def test_box_muller_normals_up_to_sixteen():
 def _all_models():
     m = {name: S._model_for(name, 0) for name in ("growth1d", "range2d", "cv4d", "arm7", "lingauss")}
     m["se2"] = S.se2_model()
+    m["arm14"] = S._model_for("scenario_d", 0)
     return m
 
 
@@ -106,8 +107,8 @@ def _independent_loglik(desc, z, mask, x):
             return math.log(1 - pd)
         dens = sum(stats.multivariate_normal.pdf(zz, x[:2], rv * np.eye(2)) for zz in dets)
         return -(M - 1) * math.log(V) + math.log((1 - pd) / V + pd / M * dens)
-    if desc.kind == S.ARM7:
-        pos = S.dh_forward_kinematics(x, p[1:8], p[8:15], p[15:22])
+    if desc.kind in (S.ARM7, S.ARM14):
+        pos = S.dh_forward_kinematics(x[:7], p[1:8], p[8:15], p[15:22])
         return stats.multivariate_normal.logpdf(z, pos, p[0] * np.eye(3)) if on(0) else 0.0
     if desc.kind == S.LINGAUSS:
         d, o = desc.d, desc.obs_dim
@@ -132,8 +133,8 @@ def _independent_loglik(desc, z, mask, x):
 def _random_state(desc, rng):
     if desc.kind == S.RANGE2D:
         return rng.uniform(0, 20, size=2)
-    if desc.kind == S.ARM7:
-        return rng.uniform(-1, 1, size=7)
+    if desc.kind in (S.ARM7, S.ARM14):
+        return rng.uniform(-1, 1, size=desc.d)
     if desc.kind == S.SE2:
         return np.array([rng.uniform(-15, 15), rng.uniform(-15, 15), rng.uniform(-7, 7)])
     return rng.normal(0, 2, size=desc.d)
@@ -144,15 +145,15 @@ def _random_obs(desc, rng, x):
         z = rng.normal(0, 3, size=desc.obs_dim)
         z[:2] = x[:2] + rng.normal(0, 0.3, size=2)
         return z
-    if desc.kind == S.ARM7:
-        return S.dh_forward_kinematics(x, desc.params[1:8], desc.params[8:15], desc.params[15:22]) \
+    if desc.kind in (S.ARM7, S.ARM14):
+        return S.dh_forward_kinematics(x[:7], desc.params[1:8], desc.params[8:15], desc.params[15:22]) \
             + rng.normal(0, 0.02, size=3)
     if desc.kind == S.SE2:
         return np.array([rng.uniform(0, 30), rng.uniform(-math.pi, math.pi)])
     return rng.normal(0, 5, size=desc.obs_dim) + (10 if desc.kind == S.RANGE2D else 0)
 
 
-@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "se2"])
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "se2", "arm14"])
 def test_loglik_matches_scipy_densities(name):
     desc = _all_models()[name]
     rng = np.random.default_rng(1)
@@ -167,7 +168,7 @@ def test_loglik_matches_scipy_densities(name):
         assert got == pytest.approx(want, rel=1e-10, abs=1e-9)
 
 
-@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "se2"])
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "se2", "arm14"])
 def test_grad_loglik_matches_finite_differences(name):
     desc = _all_models()[name]
     rng = np.random.default_rng(2)
@@ -204,6 +205,23 @@ def test_transition_means_match_model_definitions():
     lg = m["lingauss"]
     x2 = rng.normal(size=2)
     assert np.allclose(O.transition_mean(lg, 1, x2), np.array([[1.0, 0.1], [0.0, 0.95]]) @ x2)
+    # Sec. V-D: q_t = q + qdot dt, qdot_t = qdot + u_{t-1} dt with
+    # u_{t-1,i} = 0.5 sin(0.2 (t - 1) + (i - 1)), dt = 0.02 (joints i = 1..7)
+    arm = m["arm14"]
+    x14 = rng.normal(size=14)
+    for t in (1, 2, 40):
+        u = [0.5 * math.sin(0.2 * (t - 1) + (i - 1)) for i in range(1, 8)]
+        want = np.concatenate([x14[:7] + 0.02 * x14[7:], x14[7:] + 0.02 * np.array(u)])
+        assert np.allclose(O.transition_mean(arm, t, x14), want, rtol=0, atol=1e-15)
+    assert np.allclose(arm.q_var[:14], [0.02 ** 2] * 7 + [5e-3] * 7, rtol=1e-15)
+    # the end effector sees the joint angles only
+    z = rng.normal(size=3)
+    x14b = x14.copy()
+    x14b[7:] += 3.0
+    assert O.loglik(arm, z, None, x14) == O.loglik(arm, z, None, x14b)
+    assert np.array_equal(O.grad_loglik(arm, z, None, x14)[7:], np.zeros(7))
+    same_chain = S.ModelDesc(S.ARM7, 7, 3, 1, arm.q_var.copy(), arm.params.copy())
+    assert np.array_equal(O.grad_loglik(arm, z, None, x14)[:7], O.grad_loglik(same_chain, z, None, x14[:7]))
 
 
 def test_se2_pose_model_closed_forms():

@@ -12,7 +12,8 @@ step kernel, timed per launch with HIP events on the launch stream), a
 lattice-mode forward-recursion bandwidth figure, the CPU oracle timed on a
 bounded sample of the same workload, the kernel / bandwidth / particle-count
 ablation grid on the 1-D growth model (``kernel_ablation``), the SE(2) pose
-scenario with unknown landmark association (``scenario_b``), and
+scenario with unknown landmark association (``scenario_b``), the 14-D
+manipulator (``scenario_d``), and
 (``batched``) a ragged mix of all
 four model families with uneven N and T (4096 sequences) run as batched
 plans: the plain method at the full iteration count (the reference MAP
@@ -65,6 +66,7 @@ def parse():
     p.add_argument("--train-seqs", type=int, default=700, help="plain sequences whose steps train the proposal")
     p.add_argument("--ablation-mc", type=int, default=50, help="sequences per kernel-ablation row (0: skip)")
     p.add_argument("--scenario-b-mc", type=int, default=10, help="pose-scenario sequences per row (0: skip)")
+    p.add_argument("--scenario-d-mc", type=int, default=20, help="14-D arm sequences per row (0: skip)")
     p.add_argument("--sweep", action="store_true",
                    help="print the batch / N / workload sweeps as one JSON line instead of the benchmark")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -239,6 +241,46 @@ def scenario_b_runs(torch, smsq, mc: int):
                      "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
     return {"model": "scenario_b (Sec. V-B SE(2) pose, unknown landmark association, outliers), FP32, "
                      "T=630, L=100, eps=1e-4", "sequences_per_row": mc, "rows": rows}
+
+
+# Stein-MAP-Seq end-effector (m) and joint-angle (rad) RMSE printed for the
+# Sec. V-D manipulator (20 runs; per particle count).  Context, not a target.
+PAPER_SCENARIO_D_RMSE = {10: (0.4686, 0.1918), 20: (0.4624, 0.1843), 30: (0.3560, 0.1720)}
+
+
+def scenario_d_runs(torch, smsq, mc: int):
+    """The Sec. V-D 14-D manipulator (joint angles and velocities, end-effector
+    observations), FP32 on the vector-ALU step kernel, T = 100, L = 100,
+    eps = 2e-4, mc Monte-Carlo sequences per particle count in one batched
+    run: end-effector and joint-angle RMSE of the MAP trajectory against the
+    simulated truth, mean J, wall time and rates."""
+    from paper_2312_08684_amd import scenarios as S
+    rows = []
+    for n in (10, 20, 30):
+        wl = S.make_workload("scenario_d", B=mc, seed=5000, n=n)
+        o, p = wl.opts, wl.model.params
+        model = smsq.Model(wl.model)
+        x0 = torch.tensor(wl.x0, dtype=torch.float32, device="cuda")
+        z = torch.tensor(wl.z, dtype=torch.float32, device="cuda")
+        so = smsq.opts_from(o)
+        smsq.run_batch(model, "f32", x0, z, None, n, so, 7)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xmap, J = smsq.run_batch(model, "f32", x0, z, None, n, so, 7)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xm = xmap.cpu().numpy().astype(np.float64)[:, 1:]
+        fk = lambda q: S.dh_forward_kinematics(q, p[1:8], p[8:15], p[15:22])
+        ee = np.array([[fk(v[:7]) for v in run] for run in xm])
+        ee_true = np.array([[fk(v[:7]) for v in run] for run in wl.truth[:, 1:]])
+        pe, pq = PAPER_SCENARIO_D_RMSE[n]
+        rows.append({"N": n, "rmse_end_effector": mean_run_rmse(ee - ee_true, per_vector=True),
+                     "rmse_joint_angles": mean_run_rmse(xm[..., :7] - wl.truth[:, 1:, :7]),
+                     "paper_rmse_end_effector": pe, "paper_rmse_joint_angles": pq,
+                     "mean_J": float(J.mean().item()), "seconds": dt, "ms_per_time_step": dt / wl.T * 1e3,
+                     "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
+    return {"model": "scenario_d (Sec. V-D 7-DoF arm, joint angles and velocities, d=14), FP32, "
+                     "T=100, L=100, eps=2e-4", "sequences_per_row": mc, "rows": rows}
 
 
 def _events(torch):
@@ -537,6 +579,8 @@ def main():
         out["kernel_ablation"] = kernel_ablation(torch, smsq, args.ablation_mc)
     if args.scenario_b_mc > 0:
         out["scenario_b"] = scenario_b_runs(torch, smsq, args.scenario_b_mc)
+    if args.scenario_d_mc > 0:
+        out["scenario_d"] = scenario_d_runs(torch, smsq, args.scenario_d_mc)
     if args.batched_seqs > 0:
         out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs)
     if args.cpu_baseline:

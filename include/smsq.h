@@ -74,6 +74,13 @@ typedef enum { SMSQ_F32 = 0, SMSQ_F64 = 1 } smsq_dtype_t;
  *             identity: p(z|x) = (1/n_l) sum_l N(z_r; |P - G_l|, p3)
  *             N(wrap(z_b - atan2(py - G_l,y, px - G_l,x)); 0, p4), the bearing
  *             residual mapped into [-pi, pi).  Batched plans reject it.
+ *   ARM14     d=14 (7 joint angles q, 7 joint velocities qdot), obs_dim=3,
+ *             n_obs=1 (Sec. V-D).  The DH chain and r_var use ARM7's slots
+ *             p[0..22); dt=p22, amp=p23, freq=p24, phase_step=p25:
+ *             f_t(x) = (q + qdot dt, qdot + u_{t-1} dt), u_{t-1,i} = amp
+ *             sin(freq (t-1) + phase_step i), i = 0..6; z = end-effector
+ *             position of q + N(0, p0 I).  Runs on the vector-ALU step
+ *             kernel; batched plans reject it.
  */
 typedef enum {
     SMSQ_MODEL_GROWTH1D = 0,
@@ -81,7 +88,8 @@ typedef enum {
     SMSQ_MODEL_CV4D = 2,
     SMSQ_MODEL_ARM7 = 3,
     SMSQ_MODEL_LINGAUSS = 4,
-    SMSQ_MODEL_SE2 = 5
+    SMSQ_MODEL_SE2 = 5,
+    SMSQ_MODEL_ARM14 = 6
 } smsq_model_kind_t;
 
 typedef struct {

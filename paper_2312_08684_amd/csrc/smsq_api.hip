@@ -58,6 +58,11 @@ smsq_status_t check_desc(const smsq_model_desc_t *d)
     case SMSQ_MODEL_ARM7:
         if (d->d != 7 || d->obs_dim != 3 || d->n_obs != 1 || !finite_pos(d->params[0])) return SMSQ_ERR_INVALID;
         return SMSQ_OK;
+    case SMSQ_MODEL_ARM14:
+        if (d->d != 14 || d->obs_dim != 3 || d->n_obs != 1 || !finite_pos(d->params[0])) return SMSQ_ERR_INVALID;
+        for (int c = 22; c < 26; ++c)
+            if (!std::isfinite(d->params[c])) return SMSQ_ERR_INVALID;
+        return SMSQ_OK;
     case SMSQ_MODEL_SE2: {
         const int nl = (int)d->params[5];
         if (d->d != 3 || d->obs_dim != 2 || d->n_obs != 1 || nl < 1 || nl > 8 || (double)nl != d->params[5])
@@ -99,11 +104,16 @@ template <typename T> DevModel<T> make_dev_model(const smsq_model_desc_t &d)
     m.log_z = (T)(-0.5 * lz);
     for (int c = 0; c < 64; ++c) m.p[c] = (T)d.params[c];
     if (d.kind == SMSQ_MODEL_RANGE2D) m.aux[0] = (T)(1.0 / d.params[0]);
-    if (d.kind == SMSQ_MODEL_ARM7)
+    if (d.kind == SMSQ_MODEL_ARM7 || d.kind == SMSQ_MODEL_ARM14)
         for (int i = 0; i < 7; ++i) {
             m.aux[i] = (T)std::cos(d.params[8 + i]);
             m.aux[7 + i] = (T)std::sin(d.params[8 + i]);
         }
+    if (d.kind == SMSQ_MODEL_ARM14) {
+        m.grow[0] = d.params[23];
+        m.grow[1] = d.params[24];
+        m.grow[2] = d.params[25];
+    }
     if (d.kind == SMSQ_MODEL_SE2) {
         m.aux[0] = (T)(1.0 / d.params[3]);
         m.aux[1] = (T)(1.0 / d.params[4]);
@@ -197,9 +207,9 @@ smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int 
 template <>
 smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
 {
-    // the matrix-core kernel runs the RBF kernel; IMQ and Matern take the
-    // vector-ALU kernel
-    if (a.kernel == 0 && use_mfma(a.n, a.n_prev)) {
+    // the matrix-core kernel runs the RBF kernel on states of up to 7
+    // dimensions; IMQ, Matern and the 14-D model take the vector-ALU kernel
+    if (a.kernel == 0 && d.d <= 7 && use_mfma(a.n, a.n_prev)) {
         switch (d.kind) {
         case SMSQ_MODEL_GROWTH1D: return launch_mfma_kd<GROWTH1D, 1>(a, batch, s);
         case SMSQ_MODEL_RANGE2D: return launch_mfma_kd<RANGE2D, 2>(a, batch, s);
@@ -222,6 +232,7 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
     case SMSQ_MODEL_CV4D: return launch_step_kd<float, CV4D, 4>(a, batch, s);
     case SMSQ_MODEL_ARM7: return launch_step_kd<float, ARM7, 7>(a, batch, s);
     case SMSQ_MODEL_SE2: return launch_step_kd<float, SE2, 3>(a, batch, s);
+    case SMSQ_MODEL_ARM14: return launch_step_kd<float, ARM14, 14>(a, batch, s);
     case SMSQ_MODEL_LINGAUSS:
         switch (d.d) {
         case 1: return launch_step_kd<float, LINGAUSS, 1>(a, batch, s);
@@ -242,6 +253,7 @@ smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<dou
     case SMSQ_MODEL_CV4D: return launch_step_kd<double, CV4D, 4>(a, batch, s);
     case SMSQ_MODEL_ARM7: return launch_step_kd<double, ARM7, 7>(a, batch, s);
     case SMSQ_MODEL_SE2: return launch_step_kd<double, SE2, 3>(a, batch, s);
+    case SMSQ_MODEL_ARM14: return launch_step_kd<double, ARM14, 14>(a, batch, s);
     case SMSQ_MODEL_LINGAUSS:
         switch (d.d) {
         case 1: return launch_step_kd<double, LINGAUSS, 1>(a, batch, s);

@@ -8,7 +8,7 @@
 
 namespace smsq {
 
-enum Kind { GROWTH1D = 0, RANGE2D = 1, CV4D = 2, ARM7 = 3, LINGAUSS = 4, SE2 = 5 };
+enum Kind { GROWTH1D = 0, RANGE2D = 1, CV4D = 2, ARM7 = 3, LINGAUSS = 4, SE2 = 5, ARM14 = 6 };
 
 // Per-launch model constants, precomputed on the host in the kernel's type.
 template <typename T> struct DevModel {
@@ -21,7 +21,8 @@ template <typename T> struct DevModel {
     T p[64];       // family parameters
     T aux[16];     // family constants (RANGE2D: 1/r_var; ARM7: cos alpha_i, sin alpha_i;
                    // SE2: 1/r_var, 1/b_var, log-density constant of one landmark)
-    double grow[3]; // GROWTH1D cosine term c, omega, phase, kept in double
+    double grow[3]; // GROWTH1D cosine term c, omega, phase; ARM14 input amplitude,
+                    // frequency, phase step (kept in double)
 };
 
 template <typename T, int KIND, int D> struct Family;
@@ -233,6 +234,36 @@ template <typename T> struct Family<T, ARM7, 7> {
             g[i] = c0 * e0 + c1 * e1 + c2 * e2;
             f.advance(ct[i], st[i], m.aux[i], m.aux[7 + i], m.p[1 + i], m.p[15 + i]);
         }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// 14-D manipulator of Sec. V-D, x = [q; qdot]: q_t = q + qdot dt and
+// qdot_t = qdot + u_{t-1} dt with u_{t-1,i} = amp sin(freq (t - 1) + phase_step i).
+// The observation is the end effector of the same DH chain as ARM7, whose
+// constants sit at the same parameter slots: the likelihood and its
+// joint-angle gradient are ARM7's, the velocity gradient is zero.
+template <typename T> struct Family<T, ARM14, 14> {
+    using Arm = Family<T, ARM7, 7>;
+    static __device__ void mean(const DevModel<T> &m, int t, const T *x, T *out)
+    {
+        const T dt = m.p[22];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+            const T u = (T)(m.grow[0] * sin(m.grow[1] * (double)(t - 1) + m.grow[2] * (double)a));
+            out[a] = x[a] + x[7 + a] * dt;
+            out[7 + a] = x[7 + a] + u * dt;
+        }
+    }
+    static __device__ T loglik(const DevModel<T> &m, const T *z, const uint8_t *mask, const T *x)
+    {
+        return Arm::loglik(m, z, mask, x);
+    }
+    static __device__ void grad(const DevModel<T> &m, const T *z, const uint8_t *mask, const T *x, T *g)
+    {
+        Arm::grad(m, z, mask, x, g);
+#pragma unroll
+        for (int a = 7; a < 14; ++a) g[a] = (T)0;
     }
 };
 

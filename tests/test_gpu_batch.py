@@ -165,6 +165,11 @@ def test_batch_plan_argument_errors():
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan([smsq.Model(se2.model)], [smsq.opts_from(se2.opts)], [q2])
     assert e.value.status == smsq.ERR_UNSUPPORTED
+    arm = S.make_workload("scenario_d", B=1, seed=0, T=3)     # and so does the 14-D manipulator
+    q3 = dict(q, x0=torch.zeros(14, device="cuda"), z=torch.zeros((3, 3), device="cuda"))
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.BatchPlan([smsq.Model(arm.model)], [smsq.opts_from(arm.opts)], [q3])
+    assert e.value.status == smsq.ERR_UNSUPPORTED
     imq = [smsq.opts(o.n_iter, o.step, o.bw_scale, kernel="imq") for o in opts]   # plans run the RBF kernel
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan(models, imq, seqs)

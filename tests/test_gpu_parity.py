@@ -124,7 +124,7 @@ def _particle_case(name, n, n_prev, seed):
     return wl, desc, xp, x
 
 
-@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "scenario_b"])
+@pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "scenario_b", "scenario_d"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_viterbi_particle_mode(name, dt):
     announce("viterbi particle", name, dt)
@@ -234,6 +234,8 @@ SVGD_CASES = [
     ("lingauss", 70, 70, 30, 0.01),
     ("scenario_b", 20, 20, 100, 1e-4),
     ("scenario_b", 300, 130, 30, 1e-4),
+    ("scenario_d", 20, 20, 100, 2e-4),
+    ("scenario_d", 150, 70, 30, 2e-4),
 ]
 
 
@@ -387,6 +389,23 @@ def test_run_sequence_scenario_b_f64():
     assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
 
 
+def test_run_sequence_scenario_d_f64():
+    """The Sec. V-D 14-D manipulator (joint angles and velocities, end-effector
+    observations): N = 20, T = 100, L = 100, Algorithm 2 against the oracle."""
+    announce("run_sequence scenario_d f64")
+    wl = S.make_workload("scenario_d", B=1, seed=1007)
+    desc, o = wl.model, wl.opts
+    res = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], None, 83, 0, o.n_iter, o.step)
+    model = smsq.Model(desc)
+    xmap, J = smsq.run_sequence(model, "f64", dev(wl.x0[0], torch.float64), dev(wl.z[0], torch.float64),
+                                None, wl.n, smsq.opts_from(o), 83)
+    xmap, J = host(xmap), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), wl.T)
+    print("J gpu %.10f oracle %.10f rel %.3e" % (J, res["J"], dJ))
+    assert dJ <= TOL_J
+    assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+
+
 @pytest.mark.parametrize("kernel", ["imq", "matern32"])
 def test_run_sequence_growth1d_kernels_f64(kernel):
     """Algorithm 2 with the ablation's kernels, 1-D growth model at N = 10."""
@@ -431,7 +450,8 @@ def test_run_sequence_map_conditioned_weights(name, n, T, L, dt):
 
 
 @pytest.mark.parametrize("name,n,T,L", [("range2d", 64, 12, 10), ("cv4d", 80, 8, 10), ("arm7", 96, 6, 10),
-                                        ("lingauss", 48, 10, 20), ("scenario_b", 20, 120, 100)])
+                                        ("lingauss", 48, 10, 20), ("scenario_b", 20, 120, 100),
+                                        ("scenario_d", 20, 40, 100)])
 def test_run_sequence_f32_free_running(name, n, T, L):
     announce("run_sequence f32", name, n, T, L)
     wl = S.make_workload(name, B=1, seed=1001, T=T, n=n, n_iter=L)
@@ -534,6 +554,15 @@ def test_argument_errors():
         with pytest.raises(smsq.SmsqError) as e:
             smsq.Model(pose)
         assert e.value.status == smsq.ERR_INVALID
+    for field, value in (("d", 7), ("d", 17), ("obs_dim", 2)):
+        arm = S._model_for("scenario_d", 0)   # d = 14 exactly; at most 16 anywhere
+        setattr(arm, field, value)
+        with pytest.raises(smsq.SmsqError):
+            smsq.Model(arm)
+    arm = S._model_for("scenario_d", 0)
+    arm.params[24] = float("inf")
+    with pytest.raises(smsq.SmsqError):
+        smsq.Model(arm)
     with pytest.raises(smsq.SmsqError) as e:   # no such kernel
         smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None, x,
                        smsq.opts(2, 0.1, kernel=3))

@@ -13,7 +13,8 @@ lattice-mode forward-recursion bandwidth figure, the CPU oracle timed on a
 bounded sample of the same workload, the kernel / bandwidth / particle-count
 ablation grid on the 1-D growth model (``kernel_ablation``), the SE(2) pose
 scenario with unknown landmark association (``scenario_b``), the 14-D
-manipulator (``scenario_d``), and
+manipulator (``scenario_d``), the PF-MAP-Seq forward recursion on
+bootstrap-PF particle sets (``pf_map_seq``), and
 (``batched``) a ragged mix of all
 four model families with uneven N and T (4096 sequences) run as batched
 plans: the plain method at the full iteration count (the reference MAP
@@ -67,6 +68,7 @@ def parse():
     p.add_argument("--ablation-mc", type=int, default=50, help="sequences per kernel-ablation row (0: skip)")
     p.add_argument("--scenario-b-mc", type=int, default=10, help="pose-scenario sequences per row (0: skip)")
     p.add_argument("--scenario-d-mc", type=int, default=20, help="14-D arm sequences per row (0: skip)")
+    p.add_argument("--pf-map-seq", type=int, default=1, help="PF-MAP-Seq forward-recursion workload (0: skip)")
     p.add_argument("--sweep", action="store_true",
                    help="print the batch / N / workload sweeps as one JSON line instead of the benchmark")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -281,6 +283,94 @@ def scenario_d_runs(torch, smsq, mc: int):
                      "particle_iters_per_s": mc * wl.T * n * o.n_iter / dt})
     return {"model": "scenario_d (Sec. V-D 7-DoF arm, joint angles and velocities, d=14), FP32, "
                      "T=100, L=100, eps=2e-4", "sequences_per_row": mc, "rows": rows}
+
+
+# Per-step computation times the paper prints for the range-only scenario
+# (Sec. V-C timing table, ms): PF-MAP-Seq by particle count, and
+# Stein-MAP-Seq by particle count.  A laptop CPU; context, not a target.
+PAPER_SCENARIO_C_MS = {"pf_map_seq": {1000: 58.94, 2000: 162.01, 4000: 505.32},
+                       "stein_map_seq": {20: 10.82, 30: 13.60, 40: 16.44}}
+
+
+def pf_map_seq(torch, smsq):
+    """The PF-MAP-Seq forward recursion as a workload of the particle-mode
+    kernel: bootstrap-PF particle sets of the range-only model (T = 200, one
+    beacon visible in steps 80..120) at N = 1000, 2000, 4000, FP32.  Per step:
+    the kernel's time (HIP events around back-to-back launches on the launch
+    stream), the whole recursion + backtrack wall time per step, edges/s and
+    the counted vector-ALU rate (N N_p (2d + 4) flops per launch).  Beside it,
+    Stein-MAP-Seq's own per-step time on one sequence at N = 20, 30, 40
+    (L = 100, eps = 0.005)."""
+    from paper_2312_08684_amd import scenarios as S
+    wl = S.make_workload("range2d", B=1, seed=6000)
+    T, d = wl.T, wl.model.d
+    model = smsq.Model(wl.model)
+    ws = smsq.workspace()
+    z = torch.tensor(wl.z[0], dtype=torch.float32, device="cuda")
+    zm = torch.tensor(wl.mask[0], dtype=torch.uint8, device="cuda")
+    x0 = torch.tensor(wl.x0[0][None, :], dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in (1000, 2000, 4000):
+        parts = torch.tensor(S.bootstrap_pf_particles(wl.model, wl.x0[0], wl.z[0], wl.mask[0], n, seed=10),
+                             dtype=torch.float32, device="cuda")
+        psi_all = torch.empty((T, n), dtype=torch.int32, device="cuda")
+
+        def recursion():
+            phi = torch.zeros(1, dtype=torch.float32, device="cuda")
+            for t in range(1, T + 1):
+                phi, psi, _ = smsq.viterbi_step(model, "f32", t, phi, x_prev=x0 if t == 1 else parts[t - 2],
+                                                z_t=z[t - 1], z_mask=zm[t - 1], x=parts[t - 1],
+                                                want_flags=False, ws=ws)
+                psi_all[t - 1] = psi
+            return smsq.backtrack("f32", psi_all, phi, ws=ws)
+
+        recursion()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, J, _ = recursion()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # kernel alone: one mid-sequence step launched back to back
+        tm = T // 2
+        ph = torch.zeros(n, dtype=torch.float32, device="cuda")
+        reps = 50
+        for _ in range(3):
+            smsq.viterbi_step(model, "f32", tm, ph, x_prev=parts[tm - 2], z_t=z[tm - 1], z_mask=zm[tm - 1],
+                              x=parts[tm - 1], want_flags=False, ws=ws)
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(reps):
+            smsq.viterbi_step(model, "f32", tm, ph, x_prev=parts[tm - 2], z_t=z[tm - 1], z_mask=zm[tm - 1],
+                              x=parts[tm - 1], want_flags=False, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        edges = n * n
+        rows.append({"N": n, "kernel_us_per_step": us, "edges_per_s": edges / (us * 1e-6),
+                     "counted_tflops": edges * (2 * d + 4) / (us * 1e-6) / 1e12,
+                     "frac_fp32_peak": edges * (2 * d + 4) / (us * 1e-6) / PEAK_FP32,
+                     "wall_ms_per_step": wall / T * 1e3, "J": float(J.item()),
+                     "paper_ms_per_step": PAPER_SCENARIO_C_MS["pf_map_seq"][n]})
+    assert smsq.device_status(ws) == smsq.OK
+    stein = []
+    for n in (20, 30, 40):
+        w2 = S.make_workload("range2d", B=1, seed=6000, n=n, n_iter=100, step=0.005)
+        m2 = smsq.Model(w2.model)
+        x0s = torch.tensor(w2.x0[0], dtype=torch.float32, device="cuda")
+        zs = torch.tensor(w2.z[0], dtype=torch.float32, device="cuda")
+        ms = torch.tensor(w2.mask[0], dtype=torch.uint8, device="cuda")
+        so = smsq.opts_from(w2.opts)
+        smsq.run_sequence(m2, "f32", x0s, zs, ms, n, so, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smsq.run_sequence(m2, "f32", x0s, zs, ms, n, so, 3)
+        torch.cuda.synchronize()
+        stein.append({"N": n, "ms_per_step": (time.perf_counter() - t0) / w2.T * 1e3,
+                      "paper_ms_per_step": PAPER_SCENARIO_C_MS["stein_map_seq"][n]})
+    return {"model": "range2d (stand-in for Sec. V-C), FP32, T=200; PF particle sets from a bootstrap PF "
+                     "with stratified resampling", "kernel": "k_viterbi_particle_wide", "rows": rows,
+            "stein_map_seq_one_sequence": stein}
 
 
 def _events(torch):
@@ -581,6 +671,8 @@ def main():
         out["scenario_b"] = scenario_b_runs(torch, smsq, args.scenario_b_mc)
     if args.scenario_d_mc > 0:
         out["scenario_d"] = scenario_d_runs(torch, smsq, args.scenario_d_mc)
+    if args.pf_map_seq:
+        out["pf_map_seq"] = pf_map_seq(torch, smsq)
     if args.batched_seqs > 0:
         out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs)
     if args.cpu_baseline:

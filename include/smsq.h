@@ -179,7 +179,12 @@ smsq_status_t smsq_svgd_step(smsq_model_t model, smsq_dtype_t dtype, int t,
  * Lattice mode (lattice != NULL): A is the given [n, n_prev] matrix and
  * loglik the given [n] vector; model, t, x_prev, z_t, z_mask and x are
  * ignored (may be NULL).  Particle mode (lattice == NULL): A and loglik are
- * computed from x_prev [n_prev, d], x [n, d] and z_t.
+ * computed from x_prev [n_prev, d], x [n, d] and z_t over the whole chip
+ * (rows i spread over workgroups, each holding the n_prev transition means
+ * in LDS); any n, and n_prev up to what fits one compute unit's LDS,
+ * n_prev * (dpad(d) + 1) element slots with dpad(d) = 1, 2, 4, 8 or 16
+ * (e.g. 13,000 previous particles in FP32 at d = 2), else
+ * SMSQ_ERR_UNSUPPORTED.
  *  phi_prev    [n_prev] accumulated scores of step t-1 (zeros for t = 1)
  *  phi, psi    [n] outputs; tie_flags [n] output or NULL: 1 where the best
  *              c_ij over j != psi(i) is >= best - tie_tol * max(1, |best|)

@@ -265,6 +265,62 @@ smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<dou
     return SMSQ_ERR_INVALID;
 }
 
+// LDS of the chip-wide particle-mode forward recursion: the scaled means
+// table [n_prev][dpad(d)] and phi_{t-1} [n_prev]
+template <typename T> long wide_lds_bytes(int n_prev, int d)
+{
+    return align16((long)n_prev * dpad(d) * sizeof(T)) + (long)n_prev * sizeof(T);
+}
+
+constexpr int kWideThreads = 256;   // 4 waves; a wave takes one row i at a time
+constexpr int kWideMaxBlocks = 512; // two workgroups per compute unit; each builds the means table once
+
+template <typename T, int KIND, int D>
+smsq_status_t launch_viterbi_wide_kd(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                     const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                     void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                     hipStream_t s)
+{
+    auto fn = &k_viterbi_particle_wide<T, KIND, D>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] { attr_err = allow_big_lds(fn); });
+    if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
+    const int rows_per_block = kWideThreads / kWave;
+    const int grid = std::min((n + rows_per_block - 1) / rows_per_block, kWideMaxBlocks);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWideThreads), (size_t)wide_lds_bytes<T>(n_prev, D), s,
+                       make_dev_model<T>(d), t, n, n_prev, (const T *)x_prev, (const T *)phi_prev, (const T *)z,
+                       mask, (const T *)x, (T *)phi, psi, flags, (T)tie_tol, status);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+template <typename T>
+smsq_status_t launch_viterbi_wide(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                  const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                  void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                  hipStream_t s)
+{
+#define SMSQ_WIDE(K, DD) \
+    launch_viterbi_wide_kd<T, K, DD>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi, flags, tie_tol, status, s)
+    switch (d.kind) {
+    case SMSQ_MODEL_GROWTH1D: return SMSQ_WIDE(GROWTH1D, 1);
+    case SMSQ_MODEL_RANGE2D: return SMSQ_WIDE(RANGE2D, 2);
+    case SMSQ_MODEL_CV4D: return SMSQ_WIDE(CV4D, 4);
+    case SMSQ_MODEL_ARM7: return SMSQ_WIDE(ARM7, 7);
+    case SMSQ_MODEL_SE2: return SMSQ_WIDE(SE2, 3);
+    case SMSQ_MODEL_ARM14: return SMSQ_WIDE(ARM14, 14);
+    case SMSQ_MODEL_LINGAUSS:
+        switch (d.d) {
+        case 1: return SMSQ_WIDE(LINGAUSS, 1);
+        case 2: return SMSQ_WIDE(LINGAUSS, 2);
+        case 3: return SMSQ_WIDE(LINGAUSS, 3);
+        case 4: return SMSQ_WIDE(LINGAUSS, 4);
+        }
+    }
+#undef SMSQ_WIDE
+    return SMSQ_ERR_INVALID;
+}
+
 bool opts_ok(const smsq_svgd_opts_t *o)
 {
     return o && o->n_iter >= 0 && std::isfinite(o->step) && finite_pos(o->bw_scale) &&
@@ -651,11 +707,16 @@ smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t, i
         return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
     }
     if (!model || t < 1 || !x_prev || !z_t || !x) return SMSQ_ERR_INVALID;
-    if (!step_shape_ok(dtype, n, n_prev, model->desc.d)) return SMSQ_ERR_UNSUPPORTED;
-    // particle mode: the step kernel with no SVGD iteration and the given particles
-    return step_dispatch(dtype, model->desc, 1, t, n_prev, x_prev, 0, nullptr, 0, phi_prev, 0, z_t, 0, z_mask,
-                         0, n, const_cast<void *>(x), 0, 1, 0, 0, nullptr, false, true, phi, 0, psi, 0,
-                         tie_flags, 0, tie_tol, nullptr, 0, ws, stream);
+    // particle mode: the chip-wide kernel, whose LDS holds the means table
+    const smsq_model_desc_t &d = model->desc;
+    if (dtype == SMSQ_F64) {
+        if (wide_lds_bytes<double>(n_prev, d.d) > kLdsLimit) return SMSQ_ERR_UNSUPPORTED;
+        return launch_viterbi_wide<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,
+                                           tie_tol, status_ptr(ws), stream);
+    }
+    if (wide_lds_bytes<float>(n_prev, d.d) > kLdsLimit) return SMSQ_ERR_UNSUPPORTED;
+    return launch_viterbi_wide<float>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,
+                                      tie_tol, status_ptr(ws), stream);
 }
 
 smsq_status_t smsq_backtrack(smsq_dtype_t dtype, int batch, int T, int n, int d, const int32_t *psi,

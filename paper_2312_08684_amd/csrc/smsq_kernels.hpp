@@ -539,6 +539,93 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
 }
 
 // ---------------------------------------------------------------------------
+// Particle-mode forward recursion over the whole chip: c_ij = log N(x_t^i;
+// f_t(x_{t-1}^j), diag q) + phi_{t-1}(j), psi_i = lowest argmax_j c_ij,
+// phi_i = log p(z_t | x_t^i) + c_{i psi_i} (eq. forward_recursion).  Each
+// workgroup evaluates the transition means of all previous particles once
+// into LDS (centred on f_t(x_{t-1}^0) and scaled by sqrt(log2 e / (2 q)), as
+// in the step kernels), then its waves take rows i in turn: the lanes walk
+// j in ascending order, the wave merges (lowest index on equal scores) and
+// lane 0 adds the observation term.  Bound by the vector ALU: (2d + 4) flops
+// and one compare per edge; the LDS table is read, never HBM, inside the
+// edge loop.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, int D>
+__global__ __launch_bounds__(256) void k_viterbi_particle_wide(DevModel<T> m, int t, int n, int n_prev,
+                                                               const T *__restrict__ x_prev,
+                                                               const T *__restrict__ phi_prev,
+                                                               const T *__restrict__ z, const uint8_t *mask,
+                                                               const T *__restrict__ x, T *phi, int32_t *psi,
+                                                               uint8_t *flags, T tie_tol, uint32_t *status)
+{
+    using F = Family<T, KIND, D>;
+    using R = RealOps<T>;
+    constexpr int DP = dpad(D);
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *sm = (T *)smem;                                       // [n_prev][DP] scaled centred means
+    T *sp = (T *)(smem + align16((long)n_prev * DP * sizeof(T)));   // [n_prev] phi_{t-1}
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & (kWave - 1);
+
+    T cen[D], rs[D];
+    {
+        T xp[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) xp[c] = x_prev[c];
+        F::mean(m, t, xp, cen);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) rs[c] = m.rs[c];
+    for (int j = tid; j < n_prev; j += nt) {
+        T xp[D], mu[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) xp[c] = x_prev[(long)j * D + c];
+        F::mean(m, t, xp, mu);
+#pragma unroll
+        for (int c = 0; c < DP; ++c) sm[(long)j * DP + c] = c < D ? (mu[c] - cen[c]) * rs[c] : (T)0;
+        sp[j] = phi_prev[j];
+    }
+    __syncthreads();
+
+    bool nan_seen = false;
+    const int waves = gridDim.x * (nt / kWave);
+    for (int i = blockIdx.x * (nt / kWave) + wave_id(); i < n; i += waves) {
+        T xi[D], xs[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            xi[c] = x[(long)i * D + c];
+            xs[c] = (xi[c] - cen[c]) * rs[c];
+        }
+        ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};
+        for (int j = lane; j < n_prev; j += kWave) {
+            T mj[DP];
+            lds_load<T, DP>(sm + (long)j * DP, mj);
+            T q2 = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) { const T r = xs[c] - mj[c]; q2 += r * r; }
+            const T cij = (m.log_z - (T)kLn2 * q2) + sp[j];
+            nan_seen |= (cij != cij);
+            if (j == lane) { ab.best = cij; ab.arg = j; }
+            else argbest_push(ab, cij, j);
+        }
+        ab = wave_argbest(ab);
+        if (lane == 0) {
+            const T ell = F::loglik(m, z, mask, xi);
+            const T ph = ab.best + ell;
+            phi[i] = ph;
+            psi[i] = ab.arg;
+            if (flags) {
+                const T mag = ab.best < 0 ? -ab.best : ab.best;
+                const T sc = mag > (T)1 ? mag : (T)1;
+                flags[i] = (n_prev > 1 && ab.second >= ab.best - tie_tol * sc) ? 1 : 0;
+            }
+            nan_seen |= (ell != ell) || (ph != ph);
+        }
+    }
+    if (__any(nan_seen) && lane == 0) atomicOr(status, STATUS_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
 // Backtracking: one workgroup (one wave) per sequence.
 // ---------------------------------------------------------------------------
 template <typename T>

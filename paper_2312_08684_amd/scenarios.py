@@ -359,6 +359,37 @@ def simulate(model: ModelDesc, T: int, B: int, seed: int, *,
     return truth[:, 0].copy(), truth, z, mask
 
 
+def bootstrap_pf_particles(model: ModelDesc, x0: np.ndarray, z: np.ndarray, mask: Optional[np.ndarray],
+                           n: int, seed: int) -> np.ndarray:
+    """Particle sets of a bootstrap particle filter on the range-only model,
+    the grid that a PF-MAP-Seq forward recursion runs on (Sec. V baselines:
+    stratified resampling at every step).  The filter is input generation
+    for that workload, not part of the estimator: it propagates the resampled
+    particles through the random walk, weights them by the range likelihood
+    and resamples.  Returns [T, n, 2], the propagated particles of each step
+    (before resampling, so they are distinct)."""
+    assert model.kind == RANGE2D
+    rng = np.random.default_rng(seed)
+    p = model.params
+    nb = int(p[1])
+    bc = p[2:2 + 2 * nb].reshape(nb, 2)
+    sq = np.sqrt(model.q_var[:2])
+    T = z.shape[0]
+    parts = np.zeros((T, n, 2))
+    anc = np.broadcast_to(np.asarray(x0, dtype=np.float64), (n, 2))
+    for t in range(T):
+        x = anc + sq * rng.normal(size=(n, 2))
+        parts[t] = x
+        rr = np.sqrt(((x[:, None, :] - bc[None]) ** 2).sum(-1))
+        on = np.ones(nb, dtype=bool) if mask is None else mask[t].astype(bool)
+        lw = -0.5 * (((z[t, :nb][None, :] - rr) ** 2) / p[0])[:, on].sum(1)
+        w = np.exp(lw - lw.max())
+        cdf = np.cumsum(w / w.sum())
+        u = (np.arange(n) + rng.uniform(size=n)) / n
+        anc = x[np.minimum(np.searchsorted(cdf, u), n - 1)]
+    return parts
+
+
 # ---------------------------------------------------------------------------
 # The five workload shapes
 # ---------------------------------------------------------------------------

@@ -187,6 +187,86 @@ def test_backtrack_bit_exact(dt):
         assert np.array_equal(xmap[b, 1:], want.astype(np.float32) if dt == "f32" else want)
 
 
+@pytest.mark.parametrize("n,n_prev", [(4000, 4000), (1, 3000), (2500, 1), (777, 1025)])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_viterbi_particle_mode_large(n, n_prev, dt):
+    """Particle mode at PF-MAP-Seq sizes (up to 4000 x 4000 edges of the
+    range-only model), with one row, one previous particle and ragged tails."""
+    announce("viterbi particle large", n, n_prev, dt)
+    wl, desc, xp, x = _particle_case("range2d", n, n_prev, 4)
+    z = wl.z[0, 1]
+    rng = np.random.default_rng(6)
+    phi_prev = rng.normal(size=n_prev) * 3
+    td = tdt(dt)
+    if dt == "f32":
+        xp, x, phi_prev, z = (v.astype(np.float32).astype(np.float64) for v in (xp, x, phi_prev, z))
+    tol = 1e-5 if dt == "f32" else 1e-9
+    phi_o, psi_o, fl_o, st = O.viterbi_particle(desc, 2, xp, phi_prev, z, None, x, tie_tol=tol)
+    assert st == O.OK
+    ws = smsq.workspace()
+    phi, psi, fl = smsq.viterbi_step(smsq.Model(desc), dt, 2, dev(phi_prev, td), x_prev=dev(xp, td),
+                                     z_t=dev(z, td), x=dev(x, td), tie_tol=tol, ws=ws)
+    assert smsq.device_status(ws) == smsq.OK
+    psi, phi, fl = host(psi), host(phi).astype(np.float64), host(fl)
+    sure = fl_o == 0
+    assert np.array_equal(psi[sure], psi_o[sure])
+    if n_prev == 1:
+        assert np.all(psi == 0) and np.all(fl == 0)
+    err = np.abs(phi - phi_o) / np.maximum(1, np.abs(phi_o))
+    print("phi rel err %.3e, sure rows %.3f" % (err.max(), sure.mean()))
+    assert err.max() <= (1e-5 if dt == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_pf_map_seq_forward_recursion(dt):
+    """The PF-MAP-Seq workload: forward recursion and backtrack over the
+    particle sets of a bootstrap particle filter (1500 particles per step,
+    12 steps of the range-only model), step by step against the oracle fed
+    the same scores, then free-running to the MAP log-posterior."""
+    announce("pf-map-seq", dt)
+    T, n = 12, 1500
+    wl = S.make_workload("range2d", B=1, seed=1008, T=T)
+    desc = wl.model
+    parts = S.bootstrap_pf_particles(desc, wl.x0[0], wl.z[0], None, n, seed=9)
+    td = tdt(dt)
+    rnd = (lambda v: v.astype(np.float32).astype(np.float64)) if dt == "f32" else (lambda v: v)
+    parts, x0, z = rnd(parts), rnd(wl.x0[0][None, :]), rnd(wl.z[0])
+    tol = 1e-5 if dt == "f32" else 1e-9
+    model = smsq.Model(desc)
+    ws = smsq.workspace()
+    phi_o = np.zeros(1)
+    phi_g = torch.zeros(1, dtype=td, device=DEV)
+    psi_all = torch.zeros((T, n), dtype=torch.int32, device=DEV)
+    psi_o_all = np.zeros((T, n), dtype=np.int32)
+    for t in range(1, T + 1):
+        xp = x0 if t == 1 else parts[t - 2]
+        ph_o, ps_o, fl_o, st = O.viterbi_particle(desc, t, xp, phi_o, z[t - 1], None, parts[t - 1], tie_tol=tol)
+        assert st == O.OK
+        # same scores on both sides for this step's comparison
+        ph_t, ps_t, _ = smsq.viterbi_step(model, dt, t, dev(rnd(phi_o), td), x_prev=dev(xp, td),
+                                          z_t=dev(z[t - 1], td), x=dev(parts[t - 1], td), tie_tol=tol, ws=ws)
+        sure = fl_o == 0
+        assert np.array_equal(host(ps_t)[sure], ps_o[sure]), t
+        err = np.abs(host(ph_t).astype(np.float64) - ph_o) / np.maximum(1, np.abs(ph_o))
+        assert err.max() <= (1e-5 if dt == "f32" else 1e-12), (t, err.max())
+        # free-running chain on the GPU's own scores
+        phi_g, psi_g, _ = smsq.viterbi_step(model, dt, t, phi_g, x_prev=dev(xp, td), z_t=dev(z[t - 1], td),
+                                            x=dev(parts[t - 1], td), tie_tol=tol, ws=ws)
+        psi_all[t - 1] = psi_g
+        psi_o_all[t - 1] = ps_o
+        phi_o = ph_o
+    assert smsq.device_status(ws) == smsq.OK
+    idx, J, _ = smsq.backtrack(dt, psi_all, phi_g, ws=ws)
+    idx_o, J_o, st = O.backtrack(psi_o_all, phi_o)
+    J = float(host(J).reshape(-1)[0])
+    dJ = abs(J - J_o) / max(abs(J_o), T)
+    print("J gpu %.8f oracle %.8f rel %.3e; path agreement %.3f" % (J, J_o, dJ,
+          np.mean(host(idx).reshape(-1) == idx_o)))
+    assert dJ <= (1e-5 if dt == "f32" else 1e-12)
+    if dt == "f64":
+        assert np.array_equal(host(idx).reshape(-1), idx_o)
+
+
 # ---------------------------------------------------------------------------
 # SVGD step, teacher-forced
 # ---------------------------------------------------------------------------
@@ -563,6 +643,15 @@ def test_argument_errors():
     arm.params[24] = float("inf")
     with pytest.raises(smsq.SmsqError):
         smsq.Model(arm)
+    # particle-mode forward recursion: the n_prev means table must fit LDS
+    # (FP64 at d = 14: 17 slots of 8 bytes per previous particle)
+    arm = smsq.Model(S._model_for("scenario_d", 0))
+    with pytest.raises(smsq.SmsqError) as e:
+        smsq.viterbi_step(arm, "f64", 2, torch.zeros(1300, dtype=torch.float64, device=DEV),
+                          x_prev=torch.zeros((1300, 14), dtype=torch.float64, device=DEV),
+                          z_t=torch.zeros(3, dtype=torch.float64, device=DEV),
+                          x=torch.zeros((8, 14), dtype=torch.float64, device=DEV))
+    assert e.value.status == smsq.ERR_UNSUPPORTED
     with pytest.raises(smsq.SmsqError) as e:   # no such kernel
         smsq.svgd_step(model, "f32", 1, torch.zeros((1, 2), device=DEV), None, z, None, x,
                        smsq.opts(2, 0.1, kernel=3))

@@ -178,14 +178,22 @@ smsq_status_t launch_step_kd(const StepArgs<T> &a, int batch, hipStream_t s)
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
 
-// The FP32 matrix-core kernel takes sequences of up to 1024 particles whose
-// state fits LDS; SMSQ_STEP_KERNEL=valu selects the vector-ALU kernel instead.
+// The FP32 matrix-core kernel takes sequences of 32 to 1024 particles whose
+// state fits LDS; below 32 particles the one-wave vector-ALU kernel is
+// faster (its median gathers all pairs at once).  SMSQ_STEP_KERNEL=valu
+// selects the vector-ALU kernel for every size, SMSQ_STEP_KERNEL=mfma the
+// matrix-core kernel for every size that fits it (batched plans run it at
+// any size).
+constexpr int kMfmaMinParticles = 32;
+
 bool use_mfma(int n, int n_prev)
 {
     const char *e = std::getenv("SMSQ_STEP_KERNEL");
     if (e && std::strcmp(e, "valu") == 0) return false;
     const MfmaLds L(n, n_prev);
-    return L.npad <= kMaxParticles && L.total <= kLdsLimit;
+    const bool fits = L.npad <= kMaxParticles && L.total <= kLdsLimit;
+    if (e && std::strcmp(e, "mfma") == 0) return fits;
+    return fits && n >= kMfmaMinParticles;
 }
 
 template <int KIND, int D>
@@ -273,7 +281,7 @@ template <typename T> long wide_lds_bytes(int n_prev, int d)
 }
 
 constexpr int kWideThreads = 256;   // 4 waves; a wave takes one row i at a time
-constexpr int kWideMaxBlocks = 512; // two workgroups per compute unit; each builds the means table once
+constexpr int kWideMaxBlocks = 2048; // up to eight workgroups per compute unit; each builds the means table once
 
 template <typename T, int KIND, int D>
 smsq_status_t launch_viterbi_wide_kd(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,

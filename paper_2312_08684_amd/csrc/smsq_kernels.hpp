@@ -168,6 +168,139 @@ __device__ T block_median_sqdist(const T *sx, int n, uint32_t *hist, uint32_t *r
     return KO::val(prefix);
 }
 
+// (1b) the same order statistic by one pass over a window: the pairs below
+// lo are counted, those in [lo, hi] are gathered into buf (wave-aggregated
+// appends, at most cap of them); when the rank falls inside the window the
+// median is the matching order statistic of the gathered values.  Returns
+// false, with the window's counts, when the rank lies outside it or it
+// overflowed; the caller then takes the radix selection.  ALL gathers every
+// pair (i, k) at slot k (k - 1) / 2 + i, with no counting.
+
+// The r-th smallest (0-based) of the first cnt keys of buf, by one wave:
+// the keys go to registers, S per lane, and the answer is built bit by bit
+// below the common prefix of the smallest and largest key; bit b is set
+// when at most r keys lie below the prefix with that bit set (ballot counts).
+template <typename T, int S>
+__device__ typename KeyOf<T>::K select_rank_wave(const T *buf, uint32_t cnt, uint32_t r, int lane)
+{
+    using KO = KeyOf<T>;
+    using K = typename KO::K;
+    constexpr int kBits = 8 * (int)sizeof(K);
+    K key[S];
+    K kmin = ~(K)0, kmax = 0;
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+        const uint32_t q = (uint32_t)(lane + sl * kWave);
+        key[sl] = ~(K)0;
+        if (q < cnt) {
+            key[sl] = KO::key(buf[q]);
+            kmin = key[sl] < kmin ? key[sl] : kmin;
+            kmax = key[sl] > kmax ? key[sl] : kmax;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const K a = __shfl_xor(kmin, off, kWave), b = __shfl_xor(kmax, off, kWave);
+        kmin = a < kmin ? a : kmin;
+        kmax = b > kmax ? b : kmax;
+    }
+    const K diff = kmin ^ kmax;
+    const int top = diff ? kBits - 1 - (sizeof(K) == 8 ? __builtin_clzll((unsigned long long)diff)
+                                                       : __builtin_clz((uint32_t)diff)) : -1;
+    K prefix = top >= kBits - 1 ? (K)0 : (kmin & ~((((K)1) << (top + 1)) - 1));
+    for (int b = top; b >= 0; --b) {
+        const K t = prefix | ((K)1 << b);
+        uint32_t c = 0;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) c += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(key[sl] < t));
+        if (c <= r) prefix = t;
+    }
+    return prefix;
+}
+
+template <typename T, int D, int DP, bool ALL>
+__device__ bool window_median_sqdist(const T *sx, int n, T lo, T hi, T *buf, uint32_t cap, uint32_t *red, T &med,
+                                     uint32_t &cnt_lo, uint32_t &cnt_in)
+{
+    using KO = KeyOf<T>;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & (kWave - 1), wave = wave_id(), nwaves = nt / kWave;
+    const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
+    const uint32_t rank = (M - 1) / 2;
+    if (!ALL) {
+        if (tid == 0) { red[2] = 0; red[3] = 0; }
+        __syncthreads();
+    }
+    uint32_t below = 0;
+    const int nb = (n + kWave - 1) / kWave;
+    const int ntiles = nb * (nb + 1) / 2;
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        int ib = 0, rem = tile;
+        while (rem >= nb - ib) { rem -= nb - ib; ++ib; }
+        const int kb = ib + rem;
+        const int i = ib * kWave + lane;
+        T xi[DP];
+        if (i < n) lds_load<T, DP>(sx + (long)i * DP, xi);
+        const int k0 = kb * kWave;
+        const int k1 = min(k0 + kWave, n);
+        for (int k = k0; k < k1; ++k) {
+            const bool valid = i < k && i < n;
+            T dd = 0;
+            if (valid) {
+                T xk[DP];
+                lds_load<T, DP>(sx + (long)k * DP, xk);
+#pragma unroll
+                for (int a = 0; a < D; ++a) { const T r = xi[a] - xk[a]; dd += r * r; }
+            }
+            if (ALL) {
+                if (valid) buf[(uint32_t)k * (uint32_t)(k - 1) / 2 + (uint32_t)i] = dd;
+                continue;
+            }
+            below += (valid && dd < lo) ? 1u : 0u;
+            const bool in = valid && dd >= lo && dd <= hi;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+            if (m) {
+                const int leader = (int)__builtin_ctzll(m);
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(&red[2], (uint32_t)__builtin_popcountll(m));
+                base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+                const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (in && pos < cap) buf[pos] = dd;
+            }
+        }
+    }
+    if (ALL) {
+        cnt_lo = 0;
+        cnt_in = M;
+        __syncthreads();
+    } else {
+        below = wave_sum(below);
+        if (lane == 0) atomicAdd(&red[3], below);
+        __syncthreads();
+        cnt_in = red[2];
+        cnt_lo = red[3];
+        __syncthreads();
+        if (cnt_in > cap || rank < cnt_lo || rank >= cnt_lo + cnt_in) return false;
+    }
+    if (wave == 0) {
+        const uint32_t r = rank - cnt_lo;
+        const uint32_t used = (cnt_in + kWave - 1) / kWave;
+        typename KO::K v;
+        if (used <= 1) v = select_rank_wave<T, 1>(buf, cnt_in, r, lane);
+        else if (used <= 2) v = select_rank_wave<T, 2>(buf, cnt_in, r, lane);
+        else if (used <= 4) v = select_rank_wave<T, 4>(buf, cnt_in, r, lane);
+        else if (used <= 8) v = select_rank_wave<T, 8>(buf, cnt_in, r, lane);
+        else if (used <= 16) v = select_rank_wave<T, 16>(buf, cnt_in, r, lane);
+        else v = select_rank_wave<T, kBins * (int)sizeof(uint32_t) / (int)sizeof(T) / kWave>(buf, cnt_in, r, lane);
+        if (lane == 0) *(T *)(red + 4) = KO::val(v);
+    }
+    __syncthreads();
+    med = *(const T *)(red + 4);
+    __syncthreads();
+    return true;
+}
+
 template <typename T> __device__ __forceinline__ T bandwidth_from_median(T med, int n, T bw_scale)
 {
     T h = (n > 1) ? bw_scale * med / RealOps<T>::log_((T)n) : (T)0;
@@ -278,10 +411,34 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
 
     const T inv_n = (T)1 / (T)n;
     T h = (T)1;
+    // median selection: all pairs gathered when they fit the window buffer,
+    // else a window around the previous iteration's median whose relative
+    // half-width adapts to keep the gathered count modest; radix selection
+    // when the window misses or overflows
+    const uint32_t n_pairs = (uint32_t)((long)n * (n - 1) / 2);
+    const uint32_t cap = min((uint32_t)(kBins * sizeof(uint32_t) / sizeof(T)), (uint32_t)(4 * nt));
+    T med_prev = (T)0, wrel = (T)0.02;
+    bool have_prev = false;
     for (int it = 0; a.do_svgd && it < a.n_iter; ++it) {
         // (1) bandwidth
         if (a.bw_mode == 0 || it == 0) {
-            const T med = block_median_sqdist<T, D, DP>(sx, n, hist, red);
+            T med = (T)0;
+            uint32_t clo = 0, cin = 0;
+            bool ok = false;
+            if (n_pairs >= 1 && n_pairs <= cap) {
+                ok = window_median_sqdist<T, D, DP, true>(sx, n, (T)0, R::inf(), (T *)hist, cap, red, med, clo, cin);
+            } else if (n_pairs > cap && have_prev) {
+                ok = window_median_sqdist<T, D, DP, false>(sx, n, med_prev * ((T)1 - wrel), med_prev * ((T)1 + wrel),
+                                                    (T *)hist, cap, red, med, clo, cin);
+                const uint32_t rank = (n_pairs - 1) / 2;
+                if (ok) wrel = cin < cap / 8 ? wrel * (T)1.5 : (cin > cap / 2 ? wrel * (T)0.7 : wrel);
+                else if (cin > cap) wrel *= (T)0.5;
+                else if (rank < clo || rank >= clo + cin) wrel *= (T)2;
+                if (wrel > (T)0.5) wrel = (T)0.5;
+            }
+            if (!ok) med = block_median_sqdist<T, D, DP>(sx, n, hist, red);
+            med_prev = med;
+            have_prev = med > (T)0 && R::finite(med);
             h = bandwidth_from_median(med, n, a.bw_scale);
         }
         if (a.h_out && tid == 0) a.h_out[(long)b * a.h_stride + it] = h;

@@ -371,6 +371,32 @@ def test_svgd_step_variants(variant):
     _compare_svgd(desc, "f32", xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode)
 
 
+@pytest.mark.parametrize("variant", ["ties_16x16", "ties_4x64", "ties_2x10"])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_svgd_step_ties_vector_alu(variant, dt, monkeypatch):
+    """The vector-ALU kernel's median under exact ties: copies of a few
+    distinct particles put hundreds or thousands of equal distances at the
+    median, so the window gathers them all or overflows (radix fallback);
+    ties_2x10 (20 particles) takes the all-pairs path with 90 zero
+    distances below the median's rank."""
+    announce("svgd ties valu", variant, dt)
+    monkeypatch.setenv("SMSQ_STEP_KERNEL", "valu")
+    groups, copies = (int(v) for v in variant[5:].split("x"))
+    wl, desc, xp, x, z, mask = _svgd_case("range2d", groups * copies, 50, 5, dt)
+    x = np.repeat(x[:groups], copies, axis=0)
+    _compare_svgd(desc, dt, xp, None, z, mask, x, 6, 0.005)
+
+
+@pytest.mark.parametrize("n,n_prev", [(1, 50), (2, 50), (20, 20), (31, 7)])
+def test_svgd_step_small_n_matrix_core(n, n_prev, monkeypatch):
+    """Below 32 particles single steps take the vector-ALU kernel; batched
+    plans still run the matrix-core kernel there, forced here."""
+    announce("svgd step small n mfma", n, n_prev)
+    monkeypatch.setenv("SMSQ_STEP_KERNEL", "mfma")
+    wl, desc, xp, x, z, mask = _svgd_case("range2d", n, n_prev, 23, "f32")
+    _compare_svgd(desc, "f32", xp, None, z, mask, x, 40, 0.005)
+
+
 KERNEL_CASES = [
     ("growth1d", 32, 32, 100, 0.05, "f64"),
     ("growth1d", 10, 10, 100, 0.05, "f64"),

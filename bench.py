@@ -439,7 +439,7 @@ def sweep(torch, smsq):
             del As
             rows.append({"mode": "lattice", "dtype": dt, "N": n, "us_per_launch": sec * 1e6,
                          "edges_per_s": n * n / sec, "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM})
-    for name, n in (("range2d", 256), ("cv4d", 512), ("arm7", 1024)):
+    for name, n in (("range2d", 256), ("cv4d", 512), ("arm7", 1024), ("range2d", 4096)):
         wl = S.make_workload(name, B=1, seed=0, T=2, n=n)
         model = smsq.Model(wl.model)
         d = wl.model.d
@@ -460,7 +460,7 @@ def sweep(torch, smsq):
         e1.record()
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3 / reps
-        rows.append({"mode": "particle (one sequence, one workgroup)", "model": name, "dtype": "f32", "N": n,
+        rows.append({"mode": "particle (one sequence, rows over the chip)", "model": name, "dtype": "f32", "N": n,
                      "us_per_launch": sec * 1e6, "edges_per_s": n * n / sec})
     out["viterbi_vs_n"] = rows
     # (3) Algorithm 2 end to end per workload: one sequence and a batch

@@ -164,7 +164,14 @@ smsq_status_t smsq_workspace_size(smsq_model_t model, smsq_dtype_t dtype, int ba
  *              the previous iteration
  *  h_out       [n_iter] bandwidth used by each iteration, or NULL
  * Requires n >= 1, n_prev >= 1; SMSQ_ERR_UNSUPPORTED when the particle sets
- * do not fit one compute unit's LDS. */
+ * do not fit one compute unit's LDS.
+ * Kernel choice (also for smsq_batch_step, smsq_run_batch and
+ * smsq_run_sequence): FP32 with the RBF kernel, d <= 7 and 32..1024
+ * particles runs on the matrix cores; FP64, the IMQ and Matern kernels,
+ * d > 7, fewer than 32 particles or more than 1024 run on the vector ALU.
+ * The environment variable SMSQ_STEP_KERNEL=valu forces the vector-ALU
+ * kernel, SMSQ_STEP_KERNEL=mfma the matrix-core kernel wherever it fits
+ * (tests use both); results agree to rounding. */
 smsq_status_t smsq_svgd_step(smsq_model_t model, smsq_dtype_t dtype, int t,
                              int n_prev, const void *x_prev, const void *log_w_prev,
                              const void *z_t, const uint8_t *z_mask,

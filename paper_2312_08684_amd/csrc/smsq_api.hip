@@ -280,8 +280,11 @@ template <typename T> long wide_lds_bytes(int n_prev, int d)
     return align16((long)n_prev * dpad(d) * sizeof(T)) + (long)n_prev * sizeof(T);
 }
 
-constexpr int kWideThreads = 256;   // 4 waves; a wave takes one row i at a time
-constexpr int kWideMaxBlocks = 2048; // up to eight workgroups per compute unit; each builds the means table once
+// 16 waves per workgroup for states of up to 8 dimensions (one means table
+// for all of them), 4 for larger states (register budget); a wave takes one
+// row i at a time
+constexpr int wide_threads(int d) { return d <= 8 ? 1024 : 256; }
+constexpr int kWideMaxBlocks = 2048;
 
 template <typename T, int KIND, int D>
 smsq_status_t launch_viterbi_wide_kd(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
@@ -289,14 +292,15 @@ smsq_status_t launch_viterbi_wide_kd(const smsq_model_desc_t &d, int t, int n, i
                                      void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
                                      hipStream_t s)
 {
-    auto fn = &k_viterbi_particle_wide<T, KIND, D>;
+    constexpr int NT = wide_threads(D);
+    auto fn = &k_viterbi_particle_wide<T, KIND, D, NT>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] { attr_err = allow_big_lds(fn); });
     if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
-    const int rows_per_block = kWideThreads / kWave;
+    const int rows_per_block = NT / kWave;
     const int grid = std::min((n + rows_per_block - 1) / rows_per_block, kWideMaxBlocks);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWideThreads), (size_t)wide_lds_bytes<T>(n_prev, D), s,
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), (size_t)wide_lds_bytes<T>(n_prev, D), s,
                        make_dev_model<T>(d), t, n, n_prev, (const T *)x_prev, (const T *)phi_prev, (const T *)z,
                        mask, (const T *)x, (T *)phi, psi, flags, (T)tie_tol, status);
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;

@@ -705,10 +705,11 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
 // j in ascending order, the wave merges (lowest index on equal scores) and
 // lane 0 adds the observation term.  Bound by the vector ALU: (2d + 4) flops
 // and one compare per edge; the LDS table is read, never HBM, inside the
-// edge loop.
+// edge loop.  NT threads per workgroup: 1024 for small states, so that one
+// table serves sixteen waves.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND, int D>
-__global__ __launch_bounds__(256) void k_viterbi_particle_wide(DevModel<T> m, int t, int n, int n_prev,
+template <typename T, int KIND, int D, int NT>
+__global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int t, int n, int n_prev,
                                                                const T *__restrict__ x_prev,
                                                                const T *__restrict__ phi_prev,
                                                                const T *__restrict__ z, const uint8_t *mask,

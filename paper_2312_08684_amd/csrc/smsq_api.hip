@@ -13,6 +13,7 @@
 
 #include "smsq.h"
 #include "smsq_kernels.hpp"
+#include "smsq_wave.hpp"
 #include "smsq_mfma.hpp"
 #include "smsq_batch.hpp"
 #include "smsq_init.hpp"
@@ -179,11 +180,10 @@ smsq_status_t launch_step_kd(const StepArgs<T> &a, int batch, hipStream_t s)
 }
 
 // The FP32 matrix-core kernel takes sequences of 32 to 1024 particles whose
-// state fits LDS; below 32 particles the one-wave vector-ALU kernel is
-// faster (its median gathers all pairs at once).  SMSQ_STEP_KERNEL=valu
-// selects the vector-ALU kernel for every size, SMSQ_STEP_KERNEL=mfma the
-// matrix-core kernel for every size that fits it (batched plans run it at
-// any size).
+// state fits LDS; below 32 particles the one-wave kernel is faster.
+// SMSQ_STEP_KERNEL=valu selects the workgroup vector-ALU kernel for every
+// size, SMSQ_STEP_KERNEL=mfma the matrix-core kernel for every size that
+// fits it (batched plans run it at any size).
 constexpr int kMfmaMinParticles = 32;
 
 bool use_mfma(int n, int n_prev)
@@ -209,12 +209,58 @@ smsq_status_t launch_mfma_kd(const StepArgs<float> &a, int batch, hipStream_t s)
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
 
+template <typename T, int KIND, int D>
+smsq_status_t launch_wave_kd(const StepArgs<T> &a, int batch, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step_wave<T, KIND, D>), dim3(batch), dim3(kWave), 0, s, a);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+// The one-wave kernel fits at most 64 particles and 64 previous ones; by
+// default it takes steps of up to 32 particles in FP64 and below the
+// matrix-core kernel's range in FP32 (measured: 8..12% faster than the
+// workgroup vector-ALU kernel at 10..20 particles, 2.2x for the 14-D model
+// in FP64, even at 32, slower at 64).  SMSQ_STEP_KERNEL=wave selects it
+// wherever it fits, =valu or =mfma the other kernels.
+constexpr int kWaveDefaultMax = 32;
+
+bool use_wave(int n, int n_prev, bool fp32)
+{
+    if (n > kWaveMaxParticles || n_prev > kWaveMaxParticles) return false;
+    const char *e = std::getenv("SMSQ_STEP_KERNEL");
+    if (e && std::strcmp(e, "wave") == 0) return true;
+    if (e && (std::strcmp(e, "valu") == 0 || std::strcmp(e, "mfma") == 0)) return false;
+    return fp32 ? n < kMfmaMinParticles : n <= kWaveDefaultMax;
+}
+
+template <typename T>
+smsq_status_t launch_wave(const smsq_model_desc_t &d, const StepArgs<T> &a, int batch, hipStream_t s)
+{
+    switch (d.kind) {
+    case SMSQ_MODEL_GROWTH1D: return launch_wave_kd<T, GROWTH1D, 1>(a, batch, s);
+    case SMSQ_MODEL_RANGE2D: return launch_wave_kd<T, RANGE2D, 2>(a, batch, s);
+    case SMSQ_MODEL_CV4D: return launch_wave_kd<T, CV4D, 4>(a, batch, s);
+    case SMSQ_MODEL_ARM7: return launch_wave_kd<T, ARM7, 7>(a, batch, s);
+    case SMSQ_MODEL_SE2: return launch_wave_kd<T, SE2, 3>(a, batch, s);
+    case SMSQ_MODEL_ARM14: return launch_wave_kd<T, ARM14, 14>(a, batch, s);
+    case SMSQ_MODEL_LINGAUSS:
+        switch (d.d) {
+        case 1: return launch_wave_kd<T, LINGAUSS, 1>(a, batch, s);
+        case 2: return launch_wave_kd<T, LINGAUSS, 2>(a, batch, s);
+        case 3: return launch_wave_kd<T, LINGAUSS, 3>(a, batch, s);
+        case 4: return launch_wave_kd<T, LINGAUSS, 4>(a, batch, s);
+        }
+    }
+    return SMSQ_ERR_INVALID;
+}
+
 template <typename T>
 smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int batch, hipStream_t s);
 
 template <>
 smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
 {
+    if (use_wave(a.n, a.n_prev, true)) return launch_wave<float>(d, a, batch, s);
     // the matrix-core kernel runs the RBF kernel on states of up to 7
     // dimensions; IMQ, Matern and the 14-D model take the vector-ALU kernel
     if (a.kernel == 0 && d.d <= 7 && use_mfma(a.n, a.n_prev)) {
@@ -255,6 +301,7 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
 template <>
 smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<double> &a, int batch, hipStream_t s)
 {
+    if (use_wave(a.n, a.n_prev, false)) return launch_wave<double>(d, a, batch, s);
     switch (d.kind) {
     case SMSQ_MODEL_GROWTH1D: return launch_step_kd<double, GROWTH1D, 1>(a, batch, s);
     case SMSQ_MODEL_RANGE2D: return launch_step_kd<double, RANGE2D, 2>(a, batch, s);

@@ -371,6 +371,62 @@ def test_svgd_step_variants(variant):
     _compare_svgd(desc, "f32", xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode)
 
 
+WAVE_CASES = [
+    ("growth1d", 1, 1, 30, 0.05, "f64"),
+    ("growth1d", 2, 64, 30, 0.05, "f64"),
+    ("growth1d", 20, 20, 100, 0.05, "f64"),
+    ("growth1d", 64, 64, 50, 0.05, "f64"),
+    ("range2d", 33, 17, 20, 0.005, "f32"),
+    ("cv4d", 40, 64, 20, 0.005, "f32"),
+    ("arm7", 64, 50, 20, 1e-5, "f32"),
+    ("lingauss", 30, 30, 30, 0.01, "f64"),
+    ("scenario_b", 20, 20, 100, 1e-4, "f32"),
+    ("scenario_d", 20, 20, 100, 2e-4, "f64"),
+    ("scenario_d", 30, 11, 40, 2e-4, "f32"),
+]
+
+
+@pytest.mark.parametrize("name,n,n_prev,L,step,dt", WAVE_CASES)
+def test_svgd_step_one_wave_kernel(name, n, n_prev, L, step, dt, monkeypatch):
+    """The one-wave kernel (particles in lane registers, readlane broadcasts)
+    on every family, from one particle to 64, against the oracle."""
+    announce("svgd step wave", name, n, n_prev, L, dt)
+    monkeypatch.setenv("SMSQ_STEP_KERNEL", "wave")
+    wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 24, dt)
+    _compare_svgd(desc, dt, xp, None, z, mask, x, L, step)
+
+
+@pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "imq", "matern32",
+                                     "ties_2x10", "ties_8x8"])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_svgd_step_one_wave_variants(variant, dt, monkeypatch):
+    """Options and exact ties on the one-wave kernel (range-only model)."""
+    announce("svgd wave variant", variant, dt)
+    monkeypatch.setenv("SMSQ_STEP_KERNEL", "wave")
+    n, n_prev = 48, 40
+    if variant.startswith("ties_"):
+        groups, copies = (int(v) for v in variant[5:].split("x"))
+        n = groups * copies
+    wl, desc, xp, x, z, mask = _svgd_case("range2d", n, n_prev, 25, dt)
+    if variant.startswith("ties_"):
+        x = np.repeat(x[:groups], copies, axis=0)
+    log_w, bw_scale, bw_mode, trans_mode, kernel = None, 1.0, 0, 0, 0
+    if variant == "weights":
+        rng = np.random.default_rng(3)
+        log_w = np.log(rng.dirichlet(np.ones(n_prev)))
+        if dt == "f32":
+            log_w = log_w.astype(np.float32).astype(np.float64)
+    if variant == "mean_reading":
+        trans_mode = 1
+    if variant == "per_step_bw":
+        bw_mode = 1
+    if variant == "bw3":
+        bw_scale = 3.0
+    if variant in ("imq", "matern32"):
+        kernel = smsq.KERNELS[variant]
+    _compare_svgd(desc, dt, xp, log_w, z, mask, x, 15, 0.005, bw_scale, bw_mode, trans_mode, kernel)
+
+
 @pytest.mark.parametrize("variant", ["ties_16x16", "ties_4x64", "ties_2x10"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_svgd_step_ties_vector_alu(variant, dt, monkeypatch):

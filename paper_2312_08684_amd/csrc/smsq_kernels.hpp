@@ -176,6 +176,14 @@ __device__ T block_median_sqdist(const T *sx, int n, uint32_t *hist, uint32_t *r
 // overflowed; the caller then takes the radix selection.  ALL gathers every
 // pair (i, k) at slot k (k - 1) / 2 + i, with no counting.
 
+__device__ __forceinline__ uint32_t uniform_key(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t uniform_key(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // The r-th smallest (0-based) of the first cnt keys of buf, by one wave:
 // the keys go to registers, S per lane, and the answer is built bit by bit
 // below the common prefix of the smallest and largest key; bit b is set
@@ -204,15 +212,22 @@ __device__ typename KeyOf<T>::K select_rank_wave(const T *buf, uint32_t cnt, uin
         kmin = a < kmin ? a : kmin;
         kmax = b > kmax ? b : kmax;
     }
+    // every lane holds the same extremes: make them scalar so that the
+    // search below runs on scalar registers with scalar loop control
+    kmin = uniform_key(kmin);
+    kmax = uniform_key(kmax);
     const K diff = kmin ^ kmax;
     const int top = diff ? kBits - 1 - (sizeof(K) == 8 ? __builtin_clzll((unsigned long long)diff)
                                                        : __builtin_clz((uint32_t)diff)) : -1;
     K prefix = top >= kBits - 1 ? (K)0 : (kmin & ~((((K)1) << (top + 1)) - 1));
     for (int b = top; b >= 0; --b) {
         const K t = prefix | ((K)1 << b);
+        uint64_t m[S];
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) m[sl] = __builtin_amdgcn_ballot_w64(key[sl] < t);
         uint32_t c = 0;
 #pragma unroll
-        for (int sl = 0; sl < S; ++sl) c += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(key[sl] < t));
+        for (int sl = 0; sl < S; ++sl) c += (uint32_t)__builtin_popcountll(m[sl]);
         if (c <= r) prefix = t;
     }
     return prefix;

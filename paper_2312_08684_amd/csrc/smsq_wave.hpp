@@ -106,7 +106,24 @@ __global__ __launch_bounds__(64) void k_step_wave(StepArgs<T> a)
         if (a.bw_mode == 0 || it == 0) {
             T med = (T)0;
             if (M > 0) {
-                for (int k = 1; k < n; ++k) {
+                // four columns at a time: independent chains for one wave
+                int k = 1;
+                for (; k + 4 <= n; k += 4) {
+                    T dd[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        dd[u] = 0;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            const T r = xi[c] - lane_bcast(xi[c], k + u);
+                            dd[u] += r * r;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (lane < k + u) pairs[(uint32_t)((k + u) * (k + u - 1) / 2 + lane)] = dd[u];
+                }
+                for (; k < n; ++k) {
                     T dd = 0;
 #pragma unroll
                     for (int c = 0; c < D; ++c) {
@@ -218,21 +235,35 @@ __global__ __launch_bounds__(64) void k_step_wave(StepArgs<T> a)
         T as[D], ar[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) { as[c] = 0; ar[c] = 0; }
-        for (int k = 0; k < n; ++k) {
-            T df[D], skb[D], dd = 0;
+        // four sources at a time (independent chains), summed in order
+        auto pair_terms = [&](int k, T (&df)[D], T (&skb)[D], T &kap, T &w) {
+            T dd = 0;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
                 df[c] = xi[c] - lane_bcast(xi[c], k);
                 skb[c] = lane_bcast(sk[c], k);
                 dd += df[c] * df[c];
             }
-            T kap, w;
             if (a.kernel == 0) {
                 kap = R::exp2_(-beta * dd);
                 w = kap;  // times 2/h below
             } else {
                 stein_kernel<T>(a.kernel, dd, inv_h, kap, w);
             }
+        };
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+            T df[4][D], skb[4][D], kap[4], w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pair_terms(k + u, df[u], skb[u], kap[u], w[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < D; ++c) { as[c] += kap[u] * skb[u][c]; ar[c] += w[u] * df[u][c]; }
+        }
+        for (; k < n; ++k) {
+            T df[D], skb[D], kap, w;
+            pair_terms(k, df, skb, kap, w);
 #pragma unroll
             for (int c = 0; c < D; ++c) { as[c] += kap * skb[c]; ar[c] += w * df[c]; }
         }

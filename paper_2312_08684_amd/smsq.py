@@ -561,6 +561,16 @@ class InitMLP:
         _check(load().smsq_init_mlp_sync(self.handle, _stream(None)), "smsq_init_mlp_sync")
         torch.cuda.synchronize()
 
+    def save(self, path: str):
+        """Writes the FP32 parameters to a .npy file (no pickled objects)."""
+        np.save(path, self.params().detach().cpu().numpy(), allow_pickle=False)
+
+    def load_params(self, path: str):
+        """Reads parameters written by save (plain array, allow_pickle=False)
+        and refreshes the BF16 weight copies and the optimiser state."""
+        P = np.load(path, allow_pickle=False)
+        self.set_params(torch.as_tensor(np.ascontiguousarray(P, dtype=np.float32), device="cuda"))
+
     def forward(self, F: torch.Tensor) -> torch.Tensor:
         B = F.shape[0]
         out = torch.empty((B, INIT_OUT), dtype=torch.float32, device=F.device)

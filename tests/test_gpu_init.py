@@ -182,3 +182,21 @@ def test_training_lowers_the_loss():
     last = last.item()
     print("mixture NLL %.4f -> %.4f" % (first, last))
     assert np.isfinite(last) and last < first - 1.0
+
+
+def test_parameters_save_and_load(tmp_path):
+    """A trained-looking parameter set survives save / load_params bit for
+    bit, and the reloaded network computes the same outputs."""
+    rng = np.random.default_rng(12)
+    P = rng.normal(scale=0.1, size=M.N_PARAMS).astype(np.float32)
+    a = _mlp_with(P.astype(np.float64))
+    path = str(tmp_path / "proposal.npy")
+    a.save(path)
+    b = smsq.InitMLP(seed=7, max_batch=256)
+    assert not torch.equal(a.params(), b.params())
+    b.load_params(path)
+    assert torch.equal(a.params(), b.params())
+    F = torch.tensor(rng.normal(size=(9, M.FEAT)).astype(np.float32), device="cuda")
+    assert torch.equal(a.forward(F), b.forward(F))
+    a.close()
+    b.close()

@@ -12,7 +12,7 @@ library's kernels.  The recipe:
 3. on a validation mix, compare the MAP log-posterior J reached with a
    reduced iteration count from the proposal against the predictive
    initialisation, per model family, and keep the proposal only where it
-   gains (the plain method judges it by its final J);
+   gains (measured by the final J it leads to);
 4. run with the reduced iteration count and the gate.
 """
 from __future__ import annotations

@@ -635,6 +635,40 @@ def test_run_sequence_f32_free_running(name, n, T, L):
     assert abs(Jpath - J) <= TOL_J * max(abs(J), T)
 
 
+@pytest.mark.parametrize("case", ["one_particle", "one_step", "all_masked", "one_particle_f64"])
+def test_run_sequence_edge_cases(case):
+    """Algorithm 2 at its edges against the oracle: a single particle per step
+    (SVGD is gradient ascent, the lattice a chain), a single time step, and
+    observations masked out everywhere (the estimate follows the dynamics)."""
+    announce("run_sequence edge", case)
+    name, n, T, L, dt = "range2d", 40, 6, 10, "f32"
+    if case.startswith("one_particle"):
+        n = 1
+    if case == "one_particle_f64":
+        name, dt, T, L = "growth1d", "f64", 12, 30
+    if case == "one_step":
+        T = 1
+    wl = S.make_workload(name, B=1, seed=1009, T=T, n=n, n_iter=L)
+    desc, o = wl.model, wl.opts
+    mask = None if wl.mask is None else wl.mask[0].copy()
+    if case == "all_masked":
+        mask[:] = 0
+    res = O.run_sequence(desc, T, n, wl.x0[0], wl.z[0], mask, 13, 0, o.n_iter, o.step)
+    td = tdt(dt)
+    model = smsq.Model(desc)
+    xmap, J = smsq.run_sequence(model, dt, dev(wl.x0[0], td), dev(wl.z[0], td),
+                                None if mask is None else dev(mask, torch.uint8), n, smsq.opts_from(o), 13)
+    xmap, J = host(xmap).astype(np.float64), float(host(J)[0])
+    dJ = abs(J - res["J"]) / max(abs(res["J"]), T)
+    print("J gpu %.8f oracle %.8f rel %.3e" % (J, res["J"], dJ))
+    assert dJ <= TOL_J
+    if dt == "f64":
+        assert np.allclose(xmap, res["xmap"], rtol=1e-6, atol=1e-6)
+    else:   # FP32 may pick another near-tied particle: J of its own path instead
+        Jpath = O.path_score(desc, xmap, wl.z[0], mask)
+        assert abs(Jpath - J) <= TOL_J * max(abs(J), T)
+
+
 def test_run_batch_matches_single_runs_and_is_deterministic():
     announce("run_batch determinism")
     wl = S.make_workload("range2d", B=3, seed=1002, T=10, n=48, n_iter=8)

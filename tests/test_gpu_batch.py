@@ -174,3 +174,37 @@ def test_batch_plan_argument_errors():
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan(models, imq, seqs)
     assert e.value.status == smsq.ERR_UNSUPPORTED
+
+
+def test_full_ragged_mix_sampled_sequences():
+    """The batched plan at the benchmark's full size: 4096 sequences of the
+    four families (N in {32, ..., 1024}, T in [50, 200], full iteration
+    counts) in one plan with graph replay.  Sampled sequences, the largest N
+    of each family, reach the J of the standalone Algorithm 2 on the same
+    inputs (itself tested against the oracle) within 1e-3 max(|J|, T), and
+    every sampled J is the path score of the plan's own MAP trajectory
+    (evaluated in FP64 by the oracle).  Over hundreds of steps the two FP32
+    kernels may part on near-ties, so the paths themselves are not compared."""
+    import oracle as O
+    from paper_2312_08684_amd import learned as LI
+    spec = LI.mix(4096, seed=11, T_lo=50, T_hi=200)
+    mx = LI.Mix(spec)
+    plan, J, _, models, seqs = LI.run(mx, 1.0, warm=False)
+    assert plan.status() == smsq.OK
+    Jn = J.cpu().numpy() if hasattr(J, "cpu") else np.asarray(J)
+    assert np.all(np.isfinite(Jn))
+    _, opts, _ = LI.build(mx, 1.0)
+    for fam in ("growth1d", "range2d", "cv4d", "arm7"):
+        idx = [i for i, s in enumerate(spec) if s[0] == fam]
+        i = max(idx, key=lambda k: (spec[k][1], -k))
+        _, n, T, _ = spec[i]
+        q = seqs[i]
+        xmap, Js = smsq.run_sequence(models[i], "f32", q["x0"], q["z"], q["z_mask"], n, opts[i], q["seed"])
+        Jp = float(plan.J[i].item())
+        Js = float(Js.cpu()[0])
+        wl = mx.wls[i]
+        mask = None if wl.mask is None else wl.mask[0]
+        Jpath = O.path_score(wl.model, plan.xmap[i].cpu().double().numpy(), wl.z[0], mask)
+        print("%s n=%d T=%d: plan J %.4f single J %.4f path score %.4f" % (fam, n, T, Jp, Js, Jpath), flush=True)
+        assert abs(Jp - Js) <= 1e-3 * max(abs(Js), T)
+        assert abs(Jpath - Jp) <= 1e-3 * max(abs(Jp), T)

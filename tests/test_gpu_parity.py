@@ -316,6 +316,10 @@ SVGD_CASES = [
     ("scenario_b", 300, 130, 30, 1e-4),
     ("scenario_d", 20, 20, 100, 2e-4),
     ("scenario_d", 150, 70, 30, 2e-4),
+    # the range-only and clutter workloads at their full particle counts and
+    # iteration counts (one teacher-forced step)
+    ("range2d", 256, 256, 50, 0.005),
+    ("cv4d", 512, 512, 50, 0.005),
 ]
 
 

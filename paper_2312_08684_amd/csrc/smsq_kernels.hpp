@@ -2,9 +2,14 @@
 //
 // One workgroup owns one sequence and keeps its whole particle state in LDS
 // for a time step: the previous particles' transition means, the current
-// particles and their scores.  Every SVGD iteration (eq. SVGD_newupdate) is
-//   (1) exact lower median of the pairwise squared distances by radix
-//       selection on their bit patterns (bandwidth h = s med / ln N),
+// particles and their scores.  The file also holds the chip-wide
+// particle-mode forward recursion, the lattice-mode recursion and the
+// backtrack.  Every SVGD iteration (eq. SVGD_newupdate) is
+//   (1) exact lower median of the pairwise squared distances (bandwidth
+//       h = s med / ln N): all pairs, or those in a window around the
+//       previous iteration's median, gathered in LDS and selected by a
+//       ballot bisection on their bit patterns; radix selection over all
+//       pairs when the window misses or overflows,
 //   (2) per-particle score: observation gradient plus the log-sum-exp
 //       transition-mixture gradient, with an online (running-max) softmax
 //       over the previous particles,

@@ -753,8 +753,8 @@ smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t, i
     if (!ws || ws_bytes < kHeader) return SMSQ_ERR_WORKSPACE;
     if (lattice) {
         if (!loglik) return SMSQ_ERR_INVALID;
-        const int rows_per_block = 4;
-        const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(rows_per_block * kWave);
+        const int rows_per_block = 2;  // four waves, two per row
+        const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(4 * kWave);
         if (dtype == SMSQ_F64)
             hipLaunchKernelGGL(k_viterbi_lattice<double>, grid, block, 0, stream, n, n_prev,
                                (const double *)lattice, (const double *)loglik, (const double *)phi_prev,

@@ -639,7 +639,8 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<T> a)
 }
 
 // ---------------------------------------------------------------------------
-// Lattice-mode forward recursion: one wave per row i, coalesced over j.
+// Lattice-mode forward recursion: two waves per row i (halves of j,
+// coalesced), merged through LDS.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, const T *__restrict__ A,
@@ -649,29 +650,36 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
                                                          uint32_t *status)
 {
     using R = RealOps<T>;
+    constexpr int kSplit = 2;                  // waves per row
+    constexpr int kRowsPerBlock = 4 / kSplit;  // four waves per workgroup
+    __shared__ T sbest[4], ssecond[4];
+    __shared__ int sarg[4];
     const int lane = threadIdx.x & (kWave - 1);
-    const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (i >= n) return;
-    const T *row = A + (long)i * n_prev;
+    const int w = threadIdx.x / kWave;
+    const int part = w % kSplit;
+    const int i = blockIdx.x * kRowsPerBlock + w / kSplit;
+    const bool live = i < n;
     ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};
     bool nan_seen = false;
     // 16-byte loads, four per lane in flight (4 KB per wave), when the rows
-    // allow; each lane still visits its indices in ascending order, so the
-    // first maximum wins within a lane and the merge keeps the lowest index
+    // allow; each wave takes one contiguous part of the row and each lane
+    // visits its indices in ascending order, so the first maximum wins within
+    // a lane and the merges keep the lowest index
     constexpr int V = 16 / (int)sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(V)));
     const bool vec = n_prev % V == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)phi_prev % 16) == 0;
-    if (vec) {
+    if (live && vec) {
         const int nv = n_prev / V;
-        const vec_t *rv = (const vec_t *)row;
+        const int lo = (int)((long)nv * part / kSplit), hi = (int)((long)nv * (part + 1) / kSplit);
+        const vec_t *rv = (const vec_t *)(A + (long)i * n_prev);
         const vec_t *pv = (const vec_t *)phi_prev;
         bool first = true;
-        for (int v0 = lane; v0 < nv; v0 += 4 * kWave) {
+        for (int v0 = lo + lane; v0 < hi; v0 += 4 * kWave) {
             vec_t a4[4], p4[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int v = v0 + u * kWave;
-                if (v < nv) {
+                if (v < hi) {
                     a4[u] = __builtin_nontemporal_load(rv + v);
                     p4[u] = pv[v];
                 }
@@ -679,7 +687,7 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int v = v0 + u * kWave;
-                if (v < nv) {
+                if (v < hi) {
 #pragma unroll
                     for (int e = 0; e < V; ++e) {
                         const T c = a4[u][e] + p4[u][e];
@@ -691,16 +699,22 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
                 }
             }
         }
-    } else {
-        for (int j = lane; j < n_prev; j += kWave) {
+    } else if (live) {
+        const int lo = (int)((long)n_prev * part / kSplit), hi = (int)((long)n_prev * (part + 1) / kSplit);
+        const T *row = A + (long)i * n_prev;
+        bool first = true;
+        for (int j = lo + lane; j < hi; j += kWave) {
             const T c = row[j] + phi_prev[j];
             nan_seen |= (c != c);
-            if (j == lane) { ab.best = c; ab.arg = j; }
+            if (first) { ab.best = c; ab.arg = j; first = false; }
             else argbest_push(ab, c, j);
         }
     }
     ab = wave_argbest(ab);
-    if (lane == 0) {
+    if (lane == 0) { sbest[w] = ab.best; ssecond[w] = ab.second; sarg[w] = ab.arg; }
+    __syncthreads();
+    if (live && part == 0 && lane == 0) {
+        for (int h = 1; h < kSplit; ++h) ab = argbest_merge(ab, ArgBest<T>{sbest[w + h], ssecond[w + h], sarg[w + h]});
         const T e = ell[i];
         const T ph = ab.best + e;
         phi[i] = ph;

@@ -26,6 +26,7 @@ reference.
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import math
 import os
@@ -439,28 +440,29 @@ def sweep(torch, smsq):
             del As
             rows.append({"mode": "lattice", "dtype": dt, "N": n, "us_per_launch": sec * 1e6,
                          "edges_per_s": n * n / sec, "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM})
-    for name, n in (("range2d", 256), ("cv4d", 512), ("arm7", 1024), ("range2d", 4096)):
+    for (name, n), (dt, tdt) in itertools.product((("range2d", 256), ("cv4d", 512), ("arm7", 1024), ("range2d", 4096)),
+                                                 (("f32", torch.float32), ("f64", torch.float64))):
         wl = S.make_workload(name, B=1, seed=0, T=2, n=n)
         model = smsq.Model(wl.model)
         d = wl.model.d
         rng = np.random.default_rng(1)
-        xp = torch.tensor(wl.truth[0, 1] + 0.02 * rng.normal(size=(n, d)), dtype=torch.float32, device="cuda")
-        x = torch.tensor(wl.truth[0, 2] + 0.02 * rng.normal(size=(n, d)), dtype=torch.float32, device="cuda")
-        z = torch.tensor(wl.z[0, 1], dtype=torch.float32, device="cuda")
+        xp = torch.tensor(wl.truth[0, 1] + 0.02 * rng.normal(size=(n, d)), dtype=tdt, device="cuda")
+        x = torch.tensor(wl.truth[0, 2] + 0.02 * rng.normal(size=(n, d)), dtype=tdt, device="cuda")
+        z = torch.tensor(wl.z[0, 1], dtype=tdt, device="cuda")
         mk = torch.tensor(wl.mask[0, 1], dtype=torch.uint8, device="cuda") if wl.mask is not None else None
-        php = torch.zeros(n, dtype=torch.float32, device="cuda")
+        php = torch.zeros(n, dtype=tdt, device="cuda")
         ws = smsq.workspace()
         for _ in range(3):
-            smsq.viterbi_step(model, "f32", 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
+            smsq.viterbi_step(model, dt, 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
         reps = 50
         e0, e1 = _events(torch)
         e0.record()
         for _ in range(reps):
-            smsq.viterbi_step(model, "f32", 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
+            smsq.viterbi_step(model, dt, 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
         e1.record()
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3 / reps
-        rows.append({"mode": "particle (one sequence, rows over the chip)", "model": name, "dtype": "f32", "N": n,
+        rows.append({"mode": "particle (one sequence, rows over the chip)", "model": name, "dtype": dt, "N": n,
                      "us_per_launch": sec * 1e6, "edges_per_s": n * n / sec})
     out["viterbi_vs_n"] = rows
     # (3) Algorithm 2 end to end per workload: one sequence and a batch

@@ -180,7 +180,8 @@ smsq_status_t launch_step_kd(const StepArgs<T> &a, int batch, hipStream_t s)
 }
 
 // The FP32 matrix-core kernel takes sequences of 32 to 1024 particles whose
-// state fits LDS; below 32 particles the one-wave kernel is faster.
+// state fits LDS and which the one-wave kernel does not take (below 32
+// particles the vector-ALU kernels are faster).
 // SMSQ_STEP_KERNEL=valu selects the workgroup vector-ALU kernel for every
 // size, SMSQ_STEP_KERNEL=mfma the matrix-core kernel for every size that
 // fits it (batched plans run it at any size).
@@ -217,20 +218,21 @@ smsq_status_t launch_wave_kd(const StepArgs<T> &a, int batch, hipStream_t s)
 }
 
 // The one-wave kernel fits at most 64 particles and 64 previous ones; by
-// default it takes steps of up to 32 particles in FP64 and below the
-// matrix-core kernel's range in FP32 (measured: 8..12% faster than the
-// workgroup vector-ALU kernel at 10..20 particles, 2.2x for the 14-D model
-// in FP64, even at 32, slower at 64).  SMSQ_STEP_KERNEL=wave selects it
-// wherever it fits, =valu or =mfma the other kernels.
+// default it takes steps of up to 32 particles in both precisions
+// (measured: 8..12% faster than the workgroup vector-ALU kernel at 10..20
+// particles, 2.2x for the 14-D model in FP64, even at 32, slower at 64; in
+// FP32 at 32 particles 0.70..0.80 of the matrix-core kernel's time, which
+// wins from 40 on for d >= 3).  SMSQ_STEP_KERNEL=wave selects it wherever
+// it fits, =valu or =mfma the other kernels.
 constexpr int kWaveDefaultMax = 32;
 
-bool use_wave(int n, int n_prev, bool fp32)
+bool use_wave(int n, int n_prev)
 {
     if (n > kWaveMaxParticles || n_prev > kWaveMaxParticles) return false;
     const char *e = std::getenv("SMSQ_STEP_KERNEL");
     if (e && std::strcmp(e, "wave") == 0) return true;
     if (e && (std::strcmp(e, "valu") == 0 || std::strcmp(e, "mfma") == 0)) return false;
-    return fp32 ? n < kMfmaMinParticles : n <= kWaveDefaultMax;
+    return n <= kWaveDefaultMax;
 }
 
 template <typename T>
@@ -260,7 +262,7 @@ smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int 
 template <>
 smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
 {
-    if (use_wave(a.n, a.n_prev, true)) return launch_wave<float>(d, a, batch, s);
+    if (use_wave(a.n, a.n_prev)) return launch_wave<float>(d, a, batch, s);
     // the matrix-core kernel runs the RBF kernel on states of up to 7
     // dimensions; IMQ, Matern and the 14-D model take the vector-ALU kernel
     if (a.kernel == 0 && d.d <= 7 && use_mfma(a.n, a.n_prev)) {
@@ -301,7 +303,7 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
 template <>
 smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<double> &a, int batch, hipStream_t s)
 {
-    if (use_wave(a.n, a.n_prev, false)) return launch_wave<double>(d, a, batch, s);
+    if (use_wave(a.n, a.n_prev)) return launch_wave<double>(d, a, batch, s);
     switch (d.kind) {
     case SMSQ_MODEL_GROWTH1D: return launch_step_kd<double, GROWTH1D, 1>(a, batch, s);
     case SMSQ_MODEL_RANGE2D: return launch_step_kd<double, RANGE2D, 2>(a, batch, s);

@@ -378,6 +378,9 @@ def test_svgd_step_variants(variant):
 WAVE_CASES = [
     ("growth1d", 1, 1, 30, 0.05, "f64"),
     ("growth1d", 2, 64, 30, 0.05, "f64"),
+    ("growth1d", 10, 10, 100, 0.05, "f64"),
+    ("range2d", 16, 16, 50, 0.005, "f32"),
+    ("scenario_b", 10, 10, 100, 1e-4, "f32"),
     ("growth1d", 20, 20, 100, 0.05, "f64"),
     ("growth1d", 64, 64, 50, 0.05, "f64"),
     ("range2d", 33, 17, 20, 0.005, "f32"),
@@ -393,7 +396,9 @@ WAVE_CASES = [
 @pytest.mark.parametrize("name,n,n_prev,L,step,dt", WAVE_CASES)
 def test_svgd_step_one_wave_kernel(name, n, n_prev, L, step, dt, monkeypatch):
     """The one-wave kernel (particles in lane registers, readlane broadcasts)
-    on every family, from one particle to 64, against the oracle."""
+    on every family, from one particle to 64, against the oracle; the pair
+    counts span every register blocking of the median's selection (1, 2, 4,
+    8, 16 and 32 distances per lane)."""
     announce("svgd step wave", name, n, n_prev, L, dt)
     monkeypatch.setenv("SMSQ_STEP_KERNEL", "wave")
     wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 24, dt)
@@ -401,7 +406,7 @@ def test_svgd_step_one_wave_kernel(name, n, n_prev, L, step, dt, monkeypatch):
 
 
 @pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "imq", "matern32",
-                                     "ties_2x10", "ties_8x8"])
+                                     "ties_2x5", "ties_4x4", "ties_2x10", "ties_8x8"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_svgd_step_one_wave_variants(variant, dt, monkeypatch):
     """Options and exact ties on the one-wave kernel (range-only model)."""
@@ -447,10 +452,11 @@ def test_svgd_step_ties_vector_alu(variant, dt, monkeypatch):
     _compare_svgd(desc, dt, xp, None, z, mask, x, 6, 0.005)
 
 
-@pytest.mark.parametrize("n,n_prev", [(1, 50), (2, 50), (20, 20), (31, 7)])
+@pytest.mark.parametrize("n,n_prev", [(1, 50), (2, 50), (20, 20), (31, 7), (32, 32)])
 def test_svgd_step_small_n_matrix_core(n, n_prev, monkeypatch):
-    """Below 32 particles single steps take the vector-ALU kernel; batched
-    plans still run the matrix-core kernel there, forced here."""
+    """Up to 32 particles single steps take the one-wave kernel (or the
+    vector-ALU kernel); batched plans still run the matrix-core kernel
+    there, forced here."""
     announce("svgd step small n mfma", n, n_prev)
     monkeypatch.setenv("SMSQ_STEP_KERNEL", "mfma")
     wl, desc, xp, x, z, mask = _svgd_case("range2d", n, n_prev, 23, "f32")

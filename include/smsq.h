@@ -166,8 +166,9 @@ smsq_status_t smsq_workspace_size(smsq_model_t model, smsq_dtype_t dtype, int ba
  * Requires n >= 1, n_prev >= 1; SMSQ_ERR_UNSUPPORTED when the particle sets
  * do not fit one compute unit's LDS.
  * Kernel choice (also for smsq_batch_step, smsq_run_batch and
- * smsq_run_sequence): up to 32 particles and at most 64 previous ones, a
- * one-wave kernel with the particles in registers;
+ * smsq_run_sequence): up to 32 particles (FP32 states of one or two
+ * dimensions: 40) and at most 64 previous ones, a one-wave kernel with the
+ * particles in registers;
  * otherwise FP32 with the RBF kernel, d <= 7 and up to 1024 particles runs
  * on the matrix cores, and FP64, the IMQ and Matern kernels, d > 7 or more
  * than 1024 particles on the workgroup vector-ALU kernel.  The environment

@@ -218,21 +218,24 @@ smsq_status_t launch_wave_kd(const StepArgs<T> &a, int batch, hipStream_t s)
 }
 
 // The one-wave kernel fits at most 64 particles and 64 previous ones; by
-// default it takes steps of up to 32 particles in both precisions
-// (measured: 8..12% faster than the workgroup vector-ALU kernel at 10..20
-// particles, 2.2x for the 14-D model in FP64, even at 32, slower at 64; in
-// FP32 at 32 particles 0.70..0.80 of the matrix-core kernel's time, which
-// wins from 40 on for d >= 3).  SMSQ_STEP_KERNEL=wave selects it wherever
-// it fits, =valu or =mfma the other kernels.
+// default it takes steps of up to 32 particles in both precisions, and of
+// up to 40 for FP32 states of one or two dimensions (measured: 8..12%
+// faster than the workgroup vector-ALU kernel at 10..20 particles, 2.2x for
+// the 14-D model in FP64, even at 32, slower at 64; in FP32 at 32 particles
+// 0.70..0.89 of the matrix-core kernel's time, and at 40 for the range
+// model 0.73, while the matrix cores win from 40 on for d >= 3 and from 48
+// on for d = 2).  SMSQ_STEP_KERNEL=wave selects it wherever it fits, =valu
+// or =mfma the other kernels.
 constexpr int kWaveDefaultMax = 32;
+constexpr int kWaveSmallStateMax = 40;
 
-bool use_wave(int n, int n_prev)
+bool use_wave(int n, int n_prev, int d, bool fp32)
 {
     if (n > kWaveMaxParticles || n_prev > kWaveMaxParticles) return false;
     const char *e = std::getenv("SMSQ_STEP_KERNEL");
     if (e && std::strcmp(e, "wave") == 0) return true;
     if (e && (std::strcmp(e, "valu") == 0 || std::strcmp(e, "mfma") == 0)) return false;
-    return n <= kWaveDefaultMax;
+    return n <= kWaveDefaultMax || (fp32 && d <= 2 && n <= kWaveSmallStateMax);
 }
 
 template <typename T>
@@ -262,7 +265,7 @@ smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int 
 template <>
 smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
 {
-    if (use_wave(a.n, a.n_prev)) return launch_wave<float>(d, a, batch, s);
+    if (use_wave(a.n, a.n_prev, d.d, true)) return launch_wave<float>(d, a, batch, s);
     // the matrix-core kernel runs the RBF kernel on states of up to 7
     // dimensions; IMQ, Matern and the 14-D model take the vector-ALU kernel
     if (a.kernel == 0 && d.d <= 7 && use_mfma(a.n, a.n_prev)) {
@@ -303,7 +306,7 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
 template <>
 smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<double> &a, int batch, hipStream_t s)
 {
-    if (use_wave(a.n, a.n_prev)) return launch_wave<double>(d, a, batch, s);
+    if (use_wave(a.n, a.n_prev, d.d, false)) return launch_wave<double>(d, a, batch, s);
     switch (d.kind) {
     case SMSQ_MODEL_GROWTH1D: return launch_step_kd<double, GROWTH1D, 1>(a, batch, s);
     case SMSQ_MODEL_RANGE2D: return launch_step_kd<double, RANGE2D, 2>(a, batch, s);

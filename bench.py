@@ -154,9 +154,30 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
     torch.cuda.synchronize()
     sec = ev0.elapsed_time(ev1) / 1e3 / (reps * batch)
     nbytes = n * n * 4 + 3 * n * 4 + n * 4
+
+    # Library references over the same lattices, for the bandwidth a single
+    # launch of this size reaches: torch's row maximum (the same reads, no
+    # argmax) and a device copy (the same reads plus as many writes).
+    def lib_rate(fn, moved):
+        for a in A[:2]:
+            fn(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            for a in A:
+                fn(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return moved / (e0.elapsed_time(e1) / 1e3 / (reps * batch)) / 1e9
+
+    dst = torch.empty_like(A[0])
+    rowmax = lib_rate(lambda a: torch.amax(a, dim=1), n * n * 4 + n * 4)
+    copy = lib_rate(lambda a: dst.copy_(a), 2 * n * n * 4)
     return {"n": n, "lattices": batch, "edges_per_s": n * n / sec, "us_per_launch": sec * 1e6,
             "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM,
-            "bytes_per_launch": nbytes}
+            "bytes_per_launch": nbytes, "torch_rowmax_GBps": rowmax, "torch_copy_GBps": copy}
 
 
 # Kernel / bandwidth / particle-count grid of the kernel ablation (Sec. V-E,

@@ -657,8 +657,14 @@ def main():
     edges = B * (n * 1 + (T - 1) * n * n)
     flops_total = B * L * (flops_per_iteration(n, 1, d, name) + (T - 1) * flops_per_iteration(n, n, d, name))
     kern = np.array(kernel_ms)                     # [steps, T] ms per launch
-    k_avg_ms = float(kern[:, 1:].mean())           # steady-state launches (n_prev = n)
-    flops_launch = B * L * flops_per_iteration(n, n, d, name)
+    if T >= 2:
+        k_avg_ms = float(kern[:, 1:].mean())       # steady-state launches (n_prev = n)
+        flops_launch = B * L * flops_per_iteration(n, n, d, name)
+        launch_kind = "steady-state launch"
+    else:
+        k_avg_ms = float(kern[:, 0].mean())        # the only launch: one previous particle
+        flops_launch = B * L * flops_per_iteration(n, 1, d, name)
+        launch_kind = "first launch (one previous particle)"
     achieved = flops_launch / (k_avg_ms / 1e3)
     peak = PEAK_FP64 if dt == "f64" else PEAK_FP32
     lat = lattice_bandwidth(torch, smsq, args.lattice_n, args.lattice_batch)
@@ -681,10 +687,10 @@ def main():
         "sequences_per_s": B / (ms / 1e3),
         "counted_tflops": flops_total / (ms / 1e3) / 1e12,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(name, B, n, dt),
+                     "frac": achieved / peak, "traffic": measured_traffic(name, B, n, dt) if T >= 2 else None,
                      "kernel": ("k_step_mfma (fused SVGD iterations + forward recursion, FP32 matrix cores)"
                                 if dt == "f32" else "k_step (fused SVGD iterations + forward recursion, FP64)")
-                     + ", steady-state launch",
+                     + ", " + launch_kind,
                      "kernel_avg_ms": k_avg_ms, "flops_per_launch": flops_launch},
         "viterbi_lattice": lat,
     }

@@ -130,7 +130,12 @@ typedef enum { SMSQ_KERNEL_RBF = 0, SMSQ_KERNEL_IMQ = 1, SMSQ_KERNEL_MATERN32 = 
  *              previous step's forward-recursion scores, in the drivers that
  *              hold them (smsq_batch_step, smsq_run_batch, smsq_run_sequence,
  *              batched plans): the step's target is conditioned on the MAP
- *              recursion so far.  smsq_svgd_step takes log_w_prev as given. */
+ *              recursion so far.  smsq_svgd_step takes log_w_prev as given.
+ *  step_kernel smsq_step_kernel_t: which step kernel runs the step (0 =
+ *              automatic choice by size, precision and kernel; the others
+ *              force one kernel wherever the shape fits it, else the
+ *              automatic choice applies).  Results agree to rounding.
+ *              Batched plans run their own persistent kernel and require 0. */
 typedef struct {
     int n_iter;
     double step;
@@ -139,7 +144,16 @@ typedef struct {
     int trans_mode;
     int kernel;
     int weights;
+    int step_kernel;
 } smsq_svgd_opts_t;
+
+/* Step kernels (see smsq_svgd_step for the automatic choice). */
+typedef enum {
+    SMSQ_STEP_AUTO = 0,
+    SMSQ_STEP_WAVE = 1,   /* one wave per sequence, particles in registers (n, n_prev <= 64) */
+    SMSQ_STEP_VALU = 2,   /* one workgroup per sequence on the vector ALU (any kernel, FP64) */
+    SMSQ_STEP_MFMA = 3    /* one workgroup per sequence on the matrix cores (FP32, RBF, d <= 7) */
+} smsq_step_kernel_t;
 
 /* Validates a model description and copies it into an immutable handle.
  * Returns SMSQ_ERR_INVALID for an unknown kind, a d or observation size that
@@ -171,9 +185,8 @@ smsq_status_t smsq_workspace_size(smsq_model_t model, smsq_dtype_t dtype, int ba
  * particles in registers;
  * otherwise FP32 with the RBF kernel, d <= 7 and up to 1024 particles runs
  * on the matrix cores, and FP64, the IMQ and Matern kernels, d > 7 or more
- * than 1024 particles on the workgroup vector-ALU kernel.  The environment
- * variable SMSQ_STEP_KERNEL=wave, =valu or =mfma forces one of them
- * wherever it fits (tests use all three); results agree to rounding. */
+ * than 1024 particles on the workgroup vector-ALU kernel.  opts->step_kernel
+ * forces one of them wherever it fits; results agree to rounding. */
 smsq_status_t smsq_svgd_step(smsq_model_t model, smsq_dtype_t dtype, int t,
                              int n_prev, const void *x_prev, const void *log_w_prev,
                              const void *z_t, const uint8_t *z_mask,

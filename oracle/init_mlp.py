@@ -4,9 +4,10 @@ Plain numpy, written from the definitions (not from the HIP code): the
 feature summary of a sequence step, the 64-256-256-120 ReLU network, the
 8-component diagonal Gaussian mixture it outputs, the mixture negative
 log-likelihood of a particle set and the gradients of both (hand-derived
-backpropagation).  The paper gives no initialisation of the particles of a
-new step (Algorithm 2 starts SVGD from them without saying how they are
-drawn); this proposal is an addition whose arithmetic is fixed here.
+backpropagation), and the Adam update that trains the network.  The paper
+gives no initialisation of the particles of a new step (Algorithm 2 starts
+SVGD from them without saying how they are drawn); this proposal is an
+addition whose arithmetic is fixed here.
 
 ``bf16=True`` rounds what the GPU kernels feed to their BF16 products (the
 input features, the weights, the hidden activations and the back-propagated
@@ -14,7 +15,9 @@ gradients) to bfloat16 with round-to-nearest-even; everything else stays
 FP64.  Pins (tests/test_oracle_init.py): backward against central finite
 differences of forward, the NLL gradient against finite differences of the
 NLL, the one-component one-dimensional NLL against scipy's normal log-pdf,
-features of a set of identical particles in closed form.
+features of a set of identical particles in closed form, the mixture
+moments against a hand-solved two-component mixture (law of total variance),
+Adam against a hand-worked two-step example and its closed-form first step.
 """
 from __future__ import annotations
 
@@ -163,3 +166,18 @@ def mixture_moments(out, a, s, d):
     m = (p * mean).sum(axis=0)
     v = (p * (sd ** 2 + mean ** 2)).sum(axis=0) - m ** 2
     return m, v
+
+
+def adam_step(P, G, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, ICLR 2015, Algorithm 1) at step t >= 1:
+    first and second moment estimates m <- b1 m + (1 - b1) g and
+    v <- b2 v + (1 - b2) g^2, their bias-corrected values m / (1 - b1^t) and
+    v / (1 - b2^t), and P <- P - lr m_hat / (sqrt(v_hat) + eps), with eps
+    added outside the square root.  Returns (P, m, v) as new arrays."""
+    P = np.asarray(P, dtype=np.float64)
+    g = np.asarray(G, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return P - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -18,8 +18,6 @@
 #include "smsq_batch.hpp"
 #include "smsq_init.hpp"
 
-#include <cstdlib>
-
 using namespace smsq;
 
 struct smsq_model_s {
@@ -181,19 +179,18 @@ smsq_status_t launch_step_kd(const StepArgs<T> &a, int batch, hipStream_t s)
 
 // The FP32 matrix-core kernel takes sequences of 32 to 1024 particles whose
 // state fits LDS and which the one-wave kernel does not take (below 32
-// particles the vector-ALU kernels are faster).
-// SMSQ_STEP_KERNEL=valu selects the workgroup vector-ALU kernel for every
-// size, SMSQ_STEP_KERNEL=mfma the matrix-core kernel for every size that
-// fits it (batched plans run it at any size).
+// particles the vector-ALU kernels are faster).  The option step_kernel =
+// SMSQ_STEP_VALU selects the workgroup vector-ALU kernel for every size,
+// SMSQ_STEP_MFMA the matrix-core kernel for every size that fits it
+// (batched plans run it at any size).
 constexpr int kMfmaMinParticles = 32;
 
-bool use_mfma(int n, int n_prev)
+bool use_mfma(int n, int n_prev, int step_kernel)
 {
-    const char *e = std::getenv("SMSQ_STEP_KERNEL");
-    if (e && std::strcmp(e, "valu") == 0) return false;
+    if (step_kernel == SMSQ_STEP_VALU) return false;
     const MfmaLds L(n, n_prev);
     const bool fits = L.npad <= kMaxParticles && L.total <= kLdsLimit;
-    if (e && std::strcmp(e, "mfma") == 0) return fits;
+    if (step_kernel == SMSQ_STEP_MFMA) return fits;
     return fits && n >= kMfmaMinParticles;
 }
 
@@ -224,17 +221,16 @@ smsq_status_t launch_wave_kd(const StepArgs<T> &a, int batch, hipStream_t s)
 // the 14-D model in FP64, even at 32, slower at 64; in FP32 at 32 particles
 // 0.70..0.89 of the matrix-core kernel's time, and at 40 for the range
 // model 0.73, while the matrix cores win from 40 on for d >= 3 and from 48
-// on for d = 2).  SMSQ_STEP_KERNEL=wave selects it wherever it fits, =valu
-// or =mfma the other kernels.
+// on for d = 2).  step_kernel = SMSQ_STEP_WAVE selects it wherever it fits,
+// SMSQ_STEP_VALU or SMSQ_STEP_MFMA the other kernels.
 constexpr int kWaveDefaultMax = 32;
 constexpr int kWaveSmallStateMax = 40;
 
-bool use_wave(int n, int n_prev, int d, bool fp32)
+bool use_wave(int n, int n_prev, int d, bool fp32, int step_kernel)
 {
     if (n > kWaveMaxParticles || n_prev > kWaveMaxParticles) return false;
-    const char *e = std::getenv("SMSQ_STEP_KERNEL");
-    if (e && std::strcmp(e, "wave") == 0) return true;
-    if (e && (std::strcmp(e, "valu") == 0 || std::strcmp(e, "mfma") == 0)) return false;
+    if (step_kernel == SMSQ_STEP_WAVE) return true;
+    if (step_kernel == SMSQ_STEP_VALU || step_kernel == SMSQ_STEP_MFMA) return false;
     return n <= kWaveDefaultMax || (fp32 && d <= 2 && n <= kWaveSmallStateMax);
 }
 
@@ -260,15 +256,17 @@ smsq_status_t launch_wave(const smsq_model_desc_t &d, const StepArgs<T> &a, int 
 }
 
 template <typename T>
-smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int batch, hipStream_t s);
+smsq_status_t launch_step(const smsq_model_desc_t &d, const StepArgs<T> &a, int batch, int step_kernel,
+                          hipStream_t s);
 
 template <>
-smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, hipStream_t s)
+smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, int step_kernel,
+                                 hipStream_t s)
 {
-    if (use_wave(a.n, a.n_prev, d.d, true)) return launch_wave<float>(d, a, batch, s);
+    if (use_wave(a.n, a.n_prev, d.d, true, step_kernel)) return launch_wave<float>(d, a, batch, s);
     // the matrix-core kernel runs the RBF kernel on states of up to 7
     // dimensions; IMQ, Matern and the 14-D model take the vector-ALU kernel
-    if (a.kernel == 0 && d.d <= 7 && use_mfma(a.n, a.n_prev)) {
+    if (a.kernel == 0 && d.d <= 7 && use_mfma(a.n, a.n_prev, step_kernel)) {
         switch (d.kind) {
         case SMSQ_MODEL_GROWTH1D: return launch_mfma_kd<GROWTH1D, 1>(a, batch, s);
         case SMSQ_MODEL_RANGE2D: return launch_mfma_kd<RANGE2D, 2>(a, batch, s);
@@ -304,9 +302,10 @@ smsq_status_t launch_step<float>(const smsq_model_desc_t &d, const StepArgs<floa
 }
 
 template <>
-smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<double> &a, int batch, hipStream_t s)
+smsq_status_t launch_step<double>(const smsq_model_desc_t &d, const StepArgs<double> &a, int batch, int step_kernel,
+                                  hipStream_t s)
 {
-    if (use_wave(a.n, a.n_prev, d.d, false)) return launch_wave<double>(d, a, batch, s);
+    if (use_wave(a.n, a.n_prev, d.d, false, step_kernel)) return launch_wave<double>(d, a, batch, s);
     switch (d.kind) {
     case SMSQ_MODEL_GROWTH1D: return launch_step_kd<double, GROWTH1D, 1>(a, batch, s);
     case SMSQ_MODEL_RANGE2D: return launch_step_kd<double, RANGE2D, 2>(a, batch, s);
@@ -389,7 +388,8 @@ bool opts_ok(const smsq_svgd_opts_t *o)
 {
     return o && o->n_iter >= 0 && std::isfinite(o->step) && finite_pos(o->bw_scale) &&
            (o->bw_mode == 0 || o->bw_mode == 1) && (o->trans_mode == 0 || o->trans_mode == 1) &&
-           o->kernel >= SMSQ_KERNEL_RBF && o->kernel <= SMSQ_KERNEL_MATERN32 && (o->weights == 0 || o->weights == 1);
+           o->kernel >= SMSQ_KERNEL_RBF && o->kernel <= SMSQ_KERNEL_MATERN32 && (o->weights == 0 || o->weights == 1) &&
+           o->step_kernel >= SMSQ_STEP_AUTO && o->step_kernel <= SMSQ_STEP_MFMA;
 }
 
 uint32_t *status_ptr(void *ws) { return reinterpret_cast<uint32_t *>(ws); }
@@ -436,7 +436,7 @@ smsq_status_t step_typed(const smsq_model_desc_t &d, int batch, int t, int n_pre
     a.bw_scale = (T)(opts ? opts->bw_scale : 1.0);
     a.tie_tol = (T)tie_tol;
     a.seed = seed; a.seq_offset = seq_offset;
-    return launch_step<T>(d, a, batch, s);
+    return launch_step<T>(d, a, batch, opts ? opts->step_kernel : SMSQ_STEP_AUTO, s);
 }
 
 smsq_status_t step_dispatch(smsq_dtype_t dt, const smsq_model_desc_t &d, int batch, int t, int n_prev,
@@ -692,6 +692,51 @@ namespace {
 
 bool batch_family(int kind) { return kind >= SMSQ_MODEL_GROWTH1D && kind <= SMSQ_MODEL_ARM7; }
 
+// Algorithm 2 for `batch` sequences in the scratch memory `ws` (ws_bytes
+// bytes, laid out by run_layout): the body of smsq_run_batch, shared with the
+// entry point that runs in the library's own device array.
+smsq_status_t run_batch_ws(smsq_model_t model, smsq_dtype_t dtype, int batch, int T, int n, const void *x0,
+                           const void *z, const uint8_t *z_mask, uint64_t seed, const smsq_svgd_opts_t *opts,
+                           void *xmap_out, void *logpost_out, void *particles_out, void *ws, size_t ws_bytes,
+                           hipStream_t stream)
+{
+    if (!model || !dtype_ok(dtype) || batch < 1 || T < 1 || n < 1 || !x0 || !z || !opts_ok(opts) || !xmap_out ||
+        !logpost_out)
+        return SMSQ_ERR_INVALID;
+    const smsq_model_desc_t &d = model->desc;
+    const RunLayout L = run_layout(dtype, batch, T, n, d.d);
+    if (!ws || ws_bytes < L.total) return SMSQ_ERR_WORKSPACE;
+    if (!step_shape_ok(dtype, n, n, d.d) || !step_shape_ok(dtype, n, 1, d.d)) return SMSQ_ERR_UNSUPPORTED;
+    char *w = (char *)ws;
+    const size_t es = elem_size(dtype);
+    char *parts = particles_out ? (char *)particles_out : w + L.parts;
+    int32_t *psi = (int32_t *)(w + L.psi);
+    char *phi_buf[2] = {w + L.phi, w + L.phi + (size_t)batch * n * es};
+    int32_t *idx = (int32_t *)(w + L.idx);
+    const long seq_stride = (long)T * n * d.d;
+    const long step_stride = (long)n * d.d;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, status_ptr(ws), 0u, 1);
+    if (hipGetLastError() != hipSuccess) return SMSQ_ERR_HIP;
+    for (int t = 1; t <= T; ++t) {
+        const void *xp = t == 1 ? x0 : (const void *)(parts + (size_t)(t - 2) * step_stride * es);
+        const long xp_stride = t == 1 ? (long)d.d : seq_stride;
+        const void *phip = t == 1 ? nullptr : (const void *)phi_buf[(t - 1) & 1];
+        const int np = t == 1 ? 1 : n;
+        const void *zt = (const char *)z + (size_t)(t - 1) * d.obs_dim * es;
+        const uint8_t *mt = z_mask ? z_mask + (size_t)(t - 1) * d.n_obs : nullptr;
+        void *xt = parts + (size_t)(t - 1) * step_stride * es;
+        const smsq_status_t st = step_dispatch(
+            dtype, d, batch, t, np, xp, xp_stride, nullptr, 0, phip, np, zt, (long)T * d.obs_dim, mt,
+            (long)T * d.n_obs, n, xt, seq_stride, 0, seed, 0, opts, true, true, phi_buf[t & 1], n,
+            psi + (size_t)(t - 1) * n, (long)T * n, nullptr, 0, 0.0, nullptr, 0, ws, stream);
+        if (st != SMSQ_OK) return st;
+    }
+    return smsq_backtrack(dtype, batch, T, n, d.d, psi, phi_buf[T & 1], idx, logpost_out, parts, x0, xmap_out, ws,
+                          ws_bytes, stream);
+}
+
+
+
 } // namespace
 
 extern "C" {
@@ -834,39 +879,8 @@ smsq_status_t smsq_run_batch(smsq_model_t model, smsq_dtype_t dtype, int batch, 
                              void *xmap_out, void *logpost_out, void *particles_out, void *ws, size_t ws_bytes,
                              hipStream_t stream)
 {
-    if (!model || !dtype_ok(dtype) || batch < 1 || T < 1 || n < 1 || !x0 || !z || !opts_ok(opts) || !xmap_out ||
-        !logpost_out)
-        return SMSQ_ERR_INVALID;
-    const smsq_model_desc_t &d = model->desc;
-    const RunLayout L = run_layout(dtype, batch, T, n, d.d);
-    if (!ws || ws_bytes < L.total) return SMSQ_ERR_WORKSPACE;
-    if (!step_shape_ok(dtype, n, n, d.d) || !step_shape_ok(dtype, n, 1, d.d)) return SMSQ_ERR_UNSUPPORTED;
-    char *w = (char *)ws;
-    const size_t es = elem_size(dtype);
-    char *parts = particles_out ? (char *)particles_out : w + L.parts;
-    int32_t *psi = (int32_t *)(w + L.psi);
-    char *phi_buf[2] = {w + L.phi, w + L.phi + (size_t)batch * n * es};
-    int32_t *idx = (int32_t *)(w + L.idx);
-    const long seq_stride = (long)T * n * d.d;
-    const long step_stride = (long)n * d.d;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, status_ptr(ws), 0u, 1);
-    if (hipGetLastError() != hipSuccess) return SMSQ_ERR_HIP;
-    for (int t = 1; t <= T; ++t) {
-        const void *xp = t == 1 ? x0 : (const void *)(parts + (size_t)(t - 2) * step_stride * es);
-        const long xp_stride = t == 1 ? (long)d.d : seq_stride;
-        const void *phip = t == 1 ? nullptr : (const void *)phi_buf[(t - 1) & 1];
-        const int np = t == 1 ? 1 : n;
-        const void *zt = (const char *)z + (size_t)(t - 1) * d.obs_dim * es;
-        const uint8_t *mt = z_mask ? z_mask + (size_t)(t - 1) * d.n_obs : nullptr;
-        void *xt = parts + (size_t)(t - 1) * step_stride * es;
-        const smsq_status_t st = step_dispatch(
-            dtype, d, batch, t, np, xp, xp_stride, nullptr, 0, phip, np, zt, (long)T * d.obs_dim, mt,
-            (long)T * d.n_obs, n, xt, seq_stride, 0, seed, 0, opts, true, true, phi_buf[t & 1], n,
-            psi + (size_t)(t - 1) * n, (long)T * n, nullptr, 0, 0.0, nullptr, 0, ws, stream);
-        if (st != SMSQ_OK) return st;
-    }
-    return smsq_backtrack(dtype, batch, T, n, d.d, psi, phi_buf[T & 1], idx, logpost_out, parts, x0, xmap_out, ws,
-                          ws_bytes, stream);
+    return run_batch_ws(model, dtype, batch, T, n, x0, z, z_mask, seed, opts, xmap_out, logpost_out, particles_out,
+                        ws, ws_bytes, stream);
 }
 
 smsq_status_t smsq_run_sequence(smsq_model_t model, smsq_dtype_t dtype, int T, int n, const void *x0,
@@ -901,7 +915,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     *out = nullptr;
     if (!models || !opts || n_models < 1 || !seqs || count < 1) return SMSQ_ERR_INVALID;
     for (int k = 0; k < n_models; ++k) {
-        if (!models[k] || !opts_ok(&opts[k])) return SMSQ_ERR_INVALID;
+        if (!models[k] || !opts_ok(&opts[k]) || opts[k].step_kernel != SMSQ_STEP_AUTO) return SMSQ_ERR_INVALID;
         if (opts[k].kernel != SMSQ_KERNEL_RBF) return SMSQ_ERR_UNSUPPORTED;  // the plan's step body is RBF
     }
     long lds = 0;

@@ -13,9 +13,11 @@
 //   [4]      ln(n) / 7
 //   [5..11]  (mean_j M_j - a) / s
 //   [12..18] ln(var_j M_j / s^2 + 1e-6) / 8
-//   [19..25] a * family scale
-//   [26..32] asinh(s * grad_x log p(z_t | a)) / 4
-//   [33]     asinh(log p(z_t | a)) / 8
+//   [19..25] asinh(s * grad_x log p(z_t | a)) / 4
+//   [26]     asinh(log p(z_t | a)) / 8
+//   [27..63] zero
+// (entries k >= d of each per-dimension block are zero).  No feature holds
+// the absolute position: the mixture is placed relative to a.
 // Outputs (120 = 8 x 15): component c has logit o[15c], mean offsets
 // o[15c + 1 + k] and log-scales o[15c + 8 + k]: mean a + s mu, standard
 // deviation s exp(clamp(rho, -7, 3)) per dimension k < d.

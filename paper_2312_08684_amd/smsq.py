@@ -64,10 +64,12 @@ class InitExample(C.Structure):
 
 class SvgdOpts(C.Structure):
     _fields_ = [("n_iter", C.c_int), ("step", C.c_double), ("bw_scale", C.c_double),
-                ("bw_mode", C.c_int), ("trans_mode", C.c_int), ("kernel", C.c_int), ("weights", C.c_int)]
+                ("bw_mode", C.c_int), ("trans_mode", C.c_int), ("kernel", C.c_int), ("weights", C.c_int),
+                ("step_kernel", C.c_int)]
 
 
 KERNELS = {"rbf": 0, "imq": 1, "matern32": 2}
+STEP_KERNELS = {"auto": 0, "wave": 1, "valu": 2, "mfma": 3}
 
 
 _lib = None
@@ -172,16 +174,19 @@ def _stream(stream=None) -> int:
 
 
 def opts(n_iter: int, step: float, bw_scale: float = 1.0, bw_mode: int = 0,
-         trans_mode: int = 0, kernel=0, weights: int = 0) -> SvgdOpts:
+         trans_mode: int = 0, kernel=0, weights: int = 0, step_kernel=0) -> SvgdOpts:
     """SVGD options; kernel: 0/"rbf", 1/"imq", 2/"matern32"; weights 1: mixture
-    weights from the previous step's forward-recursion scores (in the drivers)."""
+    weights from the previous step's forward-recursion scores (in the drivers);
+    step_kernel: 0/"auto", 1/"wave", 2/"valu", 3/"mfma" (forces a step kernel
+    wherever the shape fits it)."""
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-    return SvgdOpts(int(n_iter), float(step), float(bw_scale), int(bw_mode), int(trans_mode), k, int(weights))
+    sk = STEP_KERNELS[step_kernel] if isinstance(step_kernel, str) else int(step_kernel)
+    return SvgdOpts(int(n_iter), float(step), float(bw_scale), int(bw_mode), int(trans_mode), k, int(weights), sk)
 
 
-def opts_from(o) -> SvgdOpts:
+def opts_from(o, step_kernel=0) -> SvgdOpts:
     return opts(o.n_iter, o.step, o.bw_scale, o.bw_mode, o.trans_mode, getattr(o, "kernel", 0),
-                getattr(o, "weights", 0))
+                getattr(o, "weights", 0), step_kernel)
 
 
 class Model:

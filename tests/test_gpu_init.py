@@ -200,3 +200,45 @@ def test_parameters_save_and_load(tmp_path):
     assert torch.equal(a.forward(F), b.forward(F))
     a.close()
     b.close()
+
+
+def test_adam_update_matches_oracle():
+    """Two training steps: the parameter update of each against the oracle's
+    Adam step (Kingma & Ba, Algorithm 1) for the gradient the step computed
+    (read back from the network's gradient buffer), with the moments carried
+    from the first step into the second.  The constants are the ones the
+    kernel holds in FP32 (beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f, lr as a
+    float).  Bound per element: half an FP32 ulp of the new parameter plus
+    1e-5 of the update (FP32 moments, square root and division); a dropped
+    bias correction or eps inside the square root moves the update by a
+    factor, far outside it."""
+    exs, models = [], []
+    for i, (name, n) in enumerate([("arm7", 128), ("range2d", 100), ("growth1d", 32)]):
+        wl, model, ex = _examples(name, n, seed=40 + i, T=5)
+        models.append(model)
+        exs += [dict(q, model=i) for q in ex]
+    iset = smsq.InitSet(models, exs)
+    rng = np.random.default_rng(21)
+    P0 = rng.normal(scale=0.05, size=M.N_PARAMS).astype(np.float32)
+    mlp = _mlp_with(P0.astype(np.float64))
+    f32 = lambda v: float(np.float32(v))
+    lr = 3e-3
+    cst = dict(lr=f32(lr), b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+    m = v = np.zeros(M.N_PARAMS)
+    P = P0.astype(np.float64)
+    for step in (1, 2):
+        mlp.train_step(iset, 0, len(exs), lr)
+        torch.cuda.synchronize()
+        Pg = mlp.params().cpu().numpy().astype(np.float64)
+        G = mlp.grads().cpu().numpy().astype(np.float64)
+        Po, m, v = M.adam_step(P, G, m, v, step, **cst)
+        upd = np.abs(Po - P)
+        bound = np.abs(Po) * 2.0 ** -24 + 1e-5 * upd + 1e-30
+        err = np.abs(Pg - Po)
+        small = np.sqrt(v / (1 - cst["b2"] ** step)) < 10 * cst["eps"]
+        print("adam step %d: max err/bound %.3f, max |update| %.3e, %d of %d elements with sqrt(v_hat) < 10 eps"
+              % (step, (err / bound).max(), upd.max(), int((small & (G != 0)).sum()), M.N_PARAMS))
+        assert np.all(err <= bound), (step, int(np.argmax(err / bound)))
+        assert upd.max() > 1e-4
+        P = Pg
+    mlp.close()

@@ -5,7 +5,10 @@ Tolerances (stated per result):
   * backtracking: bit-exact indices and score;
   * SVGD step, teacher-forced (same previous and initial particles on both
     sides): ||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-4 in FP32 and
-    <= 1e-10 in FP64, after the full iteration count;
+    <= 1e-10 in FP64, after the full iteration count; the same difference
+    over the oracle's move ||X_oracle - X_init||_F <= 1e-3 (FP32) and
+    <= 1e-9 (FP64), and per moving particle <= 1e-2 (FP32) and <= 1e-8
+    (FP64);
   * trajectory log-posterior J: |dJ| <= 1e-3 max(|J|, T).
 The FP32-vs-FP64 errors measured here are printed with each case.
 """
@@ -24,6 +27,8 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 TOL_X = {"f32": 1e-4, "f64": 1e-10}
 TOL_H = {"f32": 1e-5, "f64": 1e-12}
+TOL_DISP = {"f32": 1e-3, "f64": 1e-9}
+TOL_DISP_PARTICLE = {"f32": 1e-2, "f64": 1e-8}
 TOL_J = 1e-3
 TIE_F32 = 2.0 ** -20
 
@@ -282,7 +287,22 @@ def _svgd_case(name, n, n_prev, seed, dt):
     return wl, desc, xp, x, z, mask
 
 
-def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mode=0, trans_mode=0, kernel=0):
+def _move_errors(xg, xo, x0):
+    """Errors of the move rather than the position: ||X_gpu - X_ora||_F over
+    the oracle's displacement ||X_ora - X_init||_F, and the largest
+    per-particle ratio |x_gpu,i - x_ora,i| / |x_ora,i - x_init,i| over the
+    particles that move at least a tenth of the root-mean-square move."""
+    dg = np.linalg.norm(xg - xo, axis=1)
+    dm = np.linalg.norm(xo - x0, axis=1)
+    rel_disp = np.linalg.norm(dg) / max(np.linalg.norm(dm), 1e-300)
+    rms = np.sqrt(np.mean(dm ** 2))
+    moving = dm >= 0.1 * rms
+    pp = float((dg[moving] / dm[moving]).max()) if rms > 0 and moving.any() else 0.0
+    return rel_disp, pp
+
+
+def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mode=0, trans_mode=0, kernel=0,
+                  step_kernel="auto"):
     td = tdt(dt)
     xo, ho, st = O.svgd_step(desc, 2, xp, log_w, z, mask, x, L, step, bw_scale, bw_mode, trans_mode, kernel)
     assert st == O.OK
@@ -292,15 +312,19 @@ def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mod
     ws = smsq.workspace()
     smsq.svgd_step(model, dt, 2, dev(xp, td), None if log_w is None else dev(log_w, td), dev(z, td),
                    None if mask is None else dev(mask, torch.uint8), xg,
-                   smsq.opts(L, step, bw_scale, bw_mode, trans_mode, kernel), h_out=hg, ws=ws)
+                   smsq.opts(L, step, bw_scale, bw_mode, trans_mode, kernel, step_kernel=step_kernel), h_out=hg,
+                   ws=ws)
     assert smsq.device_status(ws) == smsq.OK
     xg, hg = host(xg).astype(np.float64), host(hg).astype(np.float64)[:L]
     rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    disp = np.linalg.norm(xo - x)
-    rel_disp = np.linalg.norm(xg - xo) / max(disp, 1e-300)
+    rel_disp, pp = _move_errors(xg, xo, x)
     herr = np.abs(hg - ho).max() / np.abs(ho).max() if L else 0.0
-    print("rel X err %.3e  rel displacement err %.3e  rel h err %.3e" % (rel, rel_disp, herr))
+    print("rel X err %.3e  rel displacement err %.3e (worst moving particle %.3e)  rel h err %.3e"
+          % (rel, rel_disp, pp, herr))
     assert rel <= TOL_X[dt]
+    if L:
+        assert rel_disp <= TOL_DISP[dt]
+        assert pp <= TOL_DISP_PARTICLE[dt]
     assert herr <= TOL_H[dt]
     return xo, xg
 
@@ -332,12 +356,12 @@ def test_svgd_step_teacher_forced(name, n, n_prev, L, step, dt):
 
 
 @pytest.mark.parametrize("name,n,n_prev,L,step", SVGD_CASES)
-def test_svgd_step_vector_alu_kernel(name, n, n_prev, L, step, monkeypatch):
+def test_svgd_step_vector_alu_kernel(name, n, n_prev, L, step):
     """The FP32 vector-ALU step kernel (selected instead of the matrix-core one)."""
     announce("svgd step valu", name, n, n_prev, L)
-    monkeypatch.setenv("SMSQ_STEP_KERNEL", "valu")
+    sk = "valu"
     wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 22, "f32")
-    _compare_svgd(desc, "f32", xp, None, z, mask, x, L, step)
+    _compare_svgd(desc, "f32", xp, None, z, mask, x, L, step, step_kernel=sk)
 
 
 @pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "one_particle",
@@ -394,24 +418,24 @@ WAVE_CASES = [
 
 
 @pytest.mark.parametrize("name,n,n_prev,L,step,dt", WAVE_CASES)
-def test_svgd_step_one_wave_kernel(name, n, n_prev, L, step, dt, monkeypatch):
+def test_svgd_step_one_wave_kernel(name, n, n_prev, L, step, dt):
     """The one-wave kernel (particles in lane registers, readlane broadcasts)
     on every family, from one particle to 64, against the oracle; the pair
     counts span every register blocking of the median's selection (1, 2, 4,
     8, 16 and 32 distances per lane)."""
     announce("svgd step wave", name, n, n_prev, L, dt)
-    monkeypatch.setenv("SMSQ_STEP_KERNEL", "wave")
+    sk = "wave"
     wl, desc, xp, x, z, mask = _svgd_case(name, n, n_prev, 24, dt)
-    _compare_svgd(desc, dt, xp, None, z, mask, x, L, step)
+    _compare_svgd(desc, dt, xp, None, z, mask, x, L, step, step_kernel=sk)
 
 
 @pytest.mark.parametrize("variant", ["weights", "mean_reading", "per_step_bw", "bw3", "imq", "matern32",
                                      "ties_2x5", "ties_4x4", "ties_2x10", "ties_8x8"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_svgd_step_one_wave_variants(variant, dt, monkeypatch):
+def test_svgd_step_one_wave_variants(variant, dt):
     """Options and exact ties on the one-wave kernel (range-only model)."""
     announce("svgd wave variant", variant, dt)
-    monkeypatch.setenv("SMSQ_STEP_KERNEL", "wave")
+    sk = "wave"
     n, n_prev = 48, 40
     if variant.startswith("ties_"):
         groups, copies = (int(v) for v in variant[5:].split("x"))
@@ -433,34 +457,35 @@ def test_svgd_step_one_wave_variants(variant, dt, monkeypatch):
         bw_scale = 3.0
     if variant in ("imq", "matern32"):
         kernel = smsq.KERNELS[variant]
-    _compare_svgd(desc, dt, xp, log_w, z, mask, x, 15, 0.005, bw_scale, bw_mode, trans_mode, kernel)
+    _compare_svgd(desc, dt, xp, log_w, z, mask, x, 15, 0.005, bw_scale, bw_mode, trans_mode, kernel,
+                  step_kernel=sk)
 
 
 @pytest.mark.parametrize("variant", ["ties_16x16", "ties_4x64", "ties_2x10"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_svgd_step_ties_vector_alu(variant, dt, monkeypatch):
+def test_svgd_step_ties_vector_alu(variant, dt):
     """The vector-ALU kernel's median under exact ties: copies of a few
     distinct particles put hundreds or thousands of equal distances at the
     median, so the window gathers them all or overflows (radix fallback);
     ties_2x10 (20 particles) takes the all-pairs path with 90 zero
     distances below the median's rank."""
     announce("svgd ties valu", variant, dt)
-    monkeypatch.setenv("SMSQ_STEP_KERNEL", "valu")
+    sk = "valu"
     groups, copies = (int(v) for v in variant[5:].split("x"))
     wl, desc, xp, x, z, mask = _svgd_case("range2d", groups * copies, 50, 5, dt)
     x = np.repeat(x[:groups], copies, axis=0)
-    _compare_svgd(desc, dt, xp, None, z, mask, x, 6, 0.005)
+    _compare_svgd(desc, dt, xp, None, z, mask, x, 6, 0.005, step_kernel=sk)
 
 
 @pytest.mark.parametrize("n,n_prev", [(1, 50), (2, 50), (20, 20), (31, 7), (32, 32)])
-def test_svgd_step_small_n_matrix_core(n, n_prev, monkeypatch):
+def test_svgd_step_small_n_matrix_core(n, n_prev):
     """Up to 32 particles single steps take the one-wave kernel (or the
     vector-ALU kernel); batched plans still run the matrix-core kernel
     there, forced here."""
     announce("svgd step small n mfma", n, n_prev)
-    monkeypatch.setenv("SMSQ_STEP_KERNEL", "mfma")
+    sk = "mfma"
     wl, desc, xp, x, z, mask = _svgd_case("range2d", n, n_prev, 23, "f32")
-    _compare_svgd(desc, "f32", xp, None, z, mask, x, 40, 0.005)
+    _compare_svgd(desc, "f32", xp, None, z, mask, x, 40, 0.005, step_kernel=sk)
 
 
 KERNEL_CASES = [
@@ -723,8 +748,12 @@ def test_run_batch_full_arm7_sampled_step():
     x_init = O.predictive_init(desc, t, xprev, n, 31, b)
     xo, _, st = O.svgd_step(desc, t, xprev, None, wl.z[b, t - 1], None, x_init, o.n_iter, o.step)
     rel = np.linalg.norm(parts[b, t - 1] - xo) / np.linalg.norm(xo)
-    print("sampled step t=%d rel X err %.3e" % (t, rel))
+    rel_disp, pp = _move_errors(parts[b, t - 1], xo, x_init)
+    print("sampled step t=%d rel X err %.3e  rel displacement err %.3e (worst moving particle %.3e)"
+          % (t, rel, rel_disp, pp))
     assert rel <= TOL_X["f32"]
+    assert rel_disp <= TOL_DISP["f32"]
+    assert pp <= TOL_DISP_PARTICLE["f32"]
 
 
 # ---------------------------------------------------------------------------

@@ -5,6 +5,8 @@ forward pass, the mixture NLL gradient against finite differences of the
 NLL, the NLL of a mixture of identical components against scipy's normal
 log-density, the bfloat16 rounding against hand-worked ties, and the
 features of a set of identical particles against their closed form."""
+import os
+
 import numpy as np
 import pytest
 from scipy import stats
@@ -128,3 +130,82 @@ def test_features_do_not_depend_on_position():
     F2, a2, _ = M.features(desc, 2, x + np.array([30.0, -12.0]), phi, wl.z[0, 1], mask, 64)
     assert not np.allclose(a1, a2)
     assert np.allclose(F1, F2, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Mixture moments and the Adam update
+# ---------------------------------------------------------------------------
+
+def _two_component_out(w, mu, sd):
+    """Outputs whose mixture (a = 0, s = 1, d = 1) has components with
+    weights w, means mu and standard deviations sd; the other six components
+    get a logit of -1e30 (weight exactly zero)."""
+    out = np.zeros(M.OUT)
+    for c in range(M.K):
+        out[c * M.COMP] = -1e30
+    for c, (wc, mc, sc) in enumerate(zip(w, mu, sd)):
+        out[c * M.COMP] = np.log(wc)
+        out[c * M.COMP + 1] = mc
+        out[c * M.COMP + 8] = np.log(sc)
+    return out
+
+
+def test_mixture_moments_two_components_by_hand():
+    """Weights (1/4, 3/4), means (-1, 3), standard deviations (1/2, 2):
+    mean = -1/4 + 9/4 = 2; E[x^2] = 1/4 (1/4 + 1) + 3/4 (4 + 9) = 161/16, so
+    the variance is 161/16 - 4 = 97/16 (law of total variance: the mean of
+    the component variances 13/16 plus the variance of the means 3)."""
+    out = _two_component_out([0.25, 0.75], [-1.0, 3.0], [0.5, 2.0])
+    a, s = np.zeros(8), np.ones(8)
+    m, v = M.mixture_moments(out, a, s, 1)
+    assert m[0] == pytest.approx(2.0, abs=1e-14)
+    assert v[0] == pytest.approx(97.0 / 16.0, abs=1e-13)
+
+
+def test_mixture_moments_follow_anchor_and_scale():
+    """Mean a + s mu and variance s^2 sigma^2 per dimension: the same two
+    components placed at a = 5 with scale s = 3 (d = 2, second dimension a
+    single point mass at the anchor's offset 0 with log-scale -7 clamped)."""
+    out = _two_component_out([0.25, 0.75], [-1.0, 3.0], [0.5, 2.0])
+    for c in range(2):
+        out[c * M.COMP + 2] = 0.0
+        out[c * M.COMP + 9] = -20.0       # clamped to -7
+    a = np.array([5.0, -1.0, 0, 0, 0, 0, 0, 0])
+    s = np.array([3.0, 0.5, 1, 1, 1, 1, 1, 1])
+    m, v = M.mixture_moments(out, a, s, 2)
+    assert m == pytest.approx([5.0 + 3.0 * 2.0, -1.0], abs=1e-13)
+    assert v == pytest.approx([9.0 * 97.0 / 16.0, 0.25 * np.exp(-14.0)], rel=1e-12)
+
+
+def _golden_adam():
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "adam_two_step.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    return np.array(rows)
+
+
+def test_adam_two_steps_by_hand():
+    g = _golden_adam()
+    P0, g1, g2, P1_ref, P2_ref = g.T
+    zero = np.zeros_like(P0)
+    P1, m1, v1 = M.adam_step(P0, g1, zero, zero, 1, 0.1)
+    P2, _, _ = M.adam_step(P1, g2, m1, v1, 2, 0.1)
+    assert np.allclose(P1, P1_ref, rtol=1e-14, atol=1e-15)
+    assert np.allclose(P2, P2_ref, rtol=1e-13, atol=1e-15)
+
+
+def test_adam_first_step_and_constant_gradient_closed_form():
+    """With m_0 = v_0 = 0 the bias correction makes the first step
+    -lr g / (|g| + eps) for any beta1, beta2; a gradient that stays constant
+    keeps m_hat = g and v_hat = g^2 at every step, so every step is the same."""
+    rng = np.random.default_rng(4)
+    P = rng.normal(size=50)
+    g = rng.normal(size=50) * np.logspace(-9, 1, 50)
+    m = v = np.zeros(50)
+    want = -0.01 * g / (np.abs(g) + 1e-8)
+    for t in range(1, 6):
+        Pn, m, v = M.adam_step(P, g, m, v, t, 0.01, b1=0.8, b2=0.99)
+        assert np.allclose(Pn - P, want, rtol=1e-9, atol=1e-18), t
+        P = Pn

@@ -794,3 +794,26 @@ def test_run_sequence_bookkeeping_and_determinism():
     mean1 = O.transition_mean(desc, 1, wl.x0[0])
     want0 = mean1 + math.sqrt(desc.q_var[0]) * O.normals(99, 0, 1, 0, 1)
     assert np.array_equal(x_init[0], want0)
+
+
+@pytest.mark.parametrize("name,n_prev,n", [("range2d", 5, 12), ("arm7", 7, 7), ("cv4d", 3, 2),
+                                           ("growth1d", 4, 9)])
+def test_predictive_init_ancestor_rule(name, n_prev, n):
+    """Predictive initial particles with several previous particles: particle
+    i starts at f_t(x_{t-1}^{i mod N_p}) plus sqrt(q) times its Philox normals
+    (counter (i, t, seq)), so subtracting the noise leaves exactly the
+    transition mean of ancestor i mod N_p (each ancestor's mean is distinct)."""
+    wl = S.make_workload(name, B=1, seed=6, T=4)
+    desc = wl.model
+    d = desc.d
+    rng = np.random.default_rng(17)
+    x_prev = wl.truth[0, 2] + rng.normal(size=(n_prev, d))
+    t, seed, seq = 3, 12345, 4
+    x = O.predictive_init(desc, t, x_prev, n, seed, seq)
+    sq = np.sqrt(np.asarray(desc.q_var[:d]))
+    means = np.stack([O.transition_mean(desc, t, v) for v in x_prev])
+    for i in range(n):
+        base = x[i] - sq * O.normals(seed, seq, t, i, d)
+        assert np.allclose(base, means[i % n_prev], rtol=1e-12, atol=1e-12), i
+        others = [j for j in range(n_prev) if j != i % n_prev]
+        assert all(not np.allclose(base, means[j], rtol=1e-6, atol=1e-6) for j in others)

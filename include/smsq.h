@@ -285,6 +285,29 @@ smsq_status_t smsq_run_sequence(smsq_model_t model, smsq_dtype_t dtype, int T, i
                                 void *xmap_out, void *logpost_out, void *particles_out,
                                 void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* smsq_run_sequence for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but the run's scratch memory
+ * (status word, the particles of every step when particles_out is NULL, the
+ * back-pointers and the ping-pong scores) lives in one 16 MiB array of the
+ * library's own device memory on each GPU, held until the process ends.  The
+ * call allocates and frees nothing; no workspace argument.
+ *  status_out  [1] int32 (device) or NULL: receives SMSQ_OK or
+ *              SMSQ_ERR_NONFINITE for this run once the stream reaches it
+ *              (the status word is cleared at the start of every run)
+ * Sizes: 256 + a(T n d e) + a(4 T n) + a(2 n e) + a(4 T) bytes must not
+ * exceed 16 MiB, with e the element size and a() rounding up to 256 bytes
+ * (e.g. T n = 500,000 particle-steps of a 7-D FP32 state), else
+ * SMSQ_ERR_WORKSPACE is returned and nothing is enqueued.  Every call on one
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and give undefined results; calls ordered on
+ * one stream are safe. */
+smsq_status_t smsq_run_sequence_noalloc(smsq_model_t model, smsq_dtype_t dtype, int T, int n,
+                                        const void *x0, const void *z, const uint8_t *z_mask,
+                                        uint64_t seed, const smsq_svgd_opts_t *opts /* host */,
+                                        void *xmap_out, void *logpost_out, void *particles_out,
+                                        int32_t *status_out, hipStream_t stream);
+
 /* ---- Batched ragged form ------------------------------------------------
  * Thousands of independent sequences of different model family, particle
  * count n and length T run Algorithm 2 together: every time step t is one

@@ -739,6 +739,44 @@ smsq_status_t run_batch_ws(smsq_model_t model, smsq_dtype_t dtype, int batch, in
 
 } // namespace
 
+// ---- allocation-free Algorithm 2 ------------------------------------------
+// Device memory of smsq_run_sequence_noalloc: one array on every GPU the
+// library runs on, held until the process ends.  On the host the array's
+// name denotes a host-side stand-in, not a device address; host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+smsq_status_t scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SMSQ_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SMSQ_ERR_HIP;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return SMSQ_OK;
+}
+
+// The run's device status word as a status code for the caller.
+__global__ void k_status_out(const uint32_t *__restrict__ word, int32_t *__restrict__ out)
+{
+    if (threadIdx.x == 0) out[0] = (word[0] & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 smsq_status_t smsq_model_create(const smsq_model_desc_t *desc, smsq_model_t *out)
@@ -890,6 +928,23 @@ smsq_status_t smsq_run_sequence(smsq_model_t model, smsq_dtype_t dtype, int T, i
 {
     return smsq_run_batch(model, dtype, 1, T, n, x0, z, z_mask, seed, opts, xmap_out, logpost_out, particles_out,
                           ws, ws_bytes, stream);
+}
+
+smsq_status_t smsq_run_sequence_noalloc(smsq_model_t model, smsq_dtype_t dtype, int T, int n, const void *x0,
+                                        const void *z, const uint8_t *z_mask, uint64_t seed,
+                                        const smsq_svgd_opts_t *opts, void *xmap_out, void *logpost_out,
+                                        void *particles_out, int32_t *status_out, hipStream_t stream)
+{
+    if (!model || !dtype_ok(dtype) || T < 1 || n < 1) return SMSQ_ERR_INVALID;
+    if (run_layout(dtype, 1, T, n, model->desc.d).total > kNoallocBytes) return SMSQ_ERR_WORKSPACE;
+    void *ws = nullptr;
+    smsq_status_t st = scratch_address(&ws);
+    if (st != SMSQ_OK) return st;
+    st = run_batch_ws(model, dtype, 1, T, n, x0, z, z_mask, seed, opts, xmap_out, logpost_out, particles_out, ws,
+                      kNoallocBytes, stream);
+    if (st != SMSQ_OK || !status_out) return st;
+    hipLaunchKernelGGL(k_status_out, dim3(1), dim3(kWave), 0, stream, (const uint32_t *)ws, status_out);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
 
 smsq_status_t smsq_get_device_status(const void *ws, smsq_status_t *out)

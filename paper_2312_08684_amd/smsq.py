@@ -30,7 +30,7 @@ SYMBOLS = [
     "smsq_init_mlp_create", "smsq_init_mlp_destroy", "smsq_init_mlp_params", "smsq_init_mlp_sync",
     "smsq_init_set_create", "smsq_init_set_destroy", "smsq_init_features", "smsq_init_mlp_forward",
     "smsq_init_mlp_backward", "smsq_init_mixture_nll", "smsq_init_mlp_train_step", "smsq_init_mlp_sample",
-    "smsq_batch_plan_set_init",
+    "smsq_batch_plan_set_init", "smsq_run_sequence_noalloc",
 ]
 
 
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH):
     L.smsq_init_mlp_train_step.argtypes = [vp, vp, i32, i32, dbl, vp, vp]
     L.smsq_init_mlp_sample.argtypes = [vp, vp, i32, i32, vp, vp]
     L.smsq_batch_plan_set_init.argtypes = [vp, vp]
+    L.smsq_run_sequence_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, vp, u64, C.POINTER(SvgdOpts), vp, vp,
+                                            vp, vp, vp]
     for name in SYMBOLS:
         fn = getattr(L, name)
         if fn.restype is None or fn.restype is C.c_int:
@@ -407,6 +409,27 @@ def run_sequence(model: Model, dtype, x0: torch.Tensor, z: torch.Tensor, z_mask:
                                   ws.numel(), _stream(stream))
     _check(st, "smsq_run_sequence")
     return xmap, J
+
+
+def run_sequence_noalloc(model: Model, dtype, x0: torch.Tensor, z: torch.Tensor, z_mask: Optional[torch.Tensor],
+                         n: int, o: SvgdOpts, seed: int, *, particles: Optional[torch.Tensor] = None,
+                         stream=None):
+    """Algorithm 2 for one sequence in the library's own device memory
+    (smsq_run_sequence_noalloc: no workspace, nothing allocated by the call).
+    Returns (xmap [T+1, d], J [1], status [1] int32)."""
+    td = torch_dtype(dtype)
+    T = z.shape[0]
+    d = x0.shape[0]
+    dev = x0.device
+    xmap = torch.empty((T + 1, d), dtype=td, device=dev)
+    J = torch.empty(1, dtype=td, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    st = load().smsq_run_sequence_noalloc(model.handle, _dt(dtype), T, n, _ptr(x0, td, "x0"), _ptr(z, td, "z"),
+                                          _ptr(z_mask, torch.uint8, "z_mask"), int(seed), C.byref(o), _ptr(xmap),
+                                          _ptr(J), _ptr(particles, td, "particles"), _ptr(status),
+                                          _stream(stream))
+    _check(st, "smsq_run_sequence_noalloc")
+    return xmap, J, status
 
 
 class BatchPlan:

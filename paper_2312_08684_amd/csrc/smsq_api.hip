@@ -1377,8 +1377,12 @@ smsq_status_t smsq_init_mlp_train_step(smsq_init_mlp_t m, smsq_init_set_t st, in
                        m->lossv, 1.f / (float)count);
     mlp_backward(m, count, s);
     m->adam_t += 1;
+    // Adam constants as FP32 values; their bias corrections in FP64
+    const float b1 = 0.9f, b2 = 0.999f;
+    const double c1 = 1.0 / (1.0 - std::pow((double)b1, m->adam_t));
+    const double c2 = 1.0 / (1.0 - std::pow((double)b2, m->adam_t));
     hipLaunchKernelGGL(k_adam, dim3((kInitParams + 255) / 256), dim3(256), 0, s, m->P, m->G, m->Mo, m->Ve,
-                       kInitParams, (float)lr, 0.9f, 0.999f, 1e-8f, m->adam_t, m->w1b, m->w2b, m->w3b);
+                       kInitParams, (float)lr, b1, b2, 1e-8f, (float)c1, (float)c2, m->w1b, m->w2b, m->w3b);
     if (loss_out) hipLaunchKernelGGL(k_mean_f32, dim3(1), dim3(kWave), 0, s, m->lossv, count, (float *)loss_out);
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }

@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--scenario-b-mc", type=int, default=10, help="pose-scenario sequences per row (0: skip)")
     p.add_argument("--scenario-d-mc", type=int, default=20, help="14-D arm sequences per row (0: skip)")
     p.add_argument("--pf-map-seq", type=int, default=1, help="PF-MAP-Seq forward-recursion workload (0: skip)")
+    p.add_argument("--cpu-table", action="store_true",
+                   help="only the CPU oracle table (single thread and all-core, four workloads)")
     p.add_argument("--sweep", action="store_true",
                    help="print the batch / N / workload sweeps as one JSON line instead of the benchmark")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -112,8 +114,32 @@ def measured_traffic(name: str, B: int, n: int, dt: str):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_threads() -> int:
+    """Host threads for the all-core oracle: the CPU share the process is
+    given (OMP_NUM_THREADS), at most the visible cores."""
+    n = os.cpu_count() or 1
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
 def cpu_baseline(name: str):
-    """The FP64 oracle, single thread, on one time step of one sequence."""
+    """The FP64 oracle on one time step (t = 2) of one sequence of the
+    workload: single thread, then all-core (OpenMP over particles; the same
+    bits).  `value` is the all-core rate."""
     import oracle as O
     from paper_2312_08684_amd import scenarios as S
     wl = S.make_workload(name, B=1, seed=0, T=2)
@@ -122,14 +148,53 @@ def cpu_baseline(name: str):
     sd = np.sqrt(desc.q_var[:desc.d])
     xprev = wl.truth[0, 1][None, :] + sd * rng.normal(size=(n, desc.d))
     x_init = O.predictive_init(desc, 2, xprev, n, 1, 0)
-    t0 = time.perf_counter()
-    x, _, _ = O.svgd_step(desc, 2, xprev, None, wl.z[0, 1], None, x_init, o.n_iter, o.step)
-    O.viterbi_particle(desc, 2, xprev, np.zeros(n), wl.z[0, 1], None, x)
-    dt = time.perf_counter() - t0
-    return {"value": n * o.n_iter / dt, "unit": "particle-iters/s", "cores": 1, "kind": "oracle",
-            "sample": "one time step (t=2) of one %s sequence: N=%d, d=%d, %d SVGD iterations + "
-                      "forward recursion, FP64 oracle, single thread, %.1f s" % (name, n, desc.d, o.n_iter, dt),
-            "host_cpus": os.cpu_count(), "cpu_model": platform.processor() or platform.machine()}
+    mask = None if wl.mask is None else wl.mask[0, 1]
+    res, secs = {}, {}
+    cores = cpu_threads()
+    for th in (1, cores):
+        O.set_threads(th)
+        t0 = time.perf_counter()
+        x, _, _ = O.svgd_step(desc, 2, xprev, None, wl.z[0, 1], mask, x_init, o.n_iter, o.step)
+        O.viterbi_particle(desc, 2, xprev, np.zeros(n), wl.z[0, 1], mask, x)
+        secs[th] = time.perf_counter() - t0
+        res[th] = x
+    same = bool(np.array_equal(res[1], res[cores]))
+    return {"value": n * o.n_iter / secs[cores], "unit": "particle-iters/s", "cores": cores, "kind": "oracle",
+            "sample": "one time step (t=2) of one %s sequence: N=%d, d=%d, %d SVGD iterations + forward "
+                      "recursion, FP64 oracle; %d threads (OpenMP over particles) %.2f s, one thread %.2f s; "
+                      "results bit-identical: %s" % (name, n, desc.d, o.n_iter, cores, secs[cores], secs[1], same),
+            "single_thread": {"value": n * o.n_iter / secs[1], "seconds": secs[1]},
+            "all_core_seconds": secs[cores], "bit_identical": same,
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+# steps timed per workload in the CPU table (the 7-DOF arm truncated to 5)
+CPU_TABLE_STEPS = {"growth1d": 50, "range2d": 20, "cv4d": 10, "arm7": 5}
+
+
+def cpu_table():
+    """Algorithm 2 in the FP64 oracle on the first steps of one sequence of
+    each workload, single thread and all-core: ms per step, particle-iters/s."""
+    import oracle as O
+    from paper_2312_08684_amd import scenarios as S
+    rows = []
+    cores = cpu_threads()
+    for name, k in CPU_TABLE_STEPS.items():
+        wl = S.make_workload(name, B=1, seed=0)
+        T = min(k, wl.T)
+        mask = None if wl.mask is None else wl.mask[0][:T]
+        row = {"workload": name, "N": wl.n, "d": wl.model.d, "L": wl.opts.n_iter, "steps": T}
+        for th, key in ((1, "single"), (cores, "all_core")):
+            O.set_threads(th)
+            t0 = time.perf_counter()
+            r = O.run_sequence(wl.model, T, wl.n, wl.x0[0], wl.z[0][:T], mask, 1, 0, wl.opts.n_iter, wl.opts.step)
+            dt = time.perf_counter() - t0
+            row[key] = {"ms_per_step": dt / T * 1e3, "particle_iters_per_s": wl.n * wl.opts.n_iter * T / dt,
+                        "J": r["J"]}
+        row["bit_identical"] = row["single"]["J"] == row["all_core"]["J"]
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    return {"cores": cores, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "rows": rows}
 
 
 def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
@@ -584,6 +649,9 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
 
 def main():
     args = parse()
+    if args.cpu_table:
+        print(json.dumps(cpu_table()), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(sequences shard across GPUs with no exchange; see the design notes)", file=sys.stderr)

@@ -39,7 +39,7 @@ def build(force: bool = False) -> str:
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -58,6 +58,8 @@ def lib():
             L = C.CDLL(build())
             M = C.POINTER(OrModel)
             L.or_philox4x32_10.argtypes = [_u32, _u32, _u32]
+            L.or_set_threads.argtypes = [C.c_int]
+            L.or_get_threads.restype = C.c_int
             L.or_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, _dp]
             L.or_transition_mean.argtypes = [M, C.c_int, _dp, _dp]
             L.or_log_transition.argtypes = [M, _dp, _dp]
@@ -118,6 +120,16 @@ def _maskptr(mask):
         return None, None
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     return m, m.ctypes.data
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's particle loops and median sort (results do
+    not depend on it)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 # -- primitives ------------------------------------------------------------------

@@ -10,8 +10,12 @@
  * generator, median, score, Stein update, forward recursion and backtracking
  * are all written out here on their own.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so that every
- * floating-point operation is a single IEEE double operation in source order.
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared -fopenmp (no fast-math), so
+ * that every floating-point operation is a single IEEE double operation in
+ * source order.  OpenMP splits only the loops over particles (each particle's
+ * sums keep their order) and the sort of the median (a sorted array is the
+ * same however it is sorted), so any thread count gives bit-identical
+ * results; or_set_threads picks the count.
  *
  * Section / equation map (paper numbering):
  *   models           Sec. II, eq. (SSM); scenario models of Sec. V (the
@@ -42,6 +46,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAXD 16
 
@@ -421,11 +428,66 @@ static int cmp_double(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
+/* Threads of the particle loops and the sort (1 = serial). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int or_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Ascending sort of v[0..M): with several threads, equal chunks are sorted
+ * by qsort at once and then merged pairwise, level by level. */
+static void sort_doubles(double *v, long M)
+{
+    int P = or_get_threads();
+    if (P <= 1 || M < 4096) {
+        qsort(v, (size_t)M, sizeof(double), cmp_double);
+        return;
+    }
+    long chunk = (M + P - 1) / P;
+    int nchunks = (int)((M + chunk - 1) / chunk);
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < nchunks; ++c) {
+        long lo = c * chunk, hi = lo + chunk < M ? lo + chunk : M;
+        qsort(v + lo, (size_t)(hi - lo), sizeof(double), cmp_double);
+    }
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)M);
+    double *src = v, *dst = tmp;
+    for (long width = chunk; width < M; width *= 2) {
+        long pairs = (M + 2 * width - 1) / (2 * width);
+#pragma omp parallel for schedule(static)
+        for (long q = 0; q < pairs; ++q) {
+            long lo = q * 2 * width;
+            long mid = lo + width < M ? lo + width : M;
+            long hi = lo + 2 * width < M ? lo + 2 * width : M;
+            long a = lo, b = mid, o = lo;
+            while (a < mid && b < hi) dst[o++] = (src[b] < src[a]) ? src[b++] : src[a++];
+            while (a < mid) dst[o++] = src[a++];
+            while (b < hi) dst[o++] = src[b++];
+        }
+        double *t = src; src = dst; dst = t;
+    }
+    if (src != v) memcpy(v, src, sizeof(double) * (size_t)M);
+    free(tmp);
+}
+
 /* Sorts v in place and returns element floor((M-1)/2). */
 double or_lower_median(double *v, long M)
 {
     if (M <= 0) return NAN;
-    qsort(v, (size_t)M, sizeof(double), cmp_double);
+    sort_doubles(v, M);
     return v[(M - 1) / 2];
 }
 
@@ -444,9 +506,12 @@ double or_bandwidth(const double *x, int n, int d, double bw_scale, double *med_
     long M = (long)n * (long)(n - 1) / 2;
     if (M > 0) {
         double *v = (double *)malloc(sizeof(double) * (size_t)M);
-        long q = 0;
-        for (int i = 0; i < n; ++i)
+        /* pair (i, k), i < k, at position i n - i (i + 1) / 2 + k - i - 1 */
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int i = 0; i < n; ++i) {
+            long q = (long)i * n - (long)i * (i + 1) / 2;
             for (int k = i + 1; k < n; ++k) v[q++] = or_sqdist(x + (size_t)i * d, x + (size_t)k * d, d);
+        }
         med = or_lower_median(v, M);
         free(v);
     }
@@ -466,11 +531,14 @@ void or_scores(const or_model *m, int n_prev, const double *means, const double 
                int trans_mode, double *s)
 {
     int d = m->d;
-    double *a = (double *)malloc(sizeof(double) * (size_t)(n_prev > 0 ? n_prev : 1));
     double mean_all[OR_MAXD] = { 0 };
     for (int j = 0; j < n_prev; ++j)
         for (int c = 0; c < d; ++c) mean_all[c] += means[(size_t)j * d + c];
     for (int c = 0; c < d; ++c) mean_all[c] /= (double)n_prev;
+#pragma omp parallel
+    {
+    double *a = (double *)malloc(sizeof(double) * (size_t)(n_prev > 0 ? n_prev : 1));
+#pragma omp for schedule(static)
     for (int k = 0; k < n; ++k) {
         const double *xk = x + (size_t)k * d;
         double g[OR_MAXD], mbar[OR_MAXD];
@@ -497,6 +565,7 @@ void or_scores(const or_model *m, int n_prev, const double *means, const double 
             s[(size_t)k * d + c] = g[c] - (xk[c] - mbar[c]) / m->q_var[c];
     }
     free(a);
+    }
 }
 
 /* Kernels of the Stein direction, functions f(D) of the squared distance
@@ -535,6 +604,7 @@ void or_kernel(int kernel, double D, double h, double *f, double *w)
  * kappa_ik = f(|x_i - x_k|^2), grad_{x_k} kappa_ik = w_ik (x_i - x_k). */
 void or_stein_phi(int n, int d, const double *x, const double *s, double h, int kernel, double *phi)
 {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         const double *xi = x + (size_t)i * d;
         double acc[OR_MAXD] = { 0 };
@@ -637,10 +707,13 @@ int or_viterbi_particle(const or_model *m, int t, int n_prev, const double *x_pr
     if (n <= 0 || n_prev <= 0) return OR_INVALID;
     int d = m->d;
     double *means = (double *)malloc(sizeof(double) * (size_t)n_prev * d);
-    double *c = (double *)malloc(sizeof(double) * (size_t)n_prev);
     for (int j = 0; j < n_prev; ++j)
         or_transition_mean(m, t, x_prev + (size_t)j * d, means + (size_t)j * d);
     int bad = 0;
+#pragma omp parallel reduction(|:bad)
+    {
+    double *c = (double *)malloc(sizeof(double) * (size_t)n_prev);
+#pragma omp for schedule(static)
     for (int i = 0; i < n; ++i) {
         const double *xi = x + (size_t)i * d;
         for (int j = 0; j < n_prev; ++j)
@@ -648,7 +721,9 @@ int or_viterbi_particle(const or_model *m, int t, int n_prev, const double *x_pr
         double ell = or_loglik(m, z, mask, xi);
         bad |= forward_row(n_prev, c, ell, tie_tol, phi + i, psi + i, flags ? flags + i : NULL);
     }
-    free(means); free(c);
+    free(c);
+    }
+    free(means);
     return bad ? OR_NONFINITE : OR_OK;
 }
 

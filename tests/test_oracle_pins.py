@@ -817,3 +817,30 @@ def test_predictive_init_ancestor_rule(name, n_prev, n):
         assert np.allclose(base, means[i % n_prev], rtol=1e-12, atol=1e-12), i
         others = [j for j in range(n_prev) if j != i % n_prev]
         assert all(not np.allclose(base, means[j], rtol=1e-6, atol=1e-6) for j in others)
+
+
+def test_oracle_threads_give_bit_identical_results():
+    """The oracle's OpenMP loops split particles (each keeps its own sum
+    order) and its median sort (chunks sorted, then merged): one thread and
+    several give the same bits.  400 particles put 79,800 pair distances in
+    the sort, above its threshold for the chunked path."""
+    wl = S.make_workload("range2d", B=1, seed=8, T=3, n=400, n_iter=4)
+    desc = wl.model
+    out = {}
+    for th in (1, 3, 8):
+        O.set_threads(th)
+        out[th] = O.run_sequence(desc, wl.T, wl.n, wl.x0[0], wl.z[0], wl.mask[0], 5, 0, 4, 0.005,
+                                 want_tables=True)
+    O.set_threads(os.cpu_count() or 1)
+    for th in (3, 8):
+        for key in ("xmap", "particles", "phi", "psi", "idx"):
+            assert np.array_equal(out[1][key], out[th][key]), (th, key)
+        assert out[1]["J"] == out[th]["J"]
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=100_003) ** 2
+    O.set_threads(5)
+    m5 = O.lower_median(v)
+    O.set_threads(1)
+    m1 = O.lower_median(v)
+    O.set_threads(os.cpu_count() or 1)
+    assert m1 == m5 == np.sort(v)[(v.size - 1) // 2]

@@ -26,16 +26,9 @@ import torch
 from . import scenarios as S
 from . import smsq
 
-FAMILIES = ("growth1d", "range2d", "cv4d", "arm7")
-PARTICLES = (32, 128, 256, 512, 1024)
-
-
-def mix(count: int, seed: int, T_lo: int, T_hi: int, n_choices: Sequence[int] = PARTICLES,
-        families: Sequence[str] = FAMILIES) -> List[Tuple[str, int, int, int]]:
-    """(family, n, T, data seed) of `count` sequences drawn uniformly."""
-    rng = np.random.default_rng(seed)
-    return [(families[int(rng.integers(0, len(families)))], int(rng.choice(n_choices)),
-             int(rng.integers(T_lo, T_hi + 1)), int(seed) * 100000 + i) for i in range(count)]
+FAMILIES = S.MIX_FAMILIES
+PARTICLES = S.MIX_PARTICLES
+mix = S.mix
 
 
 class Mix:

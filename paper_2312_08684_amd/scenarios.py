@@ -459,6 +459,22 @@ def make_workload(name: str, *, B: int = 1, seed: int = 0, n: Optional[int] = No
                     truth, dt)
 
 
+# The ragged mix of the batched form: families with their own preset
+# iteration counts and step sizes, particle counts and lengths drawn
+# uniformly per sequence.
+MIX_FAMILIES = ("growth1d", "range2d", "cv4d", "arm7")
+MIX_PARTICLES = (32, 128, 256, 512, 1024)
+
+
+def mix(count: int, seed: int, T_lo: int, T_hi: int, n_choices=MIX_PARTICLES,
+        families=MIX_FAMILIES):
+    """(family, n, T, data seed) of `count` sequences drawn uniformly; the
+    sequence's Philox key is its data seed + 7."""
+    rng = np.random.default_rng(seed)
+    return [(families[int(rng.integers(0, len(families)))], int(rng.choice(n_choices)),
+             int(rng.integers(T_lo, T_hi + 1)), int(seed) * 100000 + i) for i in range(count)]
+
+
 def random_particles(rng: np.random.Generator, n: int, d: int, center=None,
                      scale=1.0) -> np.ndarray:
     c = np.zeros(d) if center is None else np.asarray(center)

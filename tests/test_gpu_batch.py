@@ -179,14 +179,24 @@ def test_batch_plan_argument_errors():
 def test_full_ragged_mix_sampled_sequences():
     """The batched plan at the benchmark's full size: 4096 sequences of the
     four families (N in {32, ..., 1024}, T in [50, 200], full iteration
-    counts) in one plan with graph replay.  Sampled sequences, the largest N
-    of each family, reach the J of the standalone Algorithm 2 on the same
-    inputs (itself tested against the oracle) within 1e-3 max(|J|, T), and
-    every sampled J is the path score of the plan's own MAP trajectory
-    (evaluated in FP64 by the oracle).  Over hundreds of steps the two FP32
-    kernels may part on near-ties, so the paths themselves are not compared."""
+    counts) in one plan with graph replay.  One sequence per family (the
+    largest N, then the smallest T) against the CPU FP64 oracle's results on
+    the same inputs and Philox key (fixtures tests/golden/mix_*.npz, written
+    by tests/golden/make_fullsize_fixtures.py):
+      * the plan's J within 1e-3 max(|J|, T) of the oracle's J, and equal
+        to the path score of the plan's own MAP trajectory (FP64, oracle);
+      * teacher-forced through the plan: the plan's particles of step
+        t_s - 1, the predictive initial particles of step t_s regenerated by
+        the oracle from the plan's Philox key, one oracle SVGD step, against
+        the plan's particles of step t_s (1e-4 of the positions; the move
+        as parity_bounds.py states);
+      * the plan's J within 1e-3 max(|J|, T) of the standalone Algorithm 2
+        on the same inputs.
+    FP32-vs-FP64 differences are printed per family."""
     import oracle as O
     from paper_2312_08684_amd import learned as LI
+    from parity_bounds import check_move
+    from test_gpu_fullsize import load_fixture
     spec = LI.mix(4096, seed=11, T_lo=50, T_hi=200)
     mx = LI.Mix(spec)
     plan, J, _, models, seqs = LI.run(mx, 1.0, warm=False)
@@ -195,16 +205,37 @@ def test_full_ragged_mix_sampled_sequences():
     assert np.all(np.isfinite(Jn))
     _, opts, _ = LI.build(mx, 1.0)
     for fam in ("growth1d", "range2d", "cv4d", "arm7"):
-        idx = [i for i, s in enumerate(spec) if s[0] == fam]
-        i = max(idx, key=lambda k: (spec[k][1], -k))
-        _, n, T, _ = spec[i]
-        q = seqs[i]
-        xmap, Js = smsq.run_sequence(models[i], "f32", q["x0"], q["z"], q["z_mask"], n, opts[i], q["seed"])
-        Jp = float(plan.J[i].item())
-        Js = float(Js.cpu()[0])
+        fx = load_fixture("mix_" + fam)
+        i = int(fx["mix_index"])
+        _, n, T, sd = spec[i]
+        assert (n, T, sd + 7) == (int(fx["n"]), int(fx["T"]), int(fx["key"]))
         wl = mx.wls[i]
+        assert np.array_equal(wl.z[0], fx["z"]) and np.array_equal(wl.x0[0], fx["x0"])
         mask = None if wl.mask is None else wl.mask[0]
-        Jpath = O.path_score(wl.model, plan.xmap[i].cpu().double().numpy(), wl.z[0], mask)
-        print("%s n=%d T=%d: plan J %.4f single J %.4f path score %.4f" % (fam, n, T, Jp, Js, Jpath), flush=True)
-        assert abs(Jp - Js) <= 1e-3 * max(abs(Js), T)
+        Jp = float(plan.J[i].item())
+        Jo = float(fx["J"])
+        xp = plan.xmap[i].cpu().double().numpy()
+        Jpath = O.path_score(wl.model, xp, wl.z[0], mask)
+        print("%s n=%d T=%d: plan J %.4f oracle J %.4f (rel %.3e, FP32 vs FP64), path score %.4f, "
+              "trajectory max |dx| %.3e" % (fam, n, T, Jp, Jo, abs(Jp - Jo) / max(abs(Jo), T), Jpath,
+                                            np.abs(xp - fx["xmap"]).max()), flush=True)
+        assert abs(Jp - Jo) <= 1e-3 * max(abs(Jo), T)
         assert abs(Jpath - Jp) <= 1e-3 * max(abs(Jp), T)
+        # teacher-forced step t_s through the plan's storage
+        ts = int(fx["t_sample"])
+        parts, _, _ = plan.storage(i)
+        parts = parts.cpu().double().numpy()
+        x_init = O.predictive_init(wl.model, ts, parts[ts - 2], n, sd + 7, 0)
+        L, eps = opts[i].n_iter, opts[i].step
+        xo, _, st = O.svgd_step(wl.model, ts, parts[ts - 2], None, wl.z[0][ts - 1],
+                                None if mask is None else mask[ts - 1], x_init, L, eps)
+        assert st == O.OK
+        rel = np.linalg.norm(parts[ts - 1] - xo) / np.linalg.norm(xo)
+        print("  teacher-forced plan step t=%d: rel X err %.3e" % (ts, rel), flush=True)
+        assert rel <= 1e-4
+        print("  " + check_move(parts[ts - 1], xo, x_init, L, "f32"), flush=True)
+        # and the standalone path on the same inputs
+        q = seqs[i]
+        _, Js = smsq.run_sequence(models[i], "f32", q["x0"], q["z"], q["z_mask"], n, opts[i], q["seed"])
+        Js = float(Js.cpu()[0])
+        assert abs(Jp - Js) <= 1e-3 * max(abs(Js), T)

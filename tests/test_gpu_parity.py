@@ -6,9 +6,8 @@ Tolerances (stated per result):
   * SVGD step, teacher-forced (same previous and initial particles on both
     sides): ||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-4 in FP32 and
     <= 1e-10 in FP64, after the full iteration count; the same difference
-    over the oracle's move ||X_oracle - X_init||_F <= 1e-3 (FP32) and
-    <= 1e-9 (FP64), and per moving particle <= 1e-2 (FP32) and <= 1e-8
-    (FP64);
+    against the oracle's move ||X_oracle - X_init||_F (bounds and their
+    FP32 rounding floor in parity_bounds.py);
   * trajectory log-posterior J: |dJ| <= 1e-3 max(|J|, T).
 The FP32-vs-FP64 errors measured here are printed with each case.
 """
@@ -21,14 +20,13 @@ import torch
 import oracle as O
 from paper_2312_08684_amd import scenarios as S
 from paper_2312_08684_amd import smsq
+from parity_bounds import check_move
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 TOL_X = {"f32": 1e-4, "f64": 1e-10}
 TOL_H = {"f32": 1e-5, "f64": 1e-12}
-TOL_DISP = {"f32": 1e-3, "f64": 1e-9}
-TOL_DISP_PARTICLE = {"f32": 1e-2, "f64": 1e-8}
 TOL_J = 1e-3
 TIE_F32 = 2.0 ** -20
 
@@ -287,20 +285,6 @@ def _svgd_case(name, n, n_prev, seed, dt):
     return wl, desc, xp, x, z, mask
 
 
-def _move_errors(xg, xo, x0):
-    """Errors of the move rather than the position: ||X_gpu - X_ora||_F over
-    the oracle's displacement ||X_ora - X_init||_F, and the largest
-    per-particle ratio |x_gpu,i - x_ora,i| / |x_ora,i - x_init,i| over the
-    particles that move at least a tenth of the root-mean-square move."""
-    dg = np.linalg.norm(xg - xo, axis=1)
-    dm = np.linalg.norm(xo - x0, axis=1)
-    rel_disp = np.linalg.norm(dg) / max(np.linalg.norm(dm), 1e-300)
-    rms = np.sqrt(np.mean(dm ** 2))
-    moving = dm >= 0.1 * rms
-    pp = float((dg[moving] / dm[moving]).max()) if rms > 0 and moving.any() else 0.0
-    return rel_disp, pp
-
-
 def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mode=0, trans_mode=0, kernel=0,
                   step_kernel="auto"):
     td = tdt(dt)
@@ -317,14 +301,10 @@ def _compare_svgd(desc, dt, xp, log_w, z, mask, x, L, step, bw_scale=1.0, bw_mod
     assert smsq.device_status(ws) == smsq.OK
     xg, hg = host(xg).astype(np.float64), host(hg).astype(np.float64)[:L]
     rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    rel_disp, pp = _move_errors(xg, xo, x)
     herr = np.abs(hg - ho).max() / np.abs(ho).max() if L else 0.0
-    print("rel X err %.3e  rel displacement err %.3e (worst moving particle %.3e)  rel h err %.3e"
-          % (rel, rel_disp, pp, herr))
+    print("rel X err %.3e  rel h err %.3e" % (rel, herr))
     assert rel <= TOL_X[dt]
-    if L:
-        assert rel_disp <= TOL_DISP[dt]
-        assert pp <= TOL_DISP_PARTICLE[dt]
+    print(check_move(xg, xo, x, L, dt))
     assert herr <= TOL_H[dt]
     return xo, xg
 
@@ -748,12 +728,9 @@ def test_run_batch_full_arm7_sampled_step():
     x_init = O.predictive_init(desc, t, xprev, n, 31, b)
     xo, _, st = O.svgd_step(desc, t, xprev, None, wl.z[b, t - 1], None, x_init, o.n_iter, o.step)
     rel = np.linalg.norm(parts[b, t - 1] - xo) / np.linalg.norm(xo)
-    rel_disp, pp = _move_errors(parts[b, t - 1], xo, x_init)
-    print("sampled step t=%d rel X err %.3e  rel displacement err %.3e (worst moving particle %.3e)"
-          % (t, rel, rel_disp, pp))
+    print("sampled step t=%d rel X err %.3e" % (t, rel))
     assert rel <= TOL_X["f32"]
-    assert rel_disp <= TOL_DISP["f32"]
-    assert pp <= TOL_DISP_PARTICLE["f32"]
+    print(check_move(parts[b, t - 1], xo, x_init, o.n_iter, "f32"))
 
 
 # ---------------------------------------------------------------------------

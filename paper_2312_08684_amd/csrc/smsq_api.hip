@@ -194,10 +194,10 @@ bool use_mfma(int n, int n_prev, int step_kernel)
     return fits && n >= kMfmaMinParticles;
 }
 
-template <int KIND, int D>
-smsq_status_t launch_mfma_kd(const StepArgs<float> &a, int batch, hipStream_t s)
+template <int KIND, int D, bool SPLIT>
+smsq_status_t launch_mfma_split(const StepArgs<float> &a, int batch, hipStream_t s)
 {
-    auto fn = &k_step_mfma<KIND, D>;
+    auto fn = &k_step_mfma<KIND, D, SPLIT>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] { attr_err = allow_big_lds(fn); });
@@ -205,6 +205,15 @@ smsq_status_t launch_mfma_kd(const StepArgs<float> &a, int batch, hipStream_t s)
     const MfmaLds L(a.n, a.n_prev);
     hipLaunchKernelGGL(fn, dim3(batch), dim3(L.nwaves * kWave), (size_t)L.total, s, a);
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+// Fewer 64-particle tasks than 16 waves: the split instantiation fills the
+// workgroup with waves that share each task's sources.
+template <int KIND, int D>
+smsq_status_t launch_mfma_kd(const StepArgs<float> &a, int batch, hipStream_t s)
+{
+    return MfmaLds(a.n, a.n_prev).ns_max > 1 ? launch_mfma_split<KIND, D, true>(a, batch, s)
+                                              : launch_mfma_split<KIND, D, false>(a, batch, s);
 }
 
 template <typename T, int KIND, int D>

@@ -92,11 +92,16 @@ __device__ __forceinline__ void batch_step_loop(const StepArgs<float> *__restric
         __syncthreads();
         if (k >= count) break;
         const StepArgs<float> &a = items[k];
-        switch (codes[k]) {
-        case GROWTH1D: step_mfma_body<GROWTH1D, 1, TS>(a, 0); break;
-        case RANGE2D: step_mfma_body<RANGE2D, 2, TS>(a, 0); break;
-        case CV4D: step_mfma_body<CV4D, 4, TS>(a, 0); break;
-        default: step_mfma_body<ARM7, 7, TS>(a, 0); break;
+        const bool split = MfmaLds(a.n, a.n_prev, (int)(blockDim.x >> 6)).ns_max > 1;
+        switch (codes[k] + (split ? kBatchFamilies : 0)) {
+        case GROWTH1D: step_mfma_body<GROWTH1D, 1, TS, false>(a, 0); break;
+        case RANGE2D: step_mfma_body<RANGE2D, 2, TS, false>(a, 0); break;
+        case CV4D: step_mfma_body<CV4D, 4, TS, false>(a, 0); break;
+        case ARM7: step_mfma_body<ARM7, 7, TS, false>(a, 0); break;
+        case kBatchFamilies + GROWTH1D: step_mfma_body<GROWTH1D, 1, TS, true>(a, 0); break;
+        case kBatchFamilies + RANGE2D: step_mfma_body<RANGE2D, 2, TS, true>(a, 0); break;
+        case kBatchFamilies + CV4D: step_mfma_body<CV4D, 4, TS, true>(a, 0); break;
+        default: step_mfma_body<ARM7, 7, TS, true>(a, 0); break;
         }
         __syncthreads();  // LDS is reused by the next item
     }

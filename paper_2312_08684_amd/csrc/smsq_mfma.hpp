@@ -83,16 +83,34 @@ constexpr int kWinRegion = kWinCap / kMaxWaves; // per-wave share of the window 
 constexpr int kWinTarget = 512;   // aimed-for number of distances in the window
 constexpr float kRescaleGap = 8.f; // log2 headroom before the softmax reference moves
 constexpr int kProgSlot = 48;      // first of the 16 wave-progress words in the reduction slots
+constexpr int kPartStride = 9;     // floats per particle in a split's partial sums (8 rows + 1)
 
-// LDS byte layout of the MFMA step workgroup.
+// LDS byte layout of the MFMA step workgroup, and how its waves share the
+// pairwise work.  With fewer 64-particle tasks than waves (N below 1024 for
+// 16 waves) the source tiles of each task are split among several waves
+// ("splits"): a wave handles task w % ntasks over the split w / ntasks of
+// the source range, leaves partial sums in LDS, and the partials are merged
+// in split order (the same result whatever the timing).  ns_sc / ns_st are
+// the splits of the score and Stein passes (at most the source tiles each
+// pass has); nwaves the waves a launch of this shape uses.
 struct MfmaLds {
-    long off_x, off_s, off_m, off_phip, off_scr, off_win, off_z, off_mask, off_red, total;
-    int npad, nppad, nwaves;
-    __host__ __device__ MfmaLds(int n, int n_prev)
+    long off_x, off_s, off_m, off_phip, off_scr, off_win, off_z, off_mask, off_red, off_part, total;
+    int npad, nppad, nwaves, ntasks, ns_sc, ns_st, ns_max;
+    __host__ __device__ MfmaLds(int n, int n_prev, int waves = kMaxWaves)
     {
         npad = (n + 63) / 64 * 64;
         nppad = (n_prev + 15) / 16 * 16;
-        nwaves = npad / 64 < kMaxWaves ? npad / 64 : kMaxWaves;
+        ntasks = npad / 64;
+        if (ntasks >= waves) {
+            ns_sc = ns_st = ns_max = 1;
+            nwaves = waves;
+        } else {
+            const int cap = waves / ntasks;
+            ns_sc = cap < nppad / 16 ? cap : nppad / 16;
+            ns_st = cap < npad / 16 ? cap : npad / 16;
+            ns_max = ns_sc > ns_st ? ns_sc : ns_st;
+            nwaves = ntasks * ns_max;
+        }
         long o = 0;
         off_x = o; o += align16((long)npad * 8 * 4);
         off_s = o; o += align16((long)npad * 8 * 4);
@@ -103,6 +121,8 @@ struct MfmaLds {
         off_z = o; o += align16((long)kMaxObs * 4);
         off_mask = o; o += 64;
         off_red = o; o += 512;  // uint slots 0..63 (48..63: wave progress), float slots from byte 256
+        // partial sums of the splits: [ns_max][npad][9] floats
+        off_part = o; o += ns_max > 1 ? align16((long)ns_max * npad * kPartStride * 4) : 0;
         total = o;
     }
 };
@@ -582,7 +602,10 @@ __device__ __forceinline__ float sum_quarters_scatter(float v0, float v1, float 
     return __uint_as_float(c[0]) + __uint_as_float(c[1]);
 }
 
-template <int KIND, int D, int TS>
+// SPLIT: the layout splits the sources of each task among waves (MfmaLds
+// ns_max > 1); a separate instantiation, so the unsplit path keeps its
+// registers.
+template <int KIND, int D, int TS, bool SPLIT>
 __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const int b)
 {
     using F = Family<float, KIND, D>;
@@ -590,8 +613,10 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     static_assert(D <= 7, "K-column 7 carries the norms");
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = a.n, np = a.n_prev;
-    const MfmaLds L(n, np);
+    const MfmaLds L(n, np, (int)(blockDim.x >> 6));
     const int npad = L.npad, nppad = L.nppad;
+    constexpr bool split = SPLIT;               // sources of a task split among waves (L.ns_max > 1)
+    float *PART = (float *)(smem + L.off_part); // [ns_max][npad][kPartStride] partial sums of the splits
     float *X8 = (float *)(smem + L.off_x);     // [npad][8]  centred particles, |x|^2 in column 7 (pad: 0.., +inf)
     float *S8 = (float *)(smem + L.off_s);     // [npad][8]  scores
     float *VT = (float *)(smem + L.off_m);     // [9][nppad] rows 2 mh_c (c < 7; 0 for c >= d), 1, c'_j
@@ -750,10 +775,11 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         };
 
         // (2) scores
-        for (int task = wave; task < ntasks; task += nwaves) {
-            const int kbase = task * 64;
-            float osum[8];  // trans_mode 0: sum_j e_kj [2 mh_j, 1] of this lane's particle kbase + lane
-            if (a.trans_mode == 0) {
+        // score_sums: osum = sum_j e_kj [2 mh_j, 1] over the source tiles
+        // [j0, j1) for this lane's particle kbase + lane, relative to the
+        // reference sref (e_kj = exp2(logit_kj - sref))
+        auto score_sums = [&](int kbase, int j0, int j1, float (&osum)[8], float &sref) {
+            {
                 f32x4 cm[kTilesPerWave];  // -reference of each particle column, as the accumulator input
                 float bx0[kTilesPerWave], bx1[kTilesPerWave];
 #pragma unroll
@@ -855,10 +881,10 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                     if (WALK) {
                         // one buffer: the walk's registers leave no room for two
                         f32x4 T[kTilesPerWave];
-                        logits(0, T);
+                        logits(j0, T);
                         rebase(T, true);
-                        body(0, T);
-                        for (int jt = 1; jt < njt; ++jt) {
+                        body(j0, T);
+                        for (int jt = j0 + 1; jt < j1; ++jt) {
                             if ((jt & 1) == 0) bal.step();
                             logits(jt, T);
                             rebase(T, false);
@@ -868,17 +894,17 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         // the logits of tile jt + 1 are issued (and checked)
                         // around the exponentials and sums of tile jt
                         auto tile = [&](int jt, f32x4 (&T)[kTilesPerWave], f32x4 (&Tn)[kTilesPerWave]) {
-                            logits(min(jt + 1, njt - 1), Tn);
+                            logits(min(jt + 1, j1 - 1), Tn);
                             body(jt, T);
                             rebase(Tn, false);
                         };
                         f32x4 TA[kTilesPerWave], TB[kTilesPerWave];
-                        logits(0, TA);
+                        logits(j0, TA);
                         rebase(TA, true);
-                        for (int jt = 0; jt < njt; jt += 2) {
+                        for (int jt = j0; jt < j1; jt += 2) {
                             bal.step();
                             tile(jt, TA, TB);
-                            if (jt + 1 < njt) tile(jt + 1, TB, TA);
+                            if (jt + 1 < j1) tile(jt + 1, TB, TA);
                         }
                     }
                 };
@@ -887,12 +913,39 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 else
                     score_loop(std::false_type{});
                 // lane l takes particle kbase + l: tile q = l / 16, summed
-                // over the four source quarters
+                // over the four source quarters; its reference is the one of
+                // column l % 16 of tile q, which lane l holds
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     osum[i] = sum_quarters_scatter(O4[0][0][i], O4[0][1][i], O4[0][2][i], O4[0][3][i]);
                     osum[4 + i] = sum_quarters_scatter(O4[1][0][i], O4[1][1][i], O4[1][2][i], O4[1][3][i]);
                 }
+                const int qq = lane >> 4;
+                float cref = cm[0][0];
+#pragma unroll
+                for (int q = 1; q < kTilesPerWave; ++q) cref = qq == q ? cm[q][0] : cref;
+                sref = -cref;
+            }
+        };
+        if (split) {
+            // this wave's split of its task's sources: partial sums to LDS,
+            // merged per particle once h is known
+            if (a.trans_mode == 0 && wave < ntasks * L.ns_sc) {
+                const int task = wave % ntasks, sp = wave / ntasks;
+                float osum[8], sref;
+                score_sums(task * 64, sp * njt / L.ns_sc, (sp + 1) * njt / L.ns_sc, osum, sref);
+                float *pp = PART + ((long)sp * npad + task * 64 + lane) * kPartStride;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) pp[c] = osum[c];
+                pp[8] = sref;
+            }
+        }
+        for (int task = wave; !split && task < ntasks; task += nwaves) {
+            const int kbase = task * 64;
+            float osum[8];  // trans_mode 0: sum_j e_kj [2 mh_j, 1] of this lane's particle kbase + lane
+            if (a.trans_mode == 0) {
+                float sref;
+                score_sums(kbase, 0, njt, osum, sref);
             }
             {
                 const int k = kbase + lane;
@@ -951,15 +1004,61 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         constexpr int NG = D <= 3 ? 1 : 2;       // row groups of four in the sums
         constexpr int kOne = NG == 1 ? 3 : 7;    // row that sums kappa
         for (int k = tid; k < npad; k += nt) {
+            if (split) {
+                // the score row of particle k from the splits' partial sums
+                // (rebased to their largest reference, summed in split order)
+                float srow[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) srow[c] = 0.f;
+                srow[7] = 1.f;
+                if (k < n) {
+                    float xt[D], xa[D], gr[D];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        xt[c] = X8[(long)k * 8 + c];
+                        xa[c] = xt[c] + ref[c];
+                    }
+                    F::grad(m, sz, mk, xa, gr);
+                    if (a.trans_mode == 0) {
+                        float mx = -inf;
+                        for (int sp = 0; sp < L.ns_sc; ++sp)
+                            mx = fmax_(mx, PART[((long)sp * npad + k) * kPartStride + 8]);
+                        float os[8];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) os[c] = 0.f;
+                        for (int sp = 0; sp < L.ns_sc; ++sp) {
+                            const float *pp = PART + ((long)sp * npad + k) * kPartStride;
+                            const float w = R::exp2_(pp[8] - mx);
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) os[c] += pp[c] * w;
+                        }
+                        const float inv_sum = 1.f / os[7];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            const float mb = os[c] * inv_sum * 0.5f / rs[c];
+                            srow[c] = gr[c] - (xt[c] - mb) * m.inv_q[c];
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) srow[c] = gr[c] - (xt[c] - mbar_all[c]) * m.inv_q[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) S8[(long)k * 8 + c] = srow[c];
+            }
 #pragma unroll
             for (int c = 0; c < D; ++c) S8[(long)k * 8 + c] -= c2 * X8[(long)k * 8 + c];
             if (kOne != 7) S8[(long)k * 8 + kOne] = 1.f;
         }
         __syncthreads();
         float phi[TS][kTilesPerWave][2];  // kept in registers until every wave is done
+        // source tiles [k0, k1) of this wave (split: its share of its task's)
+        const int sp_st = split ? wave / ntasks : 0;
+        const int k0 = split ? sp_st * nkt / L.ns_st : 0;
+        const int k1 = split ? (sp_st + 1) * nkt / L.ns_st : nkt;
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {
-            const int task = wave + ts * nwaves;
+            const int task = split ? (ts == 0 && sp_st < L.ns_st ? wave % ntasks : ntasks) : wave + ts * nwaves;
             if (task >= ntasks) break;
             const int ibase = task * 64;
             // B columns (2 beta x_i, -beta in K-row 7); the accumulator starts
@@ -1005,7 +1104,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
                     for (int gg = 0; gg < NG; ++gg) av[r][gg] = vb[r * 8 + 4 * gg];
-                gram(min(kt + 1, nkt - 1), Gn);
+                gram(min(kt + 1, k1 - 1), Gn);
 #pragma unroll
                 for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
@@ -1020,17 +1119,19 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                             O4[gg][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[r][gg], G[q][r], O4[gg][q], 0, 0, 0);
             };
             f32x4 GA[kTilesPerWave], GB[kTilesPerWave];
-            gram(0, GA);
-            for (int kt = 0; kt < nkt; kt += 2) {
+            gram(k0, GA);
+            for (int kt = k0; kt < k1; kt += 2) {
                 bal.step();
                 tile(kt, GA, GB);
-                if (kt + 1 < nkt) tile(kt + 1, GB, GA);
+                if (kt + 1 < k1) tile(kt + 1, GB, GA);
             }
             // lane (col, g): target ibase + 16 q + col, coordinates g, 4 + g
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = ibase + 16 * q + col;
                 const float ksum = sum_row_quarters(O4[NG - 1][q][kOne - 4 * (NG - 1)]);
+                float *pp = PART + ((long)sp_st * npad + ii) * kPartStride;
+                if (split && g == 0) pp[8] = ksum;
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2) {
                     const int c = g + 4 * h2;
@@ -1039,7 +1140,11 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         // row c = 4 h2 + g: register g of the lane's row
                         const f32x4 &o = O4[h2 < NG ? h2 : 0][q];
                         const float sv = sum_quarters_scatter(o[0], o[1], o[2], o[3]);
-                        if (c < D) v = (sv + c2 * X8[(long)ii * 8 + c] * ksum) * inv_n;
+                        if (split) {
+                            if (c < D) pp[c] = sv;
+                        } else if (c < D) {
+                            v = (sv + c2 * X8[(long)ii * 8 + c] * ksum) * inv_n;
+                        }
                     }
                     phi[ts][q][h2] = v;
                 }
@@ -1050,11 +1155,36 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         // the window histogram starts the next walk at zero (the barrier at
         // the end of the iteration orders this before it)
         for (int q = tid; q < 256; q += nt) whist[q] = 0;
+        if (split) {
+            // synchronous update from the splits' partial sums (split order),
+            // then the squared norm of the moved particle
+            for (int i = tid; i < n; i += nt) {
+                float tot[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) tot[c] = 0.f;
+                float ks = 0.f;
+                for (int sp = 0; sp < L.ns_st; ++sp) {
+                    const float *pp = PART + ((long)sp * npad + i) * kPartStride;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) tot[c] += pp[c];
+                    ks += pp[8];
+                }
+                float nrm = 0.f;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const float xc = X8[(long)i * 8 + c];
+                    const float v = xc + a.step * ((tot[c] + c2 * xc * ks) * inv_n);
+                    X8[(long)i * 8 + c] = v;
+                    nrm += v * v;
+                }
+                X8[(long)i * 8 + 7] = nrm;
+            }
+        }
         // synchronous update, then unscaled squared norms for the next median
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {
             const int task = wave + ts * nwaves;
-            if (task >= ntasks) break;
+            if (split || task >= ntasks) break;
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = task * 64 + 16 * q + col;
@@ -1074,7 +1204,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
 #pragma unroll
         for (int ts = 0; ts < TS; ++ts) {
             const int task = wave + ts * nwaves;
-            if (task >= ntasks) break;
+            if (split || task >= ntasks) break;
             const int i = task * 64 + lane;
             if (i < n) {
                 float nrm = 0.f;
@@ -1138,10 +1268,10 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     if (bad) atomicOr(a.status, STATUS_NONFINITE);
 }
 
-template <int KIND, int D>
+template <int KIND, int D, bool SPLIT>
 __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
 {
-    step_mfma_body<KIND, D, kMaxParticles / 64 / kMaxWaves>(a, blockIdx.x);
+    step_mfma_body<KIND, D, kMaxParticles / 64 / kMaxWaves, SPLIT>(a, blockIdx.x);
 }
 
 } // namespace smsq

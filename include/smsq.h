@@ -152,7 +152,10 @@ typedef enum {
     SMSQ_STEP_AUTO = 0,
     SMSQ_STEP_WAVE = 1,   /* one wave per sequence, particles in registers (n, n_prev <= 64) */
     SMSQ_STEP_VALU = 2,   /* one workgroup per sequence on the vector ALU (any kernel, FP64) */
-    SMSQ_STEP_MFMA = 3    /* one workgroup per sequence on the matrix cores (FP32, RBF, d <= 7) */
+    SMSQ_STEP_MFMA = 3,   /* one workgroup per sequence on the matrix cores (FP32, RBF, d <= 7) */
+    SMSQ_STEP_COOP = 4    /* matrix cores, several workgroups per sequence: the Algorithm 2
+                             drivers at any size that splits evenly (see smsq_run_batch);
+                             elsewhere the automatic choice */
 } smsq_step_kernel_t;
 
 /* Validates a model description and copies it into an immutable handle.
@@ -163,7 +166,9 @@ smsq_status_t smsq_model_destroy(smsq_model_t model);
 
 /* Bytes of workspace needed by smsq_run_batch for `batch` sequences of T
  * steps with n particles (also enough for smsq_run_sequence with batch = 1
- * and for the single-step calls, which need only the 256-byte header). */
+ * and for the single-step calls, which need only the 256-byte header).
+ * Includes the exchange areas of the multi-workgroup steps where the shape
+ * can take them (see smsq_run_batch). */
 smsq_status_t smsq_workspace_size(smsq_model_t model, smsq_dtype_t dtype, int batch, int T,
                                   int n, size_t *bytes);
 
@@ -263,6 +268,19 @@ smsq_status_t smsq_batch_step(smsq_model_t model, smsq_dtype_t dtype, int batch,
 
 /* Algorithm 2 end to end for `batch` independent sequences (Monte-Carlo
  * runs) sharing a model and sizes.
+ * Multi-workgroup steps: in FP32 with the RBF kernel (families GROWTH1D,
+ * RANGE2D, CV4D, ARM7, d <= 7), when a sequence has at least 512 particles
+ * and the batch keeps at most a quarter of the compute units busy with one
+ * workgroup per sequence, each step of a sequence runs on G workgroups (the
+ * largest power of two dividing its 64-particle tasks with batch * G within
+ * the compute units) that own its target particles and exchange particles,
+ * score rows and the median's data through the workspace every SVGD
+ * iteration (a cooperative launch; on a stream under graph capture the
+ * one-workgroup kernels run instead).  opts->step_kernel = SMSQ_STEP_COOP
+ * takes this path at any size that splits evenly, SMSQ_STEP_MFMA never.
+ * Results agree with the one-workgroup kernels to rounding.  A step whose
+ * workgroups fail to meet at a barrier within a bounded wait (they did not
+ * all run at once) sets the device status to SMSQ_ERR_HIP.
  *  x0 [batch, d], z [batch, T, obs_dim], z_mask [batch, T, n_obs] or NULL
  *  seed           Philox key of the predictive initial particles (sequence b
  *                 uses counter word 2 = b)
@@ -472,8 +490,9 @@ smsq_status_t smsq_init_mlp_sample(smsq_init_mlp_t mlp, smsq_init_set_t set, int
 smsq_status_t smsq_batch_plan_set_init(smsq_batch_plan_t plan, smsq_init_mlp_t mlp);
 
 /* Reads the workspace status word (synchronous device-to-host copy; call
- * after the work has been synchronised).  *out is SMSQ_OK or
- * SMSQ_ERR_NONFINITE. */
+ * after the work has been synchronised).  *out is SMSQ_OK,
+ * SMSQ_ERR_NONFINITE, or SMSQ_ERR_HIP for a multi-workgroup step whose
+ * workgroups did not all run at once (see smsq_run_batch). */
 smsq_status_t smsq_get_device_status(const void *ws, smsq_status_t *out);
 /* Enqueues a reset of the workspace status word to SMSQ_OK. */
 smsq_status_t smsq_clear_device_status(void *ws, hipStream_t stream);

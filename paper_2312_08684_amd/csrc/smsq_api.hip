@@ -10,6 +10,7 @@
 #include <new>
 #include <algorithm>
 #include <vector>
+#include <type_traits>
 
 #include "smsq.h"
 #include "smsq_kernels.hpp"
@@ -398,10 +399,57 @@ bool opts_ok(const smsq_svgd_opts_t *o)
     return o && o->n_iter >= 0 && std::isfinite(o->step) && finite_pos(o->bw_scale) &&
            (o->bw_mode == 0 || o->bw_mode == 1) && (o->trans_mode == 0 || o->trans_mode == 1) &&
            o->kernel >= SMSQ_KERNEL_RBF && o->kernel <= SMSQ_KERNEL_MATERN32 && (o->weights == 0 || o->weights == 1) &&
-           o->step_kernel >= SMSQ_STEP_AUTO && o->step_kernel <= SMSQ_STEP_MFMA;
+           o->step_kernel >= SMSQ_STEP_AUTO && o->step_kernel <= SMSQ_STEP_COOP;
 }
 
 uint32_t *status_ptr(void *ws) { return reinterpret_cast<uint32_t *>(ws); }
+
+// Barrier counters of the exchange areas to zero before a multi-workgroup step.
+__global__ void k_coop_reset(char *base, long stride, int batch)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < batch) *(uint32_t *)(base + (long)b * stride) = 0u;
+}
+
+template <int KIND, int D>
+smsq_status_t launch_coop_kd(const StepArgs<float> &a, int batch, const CoopArgs &c, hipStream_t s)
+{
+    auto fn = &k_step_mfma_coop<KIND, D>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] { attr_err = allow_big_lds(fn); });
+    if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
+    const int npad = (a.n + 63) / 64 * 64;
+    const MfmaLds L(a.n, a.n_prev, kMaxWaves, npad / 64 / c.G, kCoopWinCap);
+    hipLaunchKernelGGL(k_coop_reset, dim3((batch + 63) / 64), dim3(64), 0, s, c.base, c.stride, batch);
+    StepArgs<float> aa = a;
+    CoopArgs cc = c;
+    void *args[] = {(void *)&aa, (void *)&cc};
+    // every workgroup of the grid resident at once (the barriers need it)
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(batch * c.G), dim3(kMaxWaves * kWave),
+                                   args, (unsigned)L.total, s) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+smsq_status_t launch_coop(const smsq_model_desc_t &d, const StepArgs<float> &a, int batch, const CoopArgs &c,
+                          hipStream_t s)
+{
+    switch (d.kind) {
+    case SMSQ_MODEL_GROWTH1D: return launch_coop_kd<GROWTH1D, 1>(a, batch, c, s);
+    case SMSQ_MODEL_RANGE2D: return launch_coop_kd<RANGE2D, 2>(a, batch, c, s);
+    case SMSQ_MODEL_CV4D: return launch_coop_kd<CV4D, 4>(a, batch, c, s);
+    case SMSQ_MODEL_ARM7: return launch_coop_kd<ARM7, 7>(a, batch, c, s);
+    }
+    return SMSQ_ERR_INVALID;
+}
+
+// A stream under graph capture takes no cooperative launch.
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
 
 // Generic batched step launch (typed).
 template <typename T>
@@ -412,7 +460,7 @@ smsq_status_t step_typed(const smsq_model_desc_t &d, int batch, int t, int n_pre
                          uint32_t seq_offset, const smsq_svgd_opts_t *opts, bool do_svgd, bool do_viterbi,
                          void *phi, long phi_stride, int32_t *psi, long psi_stride, uint8_t *flags,
                          long flags_stride, double tie_tol, void *h_out, long h_stride, void *ws,
-                         hipStream_t s)
+                         hipStream_t s, const CoopArgs *coop = nullptr)
 {
     StepArgs<T> a;
     std::memset(&a, 0, sizeof(a));
@@ -445,6 +493,8 @@ smsq_status_t step_typed(const smsq_model_desc_t &d, int batch, int t, int n_pre
     a.bw_scale = (T)(opts ? opts->bw_scale : 1.0);
     a.tie_tol = (T)tie_tol;
     a.seed = seed; a.seq_offset = seq_offset;
+    if constexpr (std::is_same<T, float>::value)
+        if (coop && coop->G > 1) return launch_coop(d, a, batch, *coop, s);
     return launch_step<T>(d, a, batch, opts ? opts->step_kernel : SMSQ_STEP_AUTO, s);
 }
 
@@ -455,7 +505,7 @@ smsq_status_t step_dispatch(smsq_dtype_t dt, const smsq_model_desc_t &d, int bat
                             int init_given, uint64_t seed, uint32_t seq_offset, const smsq_svgd_opts_t *opts,
                             bool do_svgd, bool do_viterbi, void *phi, long phi_stride, int32_t *psi,
                             long psi_stride, uint8_t *flags, long flags_stride, double tie_tol, void *h_out,
-                            long h_stride, void *ws, hipStream_t s)
+                            long h_stride, void *ws, hipStream_t s, const CoopArgs *coop = nullptr)
 {
     if (dt == SMSQ_F64)
         return step_typed<double>(d, batch, t, n_prev, x_prev, x_prev_stride, log_w, log_w_stride, phi_prev,
@@ -465,29 +515,8 @@ smsq_status_t step_dispatch(smsq_dtype_t dt, const smsq_model_desc_t &d, int bat
     return step_typed<float>(d, batch, t, n_prev, x_prev, x_prev_stride, log_w, log_w_stride, phi_prev,
                              phi_prev_stride, z, z_stride, mask, mask_stride, n, x, x_stride, init_given, seed,
                              seq_offset, opts, do_svgd, do_viterbi, phi, phi_stride, psi, psi_stride, flags,
-                             flags_stride, tie_tol, h_out, h_stride, ws, s);
+                             flags_stride, tie_tol, h_out, h_stride, ws, s, coop);
 }
-
-struct RunLayout {
-    size_t parts, psi, phi, idx, total;
-};
-
-RunLayout run_layout(smsq_dtype_t dt, int batch, int T, int n, int d)
-{
-    RunLayout L;
-    size_t o = kHeader;
-    const size_t es = elem_size(dt);
-    L.parts = o; o += align256((size_t)batch * T * n * d * es);
-    L.psi = o; o += align256((size_t)batch * T * n * sizeof(int32_t));
-    L.phi = o; o += align256((size_t)2 * batch * n * es);
-    L.idx = o; o += align256((size_t)batch * T * sizeof(int32_t));
-    L.total = o;
-    return L;
-}
-
-bool dtype_ok(smsq_dtype_t dt) { return dt == SMSQ_F32 || dt == SMSQ_F64; }
-
-// ---- batched ragged plans ------------------------------------------------
 
 int device_cus()
 {
@@ -501,6 +530,73 @@ int device_cus()
     });
     return cus;
 }
+
+// ---- multi-workgroup steps (Algorithm 2 drivers) --------------------------
+// When a batch leaves most compute units idle (at most a quarter busy with
+// one workgroup per sequence) and a sequence has at least 512 particles, the
+// FP32 matrix-core step of each sequence runs on G workgroups that own its
+// target tasks (k_step_mfma_coop): G is the largest power of two that
+// divides the sequence's 64-particle tasks with batch * G within the
+// compute units (1: the one-workgroup kernels).  Below 512 particles an
+// SVGD iteration of one workgroup (26 us at 256 particles) is too short for
+// the two barriers and exchanges per iteration to pay (measured: no gain at
+// 256, 1.9x at 512, 3.7x at 1024 for one sequence).  Families of the
+// matrix-core drivers with a multi-workgroup kernel: growth, range-only,
+// clutter, arm.
+constexpr int kCoopMinParticles = 512;
+bool coop_family(int kind)
+{
+    return kind == SMSQ_MODEL_GROWTH1D || kind == SMSQ_MODEL_RANGE2D || kind == SMSQ_MODEL_CV4D ||
+           kind == SMSQ_MODEL_ARM7;
+}
+
+// force: any shape the multi-workgroup kernel takes (step_kernel =
+// SMSQ_STEP_COOP), not only where it pays.
+int coop_groups(smsq_dtype_t dt, const smsq_model_desc_t &d, int batch, int n, bool force)
+{
+    if (dt != SMSQ_F32 || !coop_family(d.kind) || d.d > 7) return 1;
+    const int ntasks = (n + 63) / 64;
+    const MfmaLds L1(n, n);
+    if (L1.npad > kMaxParticles) return 1;
+    if (!force && (n < kCoopMinParticles || 4L * batch > device_cus())) return 1;
+    int G = 1;
+    while (2 * G <= ntasks && ntasks % (2 * G) == 0 && (long)batch * 2 * G <= device_cus()) G *= 2;
+    if (G > 1 && (MfmaLds(n, n, kMaxWaves, ntasks / G, kCoopWinCap).total > kLdsLimit ||
+                  MfmaLds(n, 1, kMaxWaves, ntasks / G, kCoopWinCap).total > kLdsLimit))
+        return 1;
+    return G;
+}
+
+// The run's scratch in the workspace: header (status word), every step's
+// particles, back-pointers, ping-pong scores, MAP indices, and the exchange
+// areas of the multi-workgroup steps (coop_groups > 1).
+struct RunLayout {
+    size_t parts, psi, phi, idx, coop, coop_stride, total;
+    int G, G_force;  // workgroups per sequence: automatic choice, largest (forced)
+};
+
+RunLayout run_layout(smsq_dtype_t dt, const smsq_model_desc_t &desc, int batch, int T, int n)
+{
+    RunLayout L;
+    size_t o = kHeader;
+    const size_t es = elem_size(dt);
+    const int d = desc.d;
+    L.parts = o; o += align256((size_t)batch * T * n * d * es);
+    L.psi = o; o += align256((size_t)batch * T * n * sizeof(int32_t));
+    L.phi = o; o += align256((size_t)2 * batch * n * es);
+    L.idx = o; o += align256((size_t)batch * T * sizeof(int32_t));
+    L.G = coop_groups(dt, desc, batch, n, false);
+    L.G_force = coop_groups(dt, desc, batch, n, true);
+    L.coop = o;
+    L.coop_stride = L.G_force > 1 ? (size_t)CoopLayout((n + 63) / 64 * 64, L.G_force).bytes : 0;
+    o += (size_t)batch * L.coop_stride;
+    L.total = o;
+    return L;
+}
+
+bool dtype_ok(smsq_dtype_t dt) { return dt == SMSQ_F32 || dt == SMSQ_F64; }
+
+// ---- batched ragged plans ------------------------------------------------
 
 hipError_t batch_kernel_attrs()
 {
@@ -713,7 +809,7 @@ smsq_status_t run_batch_ws(smsq_model_t model, smsq_dtype_t dtype, int batch, in
         !logpost_out)
         return SMSQ_ERR_INVALID;
     const smsq_model_desc_t &d = model->desc;
-    const RunLayout L = run_layout(dtype, batch, T, n, d.d);
+    const RunLayout L = run_layout(dtype, d, batch, T, n);
     if (!ws || ws_bytes < L.total) return SMSQ_ERR_WORKSPACE;
     if (!step_shape_ok(dtype, n, n, d.d) || !step_shape_ok(dtype, n, 1, d.d)) return SMSQ_ERR_UNSUPPORTED;
     char *w = (char *)ws;
@@ -726,6 +822,11 @@ smsq_status_t run_batch_ws(smsq_model_t model, smsq_dtype_t dtype, int batch, in
     const long step_stride = (long)n * d.d;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, status_ptr(ws), 0u, 1);
     if (hipGetLastError() != hipSuccess) return SMSQ_ERR_HIP;
+    // several workgroups per sequence while the batch leaves compute units idle
+    const int G = opts->step_kernel == SMSQ_STEP_COOP ? L.G_force
+                  : opts->step_kernel == SMSQ_STEP_AUTO ? L.G : 1;
+    const bool coop = G > 1 && opts->kernel == SMSQ_KERNEL_RBF && !capturing(stream);
+    const CoopArgs ca{w + L.coop, (long)L.coop_stride, G, 0};
     for (int t = 1; t <= T; ++t) {
         const void *xp = t == 1 ? x0 : (const void *)(parts + (size_t)(t - 2) * step_stride * es);
         const long xp_stride = t == 1 ? (long)d.d : seq_stride;
@@ -737,7 +838,7 @@ smsq_status_t run_batch_ws(smsq_model_t model, smsq_dtype_t dtype, int batch, in
         const smsq_status_t st = step_dispatch(
             dtype, d, batch, t, np, xp, xp_stride, nullptr, 0, phip, np, zt, (long)T * d.obs_dim, mt,
             (long)T * d.n_obs, n, xt, seq_stride, 0, seed, 0, opts, true, true, phi_buf[t & 1], n,
-            psi + (size_t)(t - 1) * n, (long)T * n, nullptr, 0, 0.0, nullptr, 0, ws, stream);
+            psi + (size_t)(t - 1) * n, (long)T * n, nullptr, 0, 0.0, nullptr, 0, ws, stream, coop ? &ca : nullptr);
         if (st != SMSQ_OK) return st;
     }
     return smsq_backtrack(dtype, batch, T, n, d.d, psi, phi_buf[T & 1], idx, logpost_out, parts, x0, xmap_out, ws,
@@ -781,7 +882,8 @@ smsq_status_t scratch_address(void **out)
 // The run's device status word as a status code for the caller.
 __global__ void k_status_out(const uint32_t *__restrict__ word, int32_t *__restrict__ out)
 {
-    if (threadIdx.x == 0) out[0] = (word[0] & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
+    if (threadIdx.x == 0)
+        out[0] = (word[0] & STATUS_STALLED) ? SMSQ_ERR_HIP : (word[0] & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
 }
 
 } // namespace
@@ -810,7 +912,7 @@ smsq_status_t smsq_model_destroy(smsq_model_t model)
 smsq_status_t smsq_workspace_size(smsq_model_t model, smsq_dtype_t dtype, int batch, int T, int n, size_t *bytes)
 {
     if (!model || !bytes || !dtype_ok(dtype) || batch < 1 || T < 1 || n < 1) return SMSQ_ERR_INVALID;
-    *bytes = run_layout(dtype, batch, T, n, model->desc.d).total;
+    *bytes = run_layout(dtype, model->desc, batch, T, n).total;
     return SMSQ_OK;
 }
 
@@ -945,7 +1047,7 @@ smsq_status_t smsq_run_sequence_noalloc(smsq_model_t model, smsq_dtype_t dtype, 
                                         void *particles_out, int32_t *status_out, hipStream_t stream)
 {
     if (!model || !dtype_ok(dtype) || T < 1 || n < 1) return SMSQ_ERR_INVALID;
-    if (run_layout(dtype, 1, T, n, model->desc.d).total > kNoallocBytes) return SMSQ_ERR_WORKSPACE;
+    if (run_layout(dtype, model->desc, 1, T, n).total > kNoallocBytes) return SMSQ_ERR_WORKSPACE;
     void *ws = nullptr;
     smsq_status_t st = scratch_address(&ws);
     if (st != SMSQ_OK) return st;
@@ -961,7 +1063,7 @@ smsq_status_t smsq_get_device_status(const void *ws, smsq_status_t *out)
     if (!ws || !out) return SMSQ_ERR_INVALID;
     uint32_t v = 0;
     if (hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return SMSQ_ERR_HIP;
-    *out = (v & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
+    *out = (v & STATUS_STALLED) ? SMSQ_ERR_HIP : (v & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
     return SMSQ_OK;
 }
 
@@ -1181,7 +1283,7 @@ smsq_status_t smsq_batch_status(smsq_batch_plan_t p, smsq_status_t *out)
     if (!p || !out) return SMSQ_ERR_INVALID;
     uint32_t v = 0;
     if (hipMemcpy(&v, p->status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return SMSQ_ERR_HIP;
-    *out = (v & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
+    *out = (v & STATUS_STALLED) ? SMSQ_ERR_HIP : (v & STATUS_NONFINITE) ? SMSQ_ERR_NONFINITE : SMSQ_OK;
     return SMSQ_OK;
 }
 

@@ -50,7 +50,9 @@ __device__ __forceinline__ void stein_kernel(int kernel, T dd, T inv_h, T &kap, 
 }
 constexpr int kMaxObs = 32;
 
-enum : uint32_t { STATUS_NONFINITE = 4u };
+// Device status bits: non-finite values; a multi-workgroup step whose
+// workgroups did not all reach a barrier within the wait bound.
+enum : uint32_t { STATUS_NONFINITE = 4u, STATUS_STALLED = 8u };
 
 template <typename T> struct StepArgs {
     DevModel<T> m;

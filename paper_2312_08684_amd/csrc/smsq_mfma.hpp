@@ -93,14 +93,19 @@ constexpr int kPartStride = 9;     // floats per particle in a split's partial s
 // in split order (the same result whatever the timing).  ns_sc / ns_st are
 // the splits of the score and Stein passes (at most the source tiles each
 // pass has); nwaves the waves a launch of this shape uses.
+// A workgroup of the multi-workgroup mode owns tasks_local of the tasks (its
+// targets) and holds every particle; win_cap is its window buffer's capacity.
 struct MfmaLds {
     long off_x, off_s, off_m, off_phip, off_scr, off_win, off_z, off_mask, off_red, off_part, total;
-    int npad, nppad, nwaves, ntasks, ns_sc, ns_st, ns_max;
-    __host__ __device__ MfmaLds(int n, int n_prev, int waves = kMaxWaves)
+    int npad, nppad, nwaves, ntasks, ns_sc, ns_st, ns_max, win_cap, win_region;
+    __host__ __device__ MfmaLds(int n, int n_prev, int waves = kMaxWaves, int tasks_local = 0,
+                                int win = kWinCap)
     {
         npad = (n + 63) / 64 * 64;
         nppad = (n_prev + 15) / 16 * 16;
-        ntasks = npad / 64;
+        ntasks = tasks_local > 0 ? tasks_local : npad / 64;
+        win_cap = win;
+        win_region = win / kMaxWaves;
         if (ntasks >= waves) {
             ns_sc = ns_st = ns_max = 1;
             nwaves = waves;
@@ -117,12 +122,12 @@ struct MfmaLds {
         off_m = o; o += align16((long)kVtRows * nppad * 4);
         off_phip = o; o += align16((long)nppad * 4);
         off_scr = o; o += (long)kBins * 4;  // the radix-selection histogram
-        off_win = o; o += (long)(kWinCap + 256) * 4;       // window buffer + its histogram
+        off_win = o; o += (long)(win_cap + 256) * 4;       // window buffer + its histogram
         off_z = o; o += align16((long)kMaxObs * 4);
         off_mask = o; o += 64;
         off_red = o; o += 512;  // uint slots 0..63 (48..63: wave progress), float slots from byte 256
-        // partial sums of the splits: [ns_max][npad][9] floats
-        off_part = o; o += ns_max > 1 ? align16((long)ns_max * npad * kPartStride * 4) : 0;
+        // partial sums of the splits: [ns_max][ntasks * 64][9] floats
+        off_part = o; o += ns_max > 1 ? align16((long)ns_max * ntasks * 64 * kPartStride * 4) : 0;
         total = o;
     }
 };
@@ -139,10 +144,11 @@ struct MfmaLds {
 // Pad particles have n = +inf, so their distances are +inf.  The median
 // window pass (TileWalker) computes every distance the same way.
 template <typename Fn>
-__device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn &&fn)
+__device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn &&fn, int vwave = -1, int nvwaves = 0)
 {
     constexpr int kBatch = 4;
-    const int lane = threadIdx.x & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = nvwaves > 0 ? vwave : wave_id(), nwaves = nvwaves > 0 ? nvwaves : (int)(blockDim.x >> 6);
     const int g = lane >> 4, col = lane & 15;
     const int nt16 = npad / 16;
     // Rows of tiles (target tile ib, source tiles kb >= ib) go to the waves in
@@ -236,21 +242,21 @@ __device__ float radix_median_mfma(const float *X8, int npad, uint32_t rank, uin
 // values sit in buf[w * kWinRegion ...] with wcnt[w] of them, all in
 // [lo, hi) (key_lo, key_hi their bit patterns).  Radix selection on the key
 // offsets key - key_lo, 8 bits per pass, as many passes as the span needs.
-__device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregions, uint32_t r, uint32_t key_lo,
-                               uint32_t key_hi, uint32_t *hist, uint32_t *red)
+__device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregions, int region, uint32_t r,
+                               uint32_t key_lo, uint32_t key_hi, uint32_t *hist, uint32_t *red)
 {
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = wave_id();
     const uint32_t span = key_hi - key_lo;
     const int bits = span == 0 ? 1 : 32 - __clz(span);
     const int passes = (bits + 7) / 8;
-    const int nslots = nregions * kWinRegion;
+    const int nslots = nregions * region;
     uint32_t prefix = 0, pmask = 0;
     for (int p = passes - 1; p >= 0; --p) {
         const int shift = 8 * p;
         for (int q = tid; q < 256; q += nt) hist[q] = 0;
         __syncthreads();
         for (int s = tid; s < nslots; s += nt) {
-            if ((uint32_t)(s % kWinRegion) < wcnt[s / kWinRegion]) {
+            if ((uint32_t)(s % region) < wcnt[s / region]) {
                 const uint32_t k = __float_as_uint(buf[s]) - key_lo;
                 if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 0xffu], 1u);
             }
@@ -289,8 +295,9 @@ __device__ float buffer_select(const float *buf, const uint32_t *wcnt, int nregi
 // not matter); wave 0 ranks the candidates by comparison.  A bin with more
 // than 64 values (heavy ties) falls back to buffer_select.  cand may alias
 // whist: the histogram is dead once the bin is known.
-__device__ float window_select(const float *buf, const uint32_t *wcnt, int nregions, uint32_t r, uint32_t key_lo,
-                               uint32_t key_hi, uint32_t shift, uint32_t *whist, uint32_t *red, float *cand)
+__device__ float window_select(const float *buf, const uint32_t *wcnt, int nregions, int region, uint32_t r,
+                               uint32_t key_lo, uint32_t key_hi, uint32_t shift, uint32_t *whist, uint32_t *red,
+                               float *cand)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
     if (wave == 0) {
@@ -316,11 +323,11 @@ __device__ float window_select(const float *buf, const uint32_t *wcnt, int nregi
     }
     __syncthreads();
     const uint32_t bin = red[2], rr = red[3], cb = red[4];
-    if (cb > (uint32_t)kWave) return buffer_select(buf, wcnt, nregions, r, key_lo, key_hi, whist, red);
+    if (cb > (uint32_t)kWave) return buffer_select(buf, wcnt, nregions, region, r, key_lo, key_hi, whist, red);
     for (int w = wave; w < nregions; w += nwaves) {
         const uint32_t c = wcnt[w];
         for (uint32_t s = lane; s < c; s += kWave) {
-            const float v = buf[w * kWinRegion + s];
+            const float v = buf[w * region + s];
             if (((__float_as_uint(v) - key_lo) >> shift) == bin) cand[atomicAdd(&red[6], 1u)] = v;
         }
     }
@@ -344,9 +351,12 @@ __device__ float window_select(const float *buf, const uint32_t *wcnt, int nregi
 // kb > ib), two source tiles kb, kb + 1 per step.  Holds the current row's
 // B operand (-2 x_i with a 1 in row 7) and the target norms as the
 // accumulator input.  The diagonal tiles of the wave's rows are visited by
-// diagonals().
+// diagonals().  In chunk mode (the multi-workgroup walk: more waves than
+// rows) virtual wave v of nv takes the v-th of nv equal contiguous runs of
+// the off-diagonal tiles listed row by row, and every nv-th diagonal tile.
 struct TileWalker {
-    int nt16, nwaves, wave, rr, ib, kb;
+    int nt16, nwaves, wave, rr, ib, kb, left;
+    bool chunk;
     float bi0, bi1;
     f32x4 cn;
 
@@ -359,17 +369,40 @@ struct TileWalker {
         const float nni = xi[7];
         cn = f32x4{nni, nni, nni, nni};
     }
-    __device__ void start(const float *X8, int npad, int g, int col)
+    __device__ void start(const float *X8, int npad, int g, int col, int vwave = -1, int nvwaves = 0)
     {
         nt16 = npad / 16;
-        nwaves = blockDim.x >> 6;
-        wave = wave_id();
-        rr = -1;
-        next_row(X8, g, col);
+        chunk = nvwaves > 0;
+        nwaves = chunk ? nvwaves : (int)(blockDim.x >> 6);
+        wave = chunk ? vwave : wave_id();
+        if (!chunk) {
+            left = 0x7fffffff;
+            rr = -1;
+            next_row(X8, g, col);
+            return;
+        }
+        const long total = (long)nt16 * (nt16 - 1) / 2;
+        long p0 = total * wave / nwaves;
+        left = (int)(total * (wave + 1) / nwaves - p0);
+        ib = 0;
+        while (ib < nt16 - 1 && p0 >= nt16 - 1 - ib) {
+            p0 -= nt16 - 1 - ib;
+            ++ib;
+        }
+        kb = ib + 1 + (int)p0;
+        if (left <= 0) ib = nt16;
+        else load_row(X8, g, col);
     }
     // next row with an off-diagonal tile
     __device__ void next_row(const float *X8, int g, int col)
     {
+        if (chunk) {
+            ++ib;
+            kb = ib + 1;
+            if (left <= 0 || kb >= nt16) ib = nt16;
+            else load_row(X8, g, col);
+            return;
+        }
         do {
             ++rr;
             ib = row_of(rr);
@@ -378,7 +411,7 @@ struct TileWalker {
         if (ib < nt16) load_row(X8, g, col);
     }
     __device__ bool done() const { return ib >= nt16; }
-    __device__ bool second() const { return kb + 1 < nt16; }
+    __device__ bool second() const { return kb + 1 < nt16 && left >= 2; }
     // distances of tiles kb and kb + 1 (clamped to the row: always in
     // bounds, also once the walk is done; results past the end are unused)
     __device__ void issue(const float *X8, int g, int col, f32x4 &D0, f32x4 &D1) const
@@ -393,14 +426,17 @@ struct TileWalker {
     }
     __device__ void advance(const float *X8, int g, int col)
     {
+        left -= second() ? 2 : 1;
         kb += 2;
-        if (kb >= nt16) next_row(X8, g, col);
+        if (left <= 0) ib = nt16;
+        else if (kb >= nt16) next_row(X8, g, col);
     }
-    // the diagonal tile of every row of this wave, fn(D, true)
+    // the diagonal tile of every row of this wave (chunk mode: every
+    // nwaves-th row), fn(D, true)
     template <typename Fn> __device__ void diagonals(const float *X8, int g, int col, Fn &&fn)
     {
         for (int r = 0;; ++r) {
-            ib = row_of(r);
+            ib = chunk ? wave + r * nwaves : row_of(r);
             if (ib >= nt16) break;
             load_row(X8, g, col);
             const float *xk = X8 + (long)(ib * 16 + col) * 8;
@@ -427,12 +463,14 @@ struct MedianTracker {
     uint32_t kept;   // per wave: distances kept (kOverflow once the region is full)
     uint32_t wshift; // window histogram bin of a kept distance: (key - key(lo)) >> wshift
     uint32_t *whist; // its 256 counters (zero before the walk)
+    int wcap;        // per-wave capacity of the window buffer
 
-    __device__ void reset()
+    __device__ void reset(int cap = kWinRegion)
     {
         med1 = med2 = density = 0.f;
         have = 0;
         active = false;
+        wcap = cap;
     }
 
     // window of this iteration (active only with a previous median)
@@ -484,7 +522,7 @@ struct MedianTracker {
             for (int r = 0; r < 4; ++r) {
                 const unsigned long long mk = __builtin_amdgcn_ballot_w64(u[r] < span);
                 const uint32_t cnt = (uint32_t)__builtin_popcountll(mk);
-                const bool fits = kept + cnt <= (uint32_t)kWinRegion;  // kOverflow stays
+                const bool fits = kept + cnt <= (uint32_t)wcap;  // kOverflow stays
                 if (fits && u[r] < span) {
                     region[kept + lanes_below(mk)] = Dv[r] + 0.f;  // no -0
                     atomicAdd(&whist[u[r] >> wshift], 1u);
@@ -520,12 +558,12 @@ struct MedianTracker {
             for (int q = 0; q < nwaves; ++q) {
                 cnt_lo += wbelow[q];
                 n_in += wcnt[q];
-                overflow |= wcnt[q] > (uint32_t)kWinRegion;
+                overflow |= wcnt[q] > (uint32_t)wcap;
             }
             density = uniform((float)n_in / (hi - lo));
             if (!overflow && rank >= cnt_lo && rank < cnt_lo + n_in) {
-                med = window_select(buf, wcnt, nwaves, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi), wshift,
-                                    whist, red, (float *)whist);
+                med = window_select(buf, wcnt, nwaves, wcap, rank - cnt_lo, __float_as_uint(lo), __float_as_uint(hi),
+                                    wshift, whist, red, (float *)whist);
                 done = true;
             }
             __syncthreads();
@@ -602,28 +640,112 @@ __device__ __forceinline__ float sum_quarters_scatter(float v0, float v1, float 
     return __uint_as_float(c[0]) + __uint_as_float(c[1]);
 }
 
+// ---- multi-workgroup mode ---------------------------------------------
+// The G workgroups of one sequence each own tasks_local = ntasks / G
+// consecutive 64-particle target tasks and hold every particle in LDS.  Per
+// SVGD iteration they exchange, through global memory, the score rows of
+// their targets and their share of the median's window pass (barrier 1),
+// then their moved particles (barrier 2); every workgroup then holds the
+// same state, and every selection they make from the exchanged data (the
+// median, the radix fallback) is the same.  The layout of one sequence's
+// exchange area, host and device:
+constexpr int kCoopWinCap = 2048;     // window buffer of a workgroup (floats)
+constexpr uint32_t kCoopSpinLimit = 1u << 24;  // barrier wait bound (polls)
+
+struct CoopLayout {
+    long off_ctr, off_x, off_s, off_info, off_whist, off_vals, off_rhist, bytes;
+    __host__ __device__ CoopLayout(int npad, int G)
+    {
+        long o = 0;
+        off_ctr = o; o += 256;
+        off_x = o; o += align16((long)npad * 8 * 4);
+        off_s = o; o += align16((long)npad * 8 * 4);
+        off_info = o; o += align16((long)G * 4 * 4);
+        off_whist = o; o += align16((long)G * 256 * 4);
+        off_vals = o; o += align16((long)G * kCoopWinCap * 4);
+        off_rhist = o; o += align16((long)2 * G * kBins * 4);   // two buffers, alternate passes
+        bytes = (o + 255) / 256 * 256;
+    }
+};
+
+struct CoopArgs {
+    char *base;     // exchange area of sequence 0; sequence b at base + b * stride
+    long stride;
+    int G;          // workgroups per sequence
+    int gi;         // this workgroup's index within its sequence (set by the kernel)
+};
+
+// Barrier among the G workgroups of a sequence: thread 0 makes the
+// workgroup's global writes visible at device scope, arrives on the counter
+// and waits for epoch * G arrivals (bounded: past the bound the stall bit is
+// set and the wait ends, and once it is set no barrier of the run waits),
+// then acquires before the workgroup reads what the others wrote.
+__device__ __forceinline__ void coop_barrier(uint32_t *ctr, uint32_t target, uint32_t *status)
+{
+    // every wave waits for its own global stores to complete, so they sit in
+    // the L2 before the workgroup barrier; thread 0's device-scope release
+    // then writes them back, and its acquire (before the second workgroup
+    // barrier) invalidates the caches the other waves read through: one
+    // write-back and one invalidation per workgroup
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(ctr, 1u);
+        uint32_t polls = 0;
+        // after one stall no later barrier waits (the run is flagged already)
+        const bool stalled = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & STATUS_STALLED) != 0;
+        while (!stalled && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++polls > kCoopSpinLimit) {
+                atomicOr(status, STATUS_STALLED);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
 // SPLIT: the layout splits the sources of each task among waves (MfmaLds
 // ns_max > 1); a separate instantiation, so the unsplit path keeps its
-// registers.
-template <int KIND, int D, int TS, bool SPLIT>
-__device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const int b)
+// registers.  COOP (with SPLIT): one of the G workgroups of sequence b in
+// the multi-workgroup mode (cx).
+template <int KIND, int D, int TS, bool SPLIT, bool COOP = false>
+__device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const int b, const CoopArgs cx = CoopArgs{})
 {
     using F = Family<float, KIND, D>;
     using R = RealOps<float>;
     static_assert(D <= 7, "K-column 7 carries the norms");
     extern __shared__ __align__(16) unsigned char smem[];
+    static_assert(!COOP || SPLIT, "the multi-workgroup mode splits the sources");
     const int n = a.n, np = a.n_prev;
-    const MfmaLds L(n, np, (int)(blockDim.x >> 6));
+    const int G = COOP ? cx.G : 1, gi = COOP ? cx.gi : 0;
+    const int npad0 = (n + 63) / 64 * 64;
+    const MfmaLds L(n, np, (int)(blockDim.x >> 6), COOP ? npad0 / 64 / G : 0, COOP ? kCoopWinCap : kWinCap);
     const int npad = L.npad, nppad = L.nppad;
     constexpr bool split = SPLIT;               // sources of a task split among waves (L.ns_max > 1)
-    float *PART = (float *)(smem + L.off_part); // [ns_max][npad][kPartStride] partial sums of the splits
+    float *PART = (float *)(smem + L.off_part); // [ns_max][ntasks * 64][kPartStride] partial sums of the splits
+    // the workgroup's targets: tasks [tbase / 64, tbase / 64 + ntasks) (all of them outside COOP)
+    const int tbase = gi * L.ntasks * 64;
+    // exchange area of this sequence (COOP)
+    const CoopLayout CL(npad, G);
+    char *cbase = COOP ? cx.base + (long)b * cx.stride : nullptr;
+    uint32_t *cctr = (uint32_t *)(cbase + CL.off_ctr);
+    float *cX = (float *)(cbase + CL.off_x);
+    float *cS = (float *)(cbase + CL.off_s);
+    uint32_t *cinfo = (uint32_t *)(cbase + CL.off_info);
+    uint32_t *cwhist = (uint32_t *)(cbase + CL.off_whist);
+    float *cvals = (float *)(cbase + CL.off_vals);
+    uint32_t *crhist = (uint32_t *)(cbase + CL.off_rhist);
+    uint32_t epoch = 0;  // barriers passed (the same count in every workgroup)
     float *X8 = (float *)(smem + L.off_x);     // [npad][8]  centred particles, |x|^2 in column 7 (pad: 0.., +inf)
     float *S8 = (float *)(smem + L.off_s);     // [npad][8]  scores
     float *VT = (float *)(smem + L.off_m);     // [9][nppad] rows 2 mh_c (c < 7; 0 for c >= d), 1, c'_j
     float *PHP = (float *)(smem + L.off_phip); // [nppad] previous forward-recursion scores
     uint32_t *hist = (uint32_t *)(smem + L.off_scr);
     float *WIN = (float *)(smem + L.off_win);                    // median window buffer
-    uint32_t *whist = (uint32_t *)(smem + L.off_win) + kWinCap;  // its histogram
+    uint32_t *whist = (uint32_t *)(smem + L.off_win) + L.win_cap;  // its histogram
     float *sz = (float *)(smem + L.off_z);
     uint8_t *smask = smem + L.off_mask;
     uint32_t *red = (uint32_t *)(smem + L.off_red);
@@ -749,13 +871,16 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         }
     }
 
-    const int ntasks = npad / 64;
+    const int ntasks = L.ntasks;   // target tasks of this workgroup
     const int njt = nppad / 16;
+    // every workgroup of the sequence has read its inputs before any writes
+    // its outputs (the x array may hold the initial particles)
+    if (COOP) coop_barrier(cctr, ++epoch * (uint32_t)G, a.status);
     const int nkt = npad / 16;
     const float inv_n = 1.f / (float)n;
     float h = 1.f;
     MedianTracker tracker;
-    tracker.reset();
+    tracker.reset(L.win_region);
 
     for (int it = 0; a.do_svgd && it < a.n_iter; ++it) {
         // (1) the bandwidth needs the exact lower median of the squared
@@ -764,8 +889,13 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         const bool need_median = a.bw_mode == 0 || it == 0;
         if (need_median) tracker.plan(whist);
         TileWalker walker;
-        if (tracker.active) walker.start(X8, npad, g, col);
-        float *wregion = WIN + wave * kWinRegion;
+        if (tracker.active) {
+            if (COOP)
+                walker.start(X8, npad, g, col, gi * nwaves + wave, G * nwaves);
+            else
+                walker.start(X8, npad, g, col);
+        }
+        float *wregion = WIN + wave * L.win_region;
         auto walk_step = [&]() {
             f32x4 W0, W1;
             walker.issue(X8, g, col, W0, W1);
@@ -933,8 +1063,8 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             if (a.trans_mode == 0 && wave < ntasks * L.ns_sc) {
                 const int task = wave % ntasks, sp = wave / ntasks;
                 float osum[8], sref;
-                score_sums(task * 64, sp * njt / L.ns_sc, (sp + 1) * njt / L.ns_sc, osum, sref);
-                float *pp = PART + ((long)sp * npad + task * 64 + lane) * kPartStride;
+                score_sums(tbase + task * 64, sp * njt / L.ns_sc, (sp + 1) * njt / L.ns_sc, osum, sref);
+                float *pp = PART + ((long)sp * ntasks * 64 + task * 64 + lane) * kPartStride;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) pp[c] = osum[c];
                 pp[8] = sref;
@@ -986,11 +1116,278 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             walker.diagonals(X8, g, col, [&](const f32x4 &Dd, bool dg) { tracker.visit(Dd, dg, wregion); });
         }
         __syncthreads();
-        if (need_median) {
+        if constexpr (COOP) {
+            // score rows of this workgroup's targets from the splits' partial
+            // sums (rebased to their largest reference, summed in split
+            // order), to the exchange area: the largest reference per target,
+            // the rebased sums per (target, row) into S8, then the rows
+            const int ntl = ntasks * 64;
+            float *mref = (float *)hist;  // [ntl] (the radix histogram is free here)
+            if (a.trans_mode == 0) {
+                for (int kl = tid; kl < ntl; kl += nt) {
+                    float mx = -inf;
+                    for (int sp = 0; sp < L.ns_sc; ++sp)
+                        mx = fmax_(mx, PART[((long)sp * ntl + kl) * kPartStride + 8]);
+                    mref[kl] = mx;
+                }
+                __syncthreads();
+                for (int e = tid; e < ntl * 8; e += nt) {
+                    const int kl = e >> 3, c = e & 7;
+                    const float mx = mref[kl];
+                    float acc = 0.f;
+                    for (int sp = 0; sp < L.ns_sc; ++sp) {
+                        const float *pp = PART + ((long)sp * ntl + kl) * kPartStride;
+                        acc += pp[c] * R::exp2_(pp[8] - mx);
+                    }
+                    S8[(long)(tbase + kl) * 8 + c] = acc;
+                }
+                __syncthreads();
+            }
+            for (int kl = tid; kl < ntl; kl += nt) {
+                const int k = tbase + kl;
+                float srow[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) srow[c] = 0.f;
+                srow[7] = 1.f;
+                if (k < n) {
+                    float xt[D], xa[D], gr[D];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        xt[c] = X8[(long)k * 8 + c];
+                        xa[c] = xt[c] + ref[c];
+                    }
+                    F::grad(m, sz, mk, xa, gr);
+                    if (a.trans_mode == 0) {
+                        const float inv_sum = 1.f / S8[(long)k * 8 + 7];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            const float mb = S8[(long)k * 8 + c] * inv_sum * 0.5f / rs[c];
+                            srow[c] = gr[c] - (xt[c] - mb) * m.inv_q[c];
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) srow[c] = gr[c] - (xt[c] - mbar_all[c]) * m.inv_q[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) cS[(long)k * 8 + c] = srow[c];
+            }
+            // this workgroup's share of the window pass: counts, its kept
+            // distances in wave order, its histogram
+            if (need_median && tracker.active) {
+                const uint32_t bw = wave_sum(tracker.below);
+                if (lane == 0) {
+                    red[26 + wave] = bw;
+                    red[10 + wave] = tracker.kept;
+                }
+                __syncthreads();
+                uint32_t below = 0, kept = 0, off_w = 0;
+                bool ovf = false;
+                for (int q = 0; q < nwaves; ++q) {
+                    const uint32_t c = red[10 + q];
+                    ovf |= c > (uint32_t)L.win_region;
+                    if (q < wave) off_w += c;
+                    below += red[26 + q];
+                    kept += c;
+                }
+                if (!ovf)
+                    for (uint32_t q = lane; q < tracker.kept; q += kWave)
+                        cvals[(long)gi * kCoopWinCap + off_w + q] = wregion[q];
+                for (int q = tid; q < 256; q += nt) cwhist[gi * 256 + q] = whist[q];
+                if (tid == 0) {
+                    cinfo[gi * 4 + 0] = below;
+                    cinfo[gi * 4 + 1] = ovf ? 0u : kept;
+                    cinfo[gi * 4 + 2] = ovf ? 1u : 0u;
+                }
+            }
+            coop_barrier(cctr, ++epoch * (uint32_t)G, a.status);
+            // every score row
+            for (int k = tid; k < npad; k += nt)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) S8[(long)k * 8 + c] = cS[(long)k * 8 + c];
+            if (need_median) {
+                // the median from every workgroup's share: the same value in all
+                const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
+                const uint32_t rank = M > 0 ? (M - 1) / 2 : 0u;
+                float med = __builtin_nanf("");
+                bool done = M == 0;
+                if (!done && tracker.active) {
+                    // the workgroups' counts, staged in LDS (one global round trip)
+                    uint32_t *ci = (uint32_t *)redf;  // [16] kept, [16] below, [16] overflow
+                    if (tid < G) {
+                        ci[tid] = cinfo[tid * 4 + 1];
+                        ci[16 + tid] = cinfo[tid * 4 + 0];
+                        ci[32 + tid] = cinfo[tid * 4 + 2];
+                    }
+                    __syncthreads();
+                    uint32_t below = 0, nin = 0;
+                    bool ovf = false;
+                    for (int q = 0; q < G; ++q) {
+                        below += ci[16 + q];
+                        nin += ci[q];
+                        ovf |= ci[32 + q] != 0u;
+                    }
+                    tracker.density = uniform((float)nin / (tracker.hi - tracker.lo));
+                    if (!ovf && rank >= below && rank < below + nin && nin <= (uint32_t)L.win_cap) {
+                        // every workgroup's kept distances into this one's window
+                        // buffer (workgroup order), their histogram, then the
+                        // window selection of the one-workgroup kernel
+                        for (uint32_t e = tid; e < nin; e += nt) {
+                            uint32_t off = 0;
+                            int gg = 0;
+                            while (e >= off + ci[gg]) {
+                                off += ci[gg];
+                                ++gg;
+                            }
+                            WIN[e] = cvals[(long)gg * kCoopWinCap + (e - off)];
+                        }
+                        for (int q = tid; q < 256; q += nt) whist[q] = 0;
+                        if (tid == 0) red[10] = nin;
+                        __syncthreads();
+                        const uint32_t klo = __float_as_uint(tracker.lo);
+                        for (uint32_t e = tid; e < nin; e += nt)
+                            atomicAdd(&whist[(__float_as_uint(WIN[e]) - klo) >> tracker.wshift], 1u);
+                        __syncthreads();
+                        med = window_select(WIN, red + 10, 1, L.win_cap, rank - below, klo,
+                                            __float_as_uint(tracker.hi), tracker.wshift, whist, red, (float *)whist);
+                        done = true;
+                    } else if (!ovf && rank >= below && rank < below + nin) {
+                        // more kept distances than this buffer holds: the summed
+                        // histograms locate the median's bin, and only that bin's
+                        // distances are gathered
+                        const uint32_t r = rank - below;
+                        for (int q = tid; q < 256; q += nt) {
+                            uint32_t c = 0;
+                            for (int gg = 0; gg < G; ++gg) c += cwhist[gg * 256 + q];
+                            whist[q] = c;
+                        }
+                        __syncthreads();
+                        if (wave == 0) {
+                            typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+                            const u32x4_t c = *(const u32x4_t *)(whist + lane * 4);
+                            const uint32_t cnt = c[0] + c[1] + c[2] + c[3];
+                            const uint32_t incl = wave_incl_scan(cnt, lane);
+                            const uint32_t excl = incl - cnt;
+                            if (r >= excl && r < incl) {
+                                uint32_t rr = r - excl;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    if (rr < c[q]) {
+                                        red[2] = (uint32_t)(lane * 4 + q);
+                                        red[3] = rr;
+                                        red[4] = c[q];
+                                        break;
+                                    }
+                                    rr -= c[q];
+                                }
+                            }
+                            if (lane == 0) red[6] = 0;
+                        }
+                        __syncthreads();
+                        const uint32_t bin = red[2], rr = red[3], cb = red[4];
+                        if (cb <= (uint32_t)kWave) {
+                            float *cand = (float *)whist;  // the histogram is dead once the bin is known
+                            const uint32_t klo = __float_as_uint(tracker.lo);
+                            for (int gg = 0; gg < G; ++gg) {
+                                const uint32_t cnt = ci[gg];
+                                for (uint32_t q = tid; q < cnt; q += nt) {
+                                    const float v = cvals[(long)gg * kCoopWinCap + q];
+                                    if (((__float_as_uint(v) - klo) >> tracker.wshift) == bin)
+                                        cand[atomicAdd(&red[6], 1u)] = v;
+                                }
+                            }
+                            __syncthreads();
+                            if (wave == 0 && (uint32_t)lane < cb) {
+                                const float v = cand[lane];
+                                uint32_t less = 0, leq = 0;
+                                for (uint32_t q = 0; q < cb; ++q) {
+                                    const float u = cand[q];
+                                    less += u < v ? 1u : 0u;
+                                    leq += u <= v ? 1u : 0u;
+                                }
+                                if (less <= rr && rr < leq) red[5] = __float_as_uint(v);
+                            }
+                            __syncthreads();
+                            med = __uint_as_float(red[5]);
+                            done = true;
+                        }
+                        // a bin of more than 64 (heavy ties): the radix selection below
+                    }
+                }
+                if (!done) {
+                    // radix selection (digits of 11, 11 and 10 bits) over every
+                    // workgroup's share of the distances, one barrier per digit
+                    uint32_t prefix = 0, pmask = 0, rk = rank;
+                    for (int pass = 0; pass < 3; ++pass) {
+                        const int shift = pass == 0 ? 21 : pass == 1 ? 10 : 0;
+                        const uint32_t dmask = pass == 2 ? 0x3ffu : 0x7ffu;
+                        for (int q = tid; q < kBins; q += nt) hist[q] = 0;
+                        __syncthreads();
+                        auto count = [&](const f32x4 &Dv, bool diag) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const uint32_t key = __float_as_uint(fmax_(Dv[r], 0.f));
+                                const bool valid = !diag || ((diag_lanes(r) >> lane) & 1ull);
+                                if (valid && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
+                            }
+                        };
+                        TileWalker rw;
+                        rw.start(X8, npad, g, col, gi * nwaves + wave, G * nwaves);
+                        while (!rw.done()) {
+                            f32x4 D0, D1;
+                            rw.issue(X8, g, col, D0, D1);
+                            count(D0, false);
+                            if (rw.second()) count(D1, false);
+                            rw.advance(X8, g, col);
+                        }
+                        rw.diagonals(X8, g, col, count);
+                        __syncthreads();
+                        uint32_t *rh = crhist + (long)(pass & 1) * G * kBins;
+                        for (int q = tid; q < kBins; q += nt) rh[(long)gi * kBins + q] = hist[q];
+                        coop_barrier(cctr, ++epoch * (uint32_t)G, a.status);
+                        for (int q = tid; q < kBins; q += nt) {
+                            uint32_t c = 0;
+                            for (int gg = 0; gg < G; ++gg) c += rh[(long)gg * kBins + q];
+                            hist[q] = c;
+                        }
+                        __syncthreads();
+                        if (wave == 0) {
+                            constexpr int per = kBins / kWave;
+                            uint32_t cnt = 0;
+                            for (int q = 0; q < per; ++q) cnt += hist[lane * per + q];
+                            const uint32_t incl = wave_incl_scan(cnt, lane);
+                            const uint32_t excl = incl - cnt;
+                            if (lane == 0) { red[0] = 0; red[1] = 0; }
+                            __builtin_amdgcn_wave_barrier();
+                            if (rk >= excl && rk < incl) {
+                                uint32_t r2 = rk - excl;
+                                for (int q = 0; q < per; ++q) {
+                                    const uint32_t hq = hist[lane * per + q];
+                                    if (r2 < hq) { red[0] = (uint32_t)(lane * per + q); red[1] = r2; break; }
+                                    r2 -= hq;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        prefix |= red[0] << shift;
+                        rk = red[1];
+                        pmask |= dmask << shift;
+                        __syncthreads();
+                    }
+                    med = __uint_as_float(prefix);
+                }
+                med = uniform(med);
+                tracker.med2 = tracker.med1;
+                tracker.med1 = med;
+                tracker.have = tracker.have < 2 ? tracker.have + 1 : 2;
+                tracker.active = false;
+                h = uniform(bandwidth_from_median(med, n, a.bw_scale));
+            }
+        } else if (need_median) {
             const float med = tracker.finish(X8, n, npad, WIN, hist, red);
             h = uniform(bandwidth_from_median(med, n, a.bw_scale));
         }
-        if (a.h_out && tid == 0) a.h_out[(long)b * a.h_stride + it] = h;
+        if (a.h_out && tid == 0 && gi == 0) a.h_out[(long)b * a.h_stride + it] = h;
         const float beta = uniform((float)kLog2e / h);
 
         // (3) Stein direction
@@ -1004,7 +1401,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         constexpr int NG = D <= 3 ? 1 : 2;       // row groups of four in the sums
         constexpr int kOne = NG == 1 ? 3 : 7;    // row that sums kappa
         for (int k = tid; k < npad; k += nt) {
-            if (split) {
+            if (split && !COOP) {
                 // the score row of particle k from the splits' partial sums
                 // (rebased to their largest reference, summed in split order)
                 float srow[8];
@@ -1022,12 +1419,12 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                     if (a.trans_mode == 0) {
                         float mx = -inf;
                         for (int sp = 0; sp < L.ns_sc; ++sp)
-                            mx = fmax_(mx, PART[((long)sp * npad + k) * kPartStride + 8]);
+                            mx = fmax_(mx, PART[((long)sp * ntasks * 64 + k) * kPartStride + 8]);
                         float os[8];
 #pragma unroll
                         for (int c = 0; c < 8; ++c) os[c] = 0.f;
                         for (int sp = 0; sp < L.ns_sc; ++sp) {
-                            const float *pp = PART + ((long)sp * npad + k) * kPartStride;
+                            const float *pp = PART + ((long)sp * ntasks * 64 + k) * kPartStride;
                             const float w = R::exp2_(pp[8] - mx);
 #pragma unroll
                             for (int c = 0; c < 8; ++c) os[c] += pp[c] * w;
@@ -1060,7 +1457,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         for (int ts = 0; ts < TS; ++ts) {
             const int task = split ? (ts == 0 && sp_st < L.ns_st ? wave % ntasks : ntasks) : wave + ts * nwaves;
             if (task >= ntasks) break;
-            const int ibase = task * 64;
+            const int ibase = tbase + task * 64;
             // B columns (2 beta x_i, -beta in K-row 7); the accumulator starts
             // at -beta n_i, so a Gram tile holds the exponent
             // -beta |x_k - x_i|^2 of kappa directly
@@ -1130,7 +1527,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = ibase + 16 * q + col;
                 const float ksum = sum_row_quarters(O4[NG - 1][q][kOne - 4 * (NG - 1)]);
-                float *pp = PART + ((long)sp_st * npad + ii) * kPartStride;
+                float *pp = PART + ((long)sp_st * ntasks * 64 + (ii - tbase)) * kPartStride;
                 if (split && g == 0) pp[8] = ksum;
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2) {
@@ -1156,28 +1553,38 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         // the end of the iteration orders this before it)
         for (int q = tid; q < 256; q += nt) whist[q] = 0;
         if (split) {
-            // synchronous update from the splits' partial sums (split order),
-            // then the squared norm of the moved particle
-            for (int i = tid; i < n; i += nt) {
-                float tot[D];
-#pragma unroll
-                for (int c = 0; c < D; ++c) tot[c] = 0.f;
-                float ks = 0.f;
-                for (int sp = 0; sp < L.ns_st; ++sp) {
-                    const float *pp = PART + ((long)sp * npad + i) * kPartStride;
-#pragma unroll
-                    for (int c = 0; c < D; ++c) tot[c] += pp[c];
-                    ks += pp[8];
+            // synchronous update from the splits' partial sums (split order):
+            // the sums per (target, row) into S8 (dead after the Stein pass),
+            // then per target the update and the squared norm of the moved
+            // particle (the workgroup's targets; in COOP also to the exchange
+            // area)
+            const int ntl = ntasks * 64;
+            for (int e = tid; e < ntl * 8; e += nt) {
+                const int il = e >> 3, c = e & 7;
+                const int cc = c < D ? c : 8;  // row 7 (or the first unused one) carries the kernel sum
+                if (c < D || c == 7) {
+                    float acc = 0.f;
+                    for (int sp = 0; sp < L.ns_st; ++sp) acc += PART[((long)sp * ntl + il) * kPartStride + cc];
+                    S8[(long)(tbase + il) * 8 + c] = acc;
                 }
+            }
+            __syncthreads();
+            for (int il = tid; il < ntl; il += nt) {
+                const int i = tbase + il;
+                if (i >= n) continue;
+                const float ks = S8[(long)i * 8 + 7];
                 float nrm = 0.f;
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     const float xc = X8[(long)i * 8 + c];
-                    const float v = xc + a.step * ((tot[c] + c2 * xc * ks) * inv_n);
+                    const float v = xc + a.step * ((S8[(long)i * 8 + c] + c2 * xc * ks) * inv_n);
                     X8[(long)i * 8 + c] = v;
                     nrm += v * v;
                 }
                 X8[(long)i * 8 + 7] = nrm;
+                if (COOP)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) cX[(long)i * 8 + c] = X8[(long)i * 8 + c];
             }
         }
         // synchronous update, then unscaled squared norms for the next median
@@ -1214,10 +1621,19 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             }
         }
         __syncthreads();
+        if constexpr (COOP) {
+            // every workgroup's moved particles
+            coop_barrier(cctr, ++epoch * (uint32_t)G, a.status);
+            for (int i = tid; i < n; i += nt)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) X8[(long)i * 8 + c] = cX[(long)i * 8 + c];
+            __syncthreads();
+        }
     }
 
     bool bad = false;
-    for (int i = tid; a.do_svgd && i < n; i += nt) {
+    const int i_lo = COOP ? tbase : 0, i_hi = COOP ? min(n, tbase + ntasks * 64) : n;
+    for (int i = i_lo + tid; a.do_svgd && i < i_hi; i += nt) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             const float v = X8[(long)i * 8 + c] + ref[c];
@@ -1229,7 +1645,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     if (a.do_viterbi) {
         for (int j = tid; j < np; j += nt) PHP[j] = a.phi_prev ? a.phi_prev[(long)b * a.phi_prev_stride + j] : 0.f;
         __syncthreads();
-        for (int i = tid; i < n; i += nt) {
+        for (int i = i_lo + tid; i < i_hi; i += nt) {
             float xs[D], xa[D];
 #pragma unroll
             for (int c = 0; c < D; ++c) {
@@ -1272,6 +1688,15 @@ template <int KIND, int D, bool SPLIT>
 __global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma(StepArgs<float> a)
 {
     step_mfma_body<KIND, D, kMaxParticles / 64 / kMaxWaves, SPLIT>(a, blockIdx.x);
+}
+
+// Multi-workgroup step: workgroup blockIdx.x is group blockIdx.x % G of
+// sequence blockIdx.x / G (a cooperative launch: all resident at once).
+template <int KIND, int D>
+__global__ __launch_bounds__(kMaxWaves * 64) void k_step_mfma_coop(StepArgs<float> a, CoopArgs c)
+{
+    c.gi = (int)(blockIdx.x % (unsigned)c.G);
+    step_mfma_body<KIND, D, 1, true, true>(a, (int)(blockIdx.x / (unsigned)c.G), c);
 }
 
 } // namespace smsq

@@ -69,7 +69,7 @@ class SvgdOpts(C.Structure):
 
 
 KERNELS = {"rbf": 0, "imq": 1, "matern32": 2}
-STEP_KERNELS = {"auto": 0, "wave": 1, "valu": 2, "mfma": 3}
+STEP_KERNELS = {"auto": 0, "wave": 1, "valu": 2, "mfma": 3, "coop": 4}
 
 
 _lib = None
@@ -179,8 +179,8 @@ def opts(n_iter: int, step: float, bw_scale: float = 1.0, bw_mode: int = 0,
          trans_mode: int = 0, kernel=0, weights: int = 0, step_kernel=0) -> SvgdOpts:
     """SVGD options; kernel: 0/"rbf", 1/"imq", 2/"matern32"; weights 1: mixture
     weights from the previous step's forward-recursion scores (in the drivers);
-    step_kernel: 0/"auto", 1/"wave", 2/"valu", 3/"mfma" (forces a step kernel
-    wherever the shape fits it)."""
+    step_kernel: 0/"auto", 1/"wave", 2/"valu", 3/"mfma", 4/"coop" (forces a
+    step kernel wherever the shape fits it)."""
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     sk = STEP_KERNELS[step_kernel] if isinstance(step_kernel, str) else int(step_kernel)
     return SvgdOpts(int(n_iter), float(step), float(bw_scale), int(bw_mode), int(trans_mode), k, int(weights), sk)

@@ -202,7 +202,8 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
     (larger together than the 256 MB last-level cache): edges/s and GB/s."""
     stream = torch.cuda.current_stream()
     gen = torch.Generator(device="cuda").manual_seed(0)
-    A = [torch.randn((n, n), generator=gen, device="cuda") for _ in range(batch)]
+    AB = torch.randn((batch, n, n), generator=gen, device="cuda")
+    A = [AB[b] for b in range(batch)]
     ell = torch.randn(n, device="cuda")
     phi_prev = torch.randn(n, device="cuda")
     ws = smsq.workspace()
@@ -240,9 +241,37 @@ def lattice_bandwidth(torch, smsq, n: int, batch: int, reps: int = 5):
     dst = torch.empty_like(A[0])
     rowmax = lib_rate(lambda a: torch.amax(a, dim=1), n * n * 4 + n * 4)
     copy = lib_rate(lambda a: dst.copy_(a), 2 * n * n * 4)
+    # all lattices in one launch (smsq_viterbi_lattice_batch), and a device
+    # copy of the same 1 GiB in one call
+    ellb = ell.expand(batch, n).contiguous()
+    phib = phi_prev.expand(batch, n).contiguous()
+    for _ in range(2):
+        smsq.viterbi_lattice_batch("f32", phib, AB, ellb, want_flags=False, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record(stream)
+    for _ in range(reps):
+        smsq.viterbi_lattice_batch("f32", phib, AB, ellb, want_flags=False, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    secb = e0.elapsed_time(e1) / 1e3 / reps
+    dstb = torch.empty_like(AB)
+    for _ in range(2):
+        dstb.copy_(AB)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        dstb.copy_(AB)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copyb = 2 * AB.numel() * 4 / (e0.elapsed_time(e1) / 1e3 / reps) / 1e9
+    del dstb
     return {"n": n, "lattices": batch, "edges_per_s": n * n / sec, "us_per_launch": sec * 1e6,
             "GBps": nbytes / sec / 1e9, "frac_hbm": nbytes / sec / PEAK_HBM,
-            "bytes_per_launch": nbytes, "torch_rowmax_GBps": rowmax, "torch_copy_GBps": copy}
+            "bytes_per_launch": nbytes, "torch_rowmax_GBps": rowmax, "torch_copy_GBps": copy,
+            "batched": {"us_per_launch": secb * 1e6, "GBps": batch * nbytes / secb / 1e9,
+                        "frac_hbm": batch * nbytes / secb / PEAK_HBM, "edges_per_s": batch * n * n / secb,
+                        "torch_copy_GBps_same_bytes": copyb}}
 
 
 # Kernel / bandwidth / particle-count grid of the kernel ablation (Sec. V-E,
@@ -418,6 +447,28 @@ def pf_map_seq(torch, smsq):
         _, J, _ = recursion()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # the T + 1 launches captured once and replayed (wall per step = the
+        # kernels' time): every replay checked against the eager J
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            recursion()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            _, Jg, _ = recursion()
+        graph_ok = True
+        for _ in range(3):
+            graph.replay()
+            torch.cuda.synchronize()
+            graph_ok &= float(Jg.item()) == float(J.item())
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        wall_graph = time.perf_counter() - t0
+        graph_ok &= float(Jg.item()) == float(J.item())
+        del graph
         # kernel alone: one mid-sequence step launched back to back
         tm = T // 2
         ph = torch.zeros(n, dtype=torch.float32, device="cuda")
@@ -437,7 +488,8 @@ def pf_map_seq(torch, smsq):
         rows.append({"N": n, "kernel_us_per_step": us, "edges_per_s": edges / (us * 1e-6),
                      "counted_tflops": edges * (2 * d + 4) / (us * 1e-6) / 1e12,
                      "frac_fp32_peak": edges * (2 * d + 4) / (us * 1e-6) / PEAK_FP32,
-                     "wall_ms_per_step": wall / T * 1e3, "J": float(J.item()),
+                     "wall_ms_per_step": wall / T * 1e3, "graph_wall_ms_per_step": wall_graph / T * 1e3,
+                     "graph_replays_match_eager": graph_ok, "J": float(J.item()),
                      "paper_ms_per_step": PAPER_SCENARIO_C_MS["pf_map_seq"][n]})
     assert smsq.device_status(ws) == smsq.OK
     stein = []

@@ -224,6 +224,17 @@ smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t,
                                 void *phi, int32_t *psi, uint8_t *tie_flags, double tie_tol,
                                 void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Lattice-mode forward recursion (eq. forward_recursion, as
+ * smsq_viterbi_step with a lattice) of `batch` independent lattices in one
+ * launch: lattice [batch][n][n_prev], loglik [batch][n], phi_prev
+ * [batch][n_prev], outputs phi [batch][n], psi [batch][n] and tie_flags
+ * [batch][n] (or NULL), all C-contiguous.  batch <= 65535.  NaN sets
+ * SMSQ_ERR_NONFINITE in the workspace status. */
+smsq_status_t smsq_viterbi_lattice_batch(smsq_dtype_t dtype, int batch, int n, int n_prev, const void *lattice,
+                                         const void *loglik, const void *phi_prev, void *phi, int32_t *psi,
+                                         uint8_t *tie_flags, double tie_tol, void *ws, size_t ws_bytes,
+                                         hipStream_t stream);
+
 /* Backtracking (Sec. IV-B; Algorithm 2, step 4) over `batch` independent
  * sequences.  psi [batch, T, n]: row t-1 holds psi_t (entries of row 0 are
  * ignored).  phi_T [batch, n].  Outputs idx_out [batch, T] (entry t-1 is

@@ -342,29 +342,43 @@ template <typename T> long wide_lds_bytes(int n_prev, int d)
 }
 
 // 16 waves per workgroup for states of up to 8 dimensions (one means table
-// for all of them), 4 for larger states (register budget); a wave takes one
-// row i at a time
+// for all of them, eight rows at a time, two waves per row), 4 for larger
+// states (register budget)
 constexpr int wide_threads(int d) { return d <= 8 ? 1024 : 256; }
-constexpr int kWideMaxBlocks = 2048;
+constexpr int kWideMaxBlocks = 512;
+constexpr long kWideStaticLds = 512;   // the kernel's row-merge slots (FP64: 320 bytes), rounded up
 
+template <typename T, int KIND, int D, bool FLAGS>
+smsq_status_t launch_viterbi_wide_flags(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                        const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                        void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                        hipStream_t s)
+{
+    constexpr int NT = wide_threads(D);
+    auto fn = &k_viterbi_particle_wide<T, KIND, D, NT, FLAGS>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] { attr_err = allow_big_lds(fn, kWideStaticLds); });
+    if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
+    const int rows_per_block = NT / kWave / 2;
+    const int grid = std::min((n + rows_per_block - 1) / rows_per_block, kWideMaxBlocks);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), (size_t)wide_lds_bytes<T>(n_prev, D), s,
+                       make_dev_model<T>(d), t, n, n_prev, (const T *)x_prev, (const T *)phi_prev, (const T *)z,
+                       mask, (const T *)x, (T *)phi, psi, flags, (T)tie_tol, status);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+// the runner-up is tracked only when tie flags are requested
 template <typename T, int KIND, int D>
 smsq_status_t launch_viterbi_wide_kd(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
                                      const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
                                      void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
                                      hipStream_t s)
 {
-    constexpr int NT = wide_threads(D);
-    auto fn = &k_viterbi_particle_wide<T, KIND, D, NT>;
-    static std::once_flag once;
-    static hipError_t attr_err = hipSuccess;
-    std::call_once(once, [&] { attr_err = allow_big_lds(fn); });
-    if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
-    const int rows_per_block = NT / kWave;
-    const int grid = std::min((n + rows_per_block - 1) / rows_per_block, kWideMaxBlocks);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), (size_t)wide_lds_bytes<T>(n_prev, D), s,
-                       make_dev_model<T>(d), t, n, n_prev, (const T *)x_prev, (const T *)phi_prev, (const T *)z,
-                       mask, (const T *)x, (T *)phi, psi, flags, (T)tie_tol, status);
-    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+    return flags ? launch_viterbi_wide_flags<T, KIND, D, true>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi,
+                                                                psi, flags, tie_tol, status, s)
+                 : launch_viterbi_wide_flags<T, KIND, D, false>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi,
+                                                                 psi, flags, tie_tol, status, s);
 }
 
 template <typename T>
@@ -968,13 +982,35 @@ smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t, i
     // particle mode: the chip-wide kernel, whose LDS holds the means table
     const smsq_model_desc_t &d = model->desc;
     if (dtype == SMSQ_F64) {
-        if (wide_lds_bytes<double>(n_prev, d.d) > kLdsLimit) return SMSQ_ERR_UNSUPPORTED;
+        if (wide_lds_bytes<double>(n_prev, d.d) > kLdsLimit - kWideStaticLds) return SMSQ_ERR_UNSUPPORTED;
         return launch_viterbi_wide<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,
                                            tie_tol, status_ptr(ws), stream);
     }
-    if (wide_lds_bytes<float>(n_prev, d.d) > kLdsLimit) return SMSQ_ERR_UNSUPPORTED;
+    if (wide_lds_bytes<float>(n_prev, d.d) > kLdsLimit - kWideStaticLds) return SMSQ_ERR_UNSUPPORTED;
     return launch_viterbi_wide<float>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,
                                       tie_tol, status_ptr(ws), stream);
+}
+
+smsq_status_t smsq_viterbi_lattice_batch(smsq_dtype_t dtype, int batch, int n, int n_prev, const void *lattice,
+                                         const void *loglik, const void *phi_prev, void *phi, int32_t *psi,
+                                         uint8_t *tie_flags, double tie_tol, void *ws, size_t ws_bytes,
+                                         hipStream_t stream)
+{
+    if (!dtype_ok(dtype) || batch < 1 || batch > 65535 || n < 1 || n_prev < 1 || !lattice || !loglik ||
+        !phi_prev || !phi || !psi || !(tie_tol >= 0.0))
+        return SMSQ_ERR_INVALID;
+    if (!ws || ws_bytes < kHeader) return SMSQ_ERR_WORKSPACE;
+    const int rows_per_block = 2;  // four waves, two per row
+    const dim3 grid((n + rows_per_block - 1) / rows_per_block, batch), block(4 * kWave);
+    if (dtype == SMSQ_F64)
+        hipLaunchKernelGGL(k_viterbi_lattice<double>, grid, block, 0, stream, n, n_prev, (const double *)lattice,
+                           (const double *)loglik, (const double *)phi_prev, (double *)phi, psi, tie_flags, tie_tol,
+                           status_ptr(ws));
+    else
+        hipLaunchKernelGGL(k_viterbi_lattice<float>, grid, block, 0, stream, n, n_prev, (const float *)lattice,
+                           (const float *)loglik, (const float *)phi_prev, (float *)phi, psi, tie_flags,
+                           (float)tie_tol, status_ptr(ws));
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
 
 smsq_status_t smsq_backtrack(smsq_dtype_t dtype, int batch, int T, int n, int d, const int32_t *psi,

@@ -656,6 +656,17 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
     constexpr int kRowsPerBlock = 4 / kSplit;  // four waves per workgroup
     __shared__ T sbest[4], ssecond[4];
     __shared__ int sarg[4];
+    // lattice blockIdx.y of a batch: consecutive [n][n_prev] lattices, [n]
+    // observation terms, [n_prev] previous scores and [n] outputs
+    {
+        const long bb = blockIdx.y;
+        A += bb * (long)n * n_prev;
+        ell += bb * n;
+        phi_prev += bb * n_prev;
+        phi += bb * n;
+        psi += bb * n;
+        if (flags) flags += bb * n;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     const int part = w % kSplit;
@@ -737,14 +748,25 @@ __global__ __launch_bounds__(256) void k_viterbi_lattice(int n, int n_prev, cons
 // phi_i = log p(z_t | x_t^i) + c_{i psi_i} (eq. forward_recursion).  Each
 // workgroup evaluates the transition means of all previous particles once
 // into LDS (centred on f_t(x_{t-1}^0) and scaled by sqrt(log2 e / (2 q)), as
-// in the step kernels), then its waves take rows i in turn: the lanes walk
-// j in ascending order, the wave merges (lowest index on equal scores) and
-// lane 0 adds the observation term.  Bound by the vector ALU: (2d + 4) flops
-// and one compare per edge; the LDS table is read, never HBM, inside the
-// edge loop.  NT threads per workgroup: 1024 for small states, so that one
-// table serves sixteen waves.
+// in the step kernels); then each row i is taken by two waves, one per half
+// of the previous particles (merged through LDS, the lower half winning
+// equal scores).  A lane walks its indices j in ascending order in kChains
+// independent chains (j = lane + 64 (kChains u + v)), so that the loads and
+// arithmetic of different chains overlap; chains and lanes merge with the
+// lowest index winning equal scores, and the first lane adds the observation
+// term.  FLAGS: the runner-up is tracked for the tie flags.  Bound by the
+// vector ALU: (2d + 4) flops and one compare per edge; the LDS table is
+// read, never HBM, inside the edge loop.  NT threads per workgroup: 1024
+// for small states, so that one table serves eight rows at a time.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND, int D, int NT>
+template <typename T> __device__ __forceinline__ void argbest_push_best(ArgBest<T> &a, T c, int j)
+{
+    const bool up = c > a.best;
+    a.best = up ? c : a.best;
+    a.arg = up ? j : a.arg;
+}
+
+template <typename T, int KIND, int D, int NT, bool FLAGS>
 __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int t, int n, int n_prev,
                                                                const T *__restrict__ x_prev,
                                                                const T *__restrict__ phi_prev,
@@ -755,11 +777,15 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
     using F = Family<T, KIND, D>;
     using R = RealOps<T>;
     constexpr int DP = dpad(D);
+    constexpr int kChains = 4;
+    constexpr int kPairs = NT / kWave / 2;   // rows at a time per workgroup
     extern __shared__ __align__(16) unsigned char smem[];
     T *sm = (T *)smem;                                       // [n_prev][DP] scaled centred means
     T *sp = (T *)(smem + align16((long)n_prev * DP * sizeof(T)));   // [n_prev] phi_{t-1}
+    __shared__ T s_best[NT / kWave], s_second[NT / kWave];
+    __shared__ int s_arg[NT / kWave];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & (kWave - 1);
+    const int lane = tid & (kWave - 1), w = wave_id(), half = w & 1;
 
     T cen[D], rs[D];
     {
@@ -782,39 +808,66 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
     __syncthreads();
 
     bool nan_seen = false;
-    const int waves = gridDim.x * (nt / kWave);
-    for (int i = blockIdx.x * (nt / kWave) + wave_id(); i < n; i += waves) {
-        T xi[D], xs[D];
+    const int jmid = (n_prev + 1) / 2;
+    const int j0 = half ? jmid : 0, j1 = half ? n_prev : jmid;
+    // the same trip count in every wave of the workgroup (barriers inside)
+    for (int ib = blockIdx.x * kPairs; ib < n; ib += gridDim.x * kPairs) {
+        const int i = ib + (w >> 1);
+        const bool live = i < n;
+        ArgBest<T> a{-R::inf(), -R::inf(), 0x7fffffff};
+        T xi[D];
+        if (live) {
+            T xs[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            xi[c] = x[(long)i * D + c];
-            xs[c] = (xi[c] - cen[c]) * rs[c];
-        }
-        ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};
-        for (int j = lane; j < n_prev; j += kWave) {
-            T mj[DP];
-            lds_load<T, DP>(sm + (long)j * DP, mj);
-            T q2 = 0;
+            for (int c = 0; c < D; ++c) {
+                xi[c] = x[(long)i * D + c];
+                xs[c] = (xi[c] - cen[c]) * rs[c];
+            }
+            ArgBest<T> ab[kChains];
 #pragma unroll
-            for (int c = 0; c < D; ++c) { const T r = xs[c] - mj[c]; q2 += r * r; }
-            const T cij = (m.log_z - (T)kLn2 * q2) + sp[j];
-            nan_seen |= (cij != cij);
-            if (j == lane) { ab.best = cij; ab.arg = j; }
-            else argbest_push(ab, cij, j);
+            for (int v = 0; v < kChains; ++v) ab[v] = ArgBest<T>{-R::inf(), -R::inf(), 0x7fffffff};
+            for (int jb = j0 + lane; jb < j1; jb += kWave * kChains) {
+#pragma unroll
+                for (int v = 0; v < kChains; ++v) {
+                    const int j = jb + kWave * v;
+                    if (j < j1) {
+                        T mj[DP];
+                        lds_load<T, DP>(sm + (long)j * DP, mj);
+                        T q2 = 0;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) { const T r = xs[c] - mj[c]; q2 += r * r; }
+                        const T cij = (m.log_z - (T)kLn2 * q2) + sp[j];
+                        nan_seen |= (cij != cij);
+                        if (FLAGS) argbest_push(ab[v], cij, j);
+                        else argbest_push_best(ab[v], cij, j);
+                    }
+                }
+            }
+            a = ab[0];
+#pragma unroll
+            for (int v = 1; v < kChains; ++v) a = argbest_merge(a, ab[v]);
+            a = wave_argbest(a);
+            if (lane == 0) {
+                s_best[w] = a.best;
+                s_second[w] = a.second;
+                s_arg[w] = a.arg;
+            }
         }
-        ab = wave_argbest(ab);
-        if (lane == 0) {
+        __syncthreads();
+        if (live && half == 0 && lane == 0) {
+            a = argbest_merge(a, ArgBest<T>{s_best[w + 1], s_second[w + 1], s_arg[w + 1]});
             const T ell = F::loglik(m, z, mask, xi);
-            const T ph = ab.best + ell;
+            const T ph = a.best + ell;
             phi[i] = ph;
-            psi[i] = ab.arg;
+            psi[i] = a.arg == 0x7fffffff ? 0 : a.arg;
             if (flags) {
-                const T mag = ab.best < 0 ? -ab.best : ab.best;
+                const T mag = a.best < 0 ? -a.best : a.best;
                 const T sc = mag > (T)1 ? mag : (T)1;
-                flags[i] = (n_prev > 1 && ab.second >= ab.best - tie_tol * sc) ? 1 : 0;
+                flags[i] = (n_prev > 1 && a.second >= a.best - tie_tol * sc) ? 1 : 0;
             }
             nan_seen |= (ell != ell) || (ph != ph);
         }
+        __syncthreads();
     }
     if (__any(nan_seen) && lane == 0) atomicOr(status, STATUS_NONFINITE);
 }

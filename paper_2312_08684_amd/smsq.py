@@ -30,7 +30,7 @@ SYMBOLS = [
     "smsq_init_mlp_create", "smsq_init_mlp_destroy", "smsq_init_mlp_params", "smsq_init_mlp_sync",
     "smsq_init_set_create", "smsq_init_set_destroy", "smsq_init_features", "smsq_init_mlp_forward",
     "smsq_init_mlp_backward", "smsq_init_mixture_nll", "smsq_init_mlp_train_step", "smsq_init_mlp_sample",
-    "smsq_batch_plan_set_init", "smsq_run_sequence_noalloc",
+    "smsq_batch_plan_set_init", "smsq_run_sequence_noalloc", "smsq_viterbi_lattice_batch",
 ]
 
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     L.smsq_init_mlp_train_step.argtypes = [vp, vp, i32, i32, dbl, vp, vp]
     L.smsq_init_mlp_sample.argtypes = [vp, vp, i32, i32, vp, vp]
     L.smsq_batch_plan_set_init.argtypes = [vp, vp]
+    L.smsq_viterbi_lattice_batch.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, dbl, vp, C.c_size_t, vp]
     L.smsq_run_sequence_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, vp, u64, C.POINTER(SvgdOpts), vp, vp,
                                             vp, vp, vp]
     for name in SYMBOLS:
@@ -288,6 +289,27 @@ def viterbi_step(model: Optional[Model], dtype, t: int, phi_prev: torch.Tensor, 
                                   float(tie_tol), _ptr(ws, torch.uint8, "ws"), ws.numel(),
                                   _stream(stream))
     _check(st, "smsq_viterbi_step")
+    return phi, psi, flags
+
+
+def viterbi_lattice_batch(dtype, phi_prev: torch.Tensor, lattice: torch.Tensor, loglik: torch.Tensor,
+                          tie_tol: float = 0.0, want_flags: bool = True, ws: Optional[torch.Tensor] = None,
+                          stream=None):
+    """Lattice-mode forward recursion of B lattices in one launch
+    (smsq_viterbi_lattice_batch): phi_prev [B, n_prev], lattice [B, n, n_prev],
+    loglik [B, n].  Returns (phi [B, n], psi [B, n], flags [B, n] or None)."""
+    td = torch_dtype(dtype)
+    B, n, n_prev = lattice.shape
+    dev = lattice.device
+    phi = torch.empty((B, n), dtype=td, device=dev)
+    psi = torch.empty((B, n), dtype=torch.int32, device=dev)
+    flags = torch.empty((B, n), dtype=torch.uint8, device=dev) if want_flags else None
+    ws = workspace(device=dev) if ws is None else ws
+    st = load().smsq_viterbi_lattice_batch(_dt(dtype), B, n, n_prev, _ptr(lattice, td, "lattice"),
+                                           _ptr(loglik, td, "loglik"), _ptr(phi_prev, td, "phi_prev"), _ptr(phi),
+                                           _ptr(psi), _ptr(flags), float(tie_tol), _ptr(ws, torch.uint8, "ws"),
+                                           ws.numel(), _stream(stream))
+    _check(st, "smsq_viterbi_lattice_batch")
     return phi, psi, flags
 
 

@@ -87,6 +87,31 @@ def test_viterbi_lattice_nan_sets_status(n_prev):
     assert smsq.device_status(ws) == smsq.ERR_NONFINITE
 
 
+@pytest.mark.parametrize("n,n_prev", [(100, 37), (64, 128), (7, 1)])
+def test_viterbi_lattice_batch_f64_bit_exact(n, n_prev):
+    """Several lattices in one launch (smsq_viterbi_lattice_batch): each
+    bit-exact against the oracle, as the single-lattice call is."""
+    announce("viterbi lattice batch f64", n, n_prev)
+    rng = np.random.default_rng(n + 3 * n_prev)
+    B = 3
+    A = rng.normal(size=(B, n, n_prev)) * 5
+    ell = rng.normal(size=(B, n))
+    php = rng.normal(size=(B, n_prev)) * 10
+    A[1, 0, :] = -np.inf
+    if n_prev > 3:
+        A[2, 1, 1] = A[2, 1, 2] = A[2, 1].max() + 1.0
+        php[2, 1] = php[2, 2]
+    ws = smsq.workspace()
+    phi, psi, fl = smsq.viterbi_lattice_batch("f64", dev(php, torch.float64), dev(A, torch.float64),
+                                              dev(ell, torch.float64), tie_tol=1e-9, ws=ws)
+    assert smsq.device_status(ws) == smsq.OK
+    for b in range(B):
+        phi_o, psi_o, fl_o, _ = O.viterbi_lattice(A[b], ell[b], php[b], tie_tol=1e-9)
+        assert np.array_equal(host(psi)[b], psi_o)
+        assert np.array_equal(host(phi)[b], phi_o)
+        assert np.array_equal(host(fl)[b], fl_o)
+
+
 @pytest.mark.parametrize("n,n_prev", [(33, 65), (512, 512), (64, 4096), (300, 1028)])
 def test_viterbi_lattice_f32(n, n_prev):
     announce("viterbi lattice f32", n, n_prev)

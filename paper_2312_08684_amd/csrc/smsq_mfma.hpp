@@ -132,18 +132,24 @@ struct MfmaLds {
     }
 };
 
+// K-chunks of the distance and Gram tiles.  Eight K-rows (two MFMAs) hold
+// up to seven coordinates and the norm in row 7; with K4 (d <= 3) four
+// K-rows (one MFMA) hold up to three coordinates and the norm in row 3.
+// ka(g): the particle-row column that K-row g (of the first chunk) reads.
+template <bool K4> __device__ __forceinline__ int gram_col(int g) { return K4 && g == 3 ? 7 : g; }
+
 // Visits the squared distances D_ik = n_i + n_k - 2 x_i . x_k of every pair
 // i < k from 16x16 MFMA Gram tiles: the A rows are the source particles with
-// their norm n_k in column 7 (padding for d <= 7), the B columns are
-// -2 x_i with a 1 in row 7, and the accumulator starts at n_i, so the tile
-// holds the distances themselves.  Each wave takes whole rows of tiles
+// their norm n_k in the last K-row (coordinates zero-padded), the B columns
+// are -2 x_i with a 1 in that row, and the accumulator starts at n_i, so
+// the tile holds the distances themselves.  Each wave takes whole rows of tiles
 // (target tile ib, source tiles kb >= ib) and issues the MFMAs of four source
 // tiles before using any result.  fn(Dv, diag) receives the four distances
 // of a lane for one tile (k = 16 kb + 4 g + r, i = 16 ib + col); in the
 // diagonal tile (diag true) only the lanes of diag_lanes(r) hold pairs k > i.
 // Pad particles have n = +inf, so their distances are +inf.  The median
 // window pass (TileWalker) computes every distance the same way.
-template <typename Fn>
+template <bool K4, typename Fn>
 __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn &&fn, int vwave = -1, int nvwaves = 0)
 {
     constexpr int kBatch = 4;
@@ -159,11 +165,12 @@ __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn 
         if (ib >= nt16) break;
         const int i0 = ib * 16;
         const float *xi = X8 + (long)(i0 + col) * 8;
-        const float bi0 = -2.f * xi[g];
+        const int ka = gram_col<K4>(g);
+        const float bi0 = K4 && g == 3 ? 1.f : -2.f * xi[g];
         const float bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
         const float nni = xi[7];
         const f32x4 cn = {nni, nni, nni, nni};
-        fn(mfma16(xi[4 + g], bi1, mfma16(xi[g], bi0, cn)), true);
+        fn(K4 ? mfma16(xi[ka], bi0, cn) : mfma16(xi[4 + g], bi1, mfma16(xi[g], bi0, cn)), true);
         // A operands of a batch of source tiles; past the row's end a tile is
         // repeated and its results are not used
         float a0[kBatch], a1[kBatch];
@@ -171,15 +178,15 @@ __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn 
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const float *xk = X8 + (long)(min(kb + u, nt16 - 1) * 16 + col) * 8;
-                a0[u] = xk[g];
-                a1[u] = xk[4 + g];
+                a0[u] = xk[ka];
+                a1[u] = K4 ? 0.f : xk[4 + g];
             }
         };
         load_batch(ib + 1);
         for (int kb = ib + 1; kb < nt16; kb += kBatch) {
             f32x4 G[kBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) G[u] = mfma16(a1[u], bi1, mfma16(a0[u], bi0, cn));
+            for (int u = 0; u < kBatch; ++u) G[u] = K4 ? mfma16(a0[u], bi0, cn) : mfma16(a1[u], bi1, mfma16(a0[u], bi0, cn));
             load_batch(kb + kBatch);  // next batch's loads overlap this batch's work
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
@@ -193,6 +200,7 @@ __device__ __forceinline__ void for_each_distance(const float *X8, int npad, Fn 
 // Exact order statistic `rank` of the squared distances by radix selection
 // over the bit patterns (digits of 11, 11 and 10 bits); every pass recomputes
 // the distances.  In diagonal tiles only pairs k > i count.
+template <bool K4>
 __device__ float radix_median_mfma(const float *X8, int npad, uint32_t rank, uint32_t *hist,
                                    uint32_t *red)
 {
@@ -203,7 +211,7 @@ __device__ float radix_median_mfma(const float *X8, int npad, uint32_t rank, uin
         const uint32_t dmask = pass == 2 ? 0x3ffu : 0x7ffu;
         for (int b = tid; b < kBins; b += nt) hist[b] = 0;
         __syncthreads();
-        for_each_distance(X8, npad, [&](const f32x4 &Dv, bool diag) {
+        for_each_distance<K4>(X8, npad, [&](const f32x4 &Dv, bool diag) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t key = __float_as_uint(fmax_(Dv[r], 0.f));
@@ -349,11 +357,12 @@ __device__ float window_select(const float *buf, const uint32_t *wcnt, int nregi
 // One wave's walk over its share of the off-diagonal distance tiles (the
 // rows of tiles of for_each_distance, in the same order, source tiles
 // kb > ib), two source tiles kb, kb + 1 per step.  Holds the current row's
-// B operand (-2 x_i with a 1 in row 7) and the target norms as the
+// B operand (-2 x_i with a 1 in the norm row) and the target norms as the
 // accumulator input.  The diagonal tiles of the wave's rows are visited by
 // diagonals().  In chunk mode (the multi-workgroup walk: more waves than
 // rows) virtual wave v of nv takes the v-th of nv equal contiguous runs of
 // the off-diagonal tiles listed row by row, and every nv-th diagonal tile.
+template <bool K4>
 struct TileWalker {
     int nt16, nwaves, wave, rr, ib, kb, left;
     bool chunk;
@@ -364,7 +373,7 @@ struct TileWalker {
     __device__ void load_row(const float *X8, int g, int col)
     {
         const float *xi = X8 + (long)(ib * 16 + col) * 8;
-        bi0 = -2.f * xi[g];
+        bi0 = K4 && g == 3 ? 1.f : -2.f * xi[g];
         bi1 = g == 3 ? 1.f : -2.f * xi[4 + g];
         const float nni = xi[7];
         cn = f32x4{nni, nni, nni, nni};
@@ -419,10 +428,13 @@ struct TileWalker {
         const int k0 = min(kb, nt16 - 1), k1 = min(kb + 1, nt16 - 1);
         const float *x0 = X8 + (long)(k0 * 16 + col) * 8;
         const float *x1 = X8 + (long)(k1 * 16 + col) * 8;
-        D0 = mfma16(x0[g], bi0, cn);
-        D1 = mfma16(x1[g], bi0, cn);
-        D0 = mfma16(x0[4 + g], bi1, D0);
-        D1 = mfma16(x1[4 + g], bi1, D1);
+        const int ka = gram_col<K4>(g);
+        D0 = mfma16(x0[ka], bi0, cn);
+        D1 = mfma16(x1[ka], bi0, cn);
+        if (!K4) {
+            D0 = mfma16(x0[4 + g], bi1, D0);
+            D1 = mfma16(x1[4 + g], bi1, D1);
+        }
     }
     __device__ void advance(const float *X8, int g, int col)
     {
@@ -440,7 +452,7 @@ struct TileWalker {
             if (ib >= nt16) break;
             load_row(X8, g, col);
             const float *xk = X8 + (long)(ib * 16 + col) * 8;
-            fn(mfma16(xk[4 + g], bi1, mfma16(xk[g], bi0, cn)), true);
+            fn(K4 ? mfma16(xk[gram_col<K4>(g)], bi0, cn) : mfma16(xk[4 + g], bi1, mfma16(xk[g], bi0, cn)), true);
         }
     }
 };
@@ -459,7 +471,7 @@ struct MedianTracker {
     int have;        // number of medians recorded (0, 1, 2+)
     bool active;     // a window pass is under way this iteration
     float lo, hi;    // the window
-    uint32_t below;  // per lane: distances below lo
+    uint32_t below;  // per wave: distances below lo
     uint32_t kept;   // per wave: distances kept (kOverflow once the region is full)
     uint32_t wshift; // window histogram bin of a kept distance: (key - key(lo)) >> wshift
     uint32_t *whist; // its 256 counters (zero before the walk)
@@ -496,11 +508,12 @@ struct MedianTracker {
     static constexpr uint32_t kOverflow = 0x40000000u;
 
     // One tile of distances (diag: only pairs k > i count).  The common case
-    // is vector work only: a per-lane count of the distances below lo, and
-    // one test for a distance inside the window, on the bit-pattern offsets
-    // key(D) - key(lo) (unsigned, below span exactly when lo <= D < hi; a
-    // negative D or NaN never is).  Only a tile holding window distances
-    // appends them to the wave's region.
+    // is two comparisons per distance, D < lo and D < hi, as wave masks: the
+    // wave's count below lo is the population count of the first (scalar
+    // work), and D lies in the window [lo, hi) where the second holds and the
+    // first does not (a NaN is in neither; -0 counts as 0).  Only a tile
+    // holding window distances appends them to the wave's region, binned by
+    // key(D) - key(lo) on the bit patterns.
     __device__ void visit(f32x4 Dv, bool diag, float *region)
     {
         if (diag) {
@@ -509,23 +522,27 @@ struct MedianTracker {
             for (int r = 0; r < 4; ++r)
                 if (!((diag_lanes(r) >> l) & 1ull)) Dv[r] = __builtin_huge_valf();
         }
-        const uint32_t klo = __float_as_uint(lo), span = __float_as_uint(hi) - klo;
-        uint32_t u[4];
+        unsigned long long win[4], any = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            below += Dv[r] < lo ? 1u : 0u;
-            u[r] = __float_as_uint(Dv[r]) - klo;
+            const unsigned long long mlo = __builtin_amdgcn_ballot_w64(Dv[r] < lo);
+            const unsigned long long mhi = __builtin_amdgcn_ballot_w64(Dv[r] < hi);
+            below += (uint32_t)__builtin_popcountll(mlo);
+            win[r] = mhi & ~mlo;
+            any |= win[r];
         }
-        const uint32_t um = min(min(u[0], u[1]), min(u[2], u[3]));
-        if (__builtin_amdgcn_ballot_w64(um < span)) {
+        if (any) {
+            const uint32_t klo = __float_as_uint(lo);
+            const int l = threadIdx.x & 63;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const unsigned long long mk = __builtin_amdgcn_ballot_w64(u[r] < span);
+                const unsigned long long mk = win[r];
                 const uint32_t cnt = (uint32_t)__builtin_popcountll(mk);
                 const bool fits = kept + cnt <= (uint32_t)wcap;  // kOverflow stays
-                if (fits && u[r] < span) {
-                    region[kept + lanes_below(mk)] = Dv[r] + 0.f;  // no -0
-                    atomicAdd(&whist[u[r] >> wshift], 1u);
+                if (fits && ((mk >> l) & 1ull)) {
+                    const float v = Dv[r] + 0.f;  // no -0
+                    region[kept + lanes_below(mk)] = v;
+                    atomicAdd(&whist[(__float_as_uint(v) - klo) >> wshift], 1u);
                 }
                 kept = fits ? kept + cnt : kOverflow;
             }
@@ -534,6 +551,7 @@ struct MedianTracker {
 
     // After every wave has visited its tiles (no barrier needed before the
     // call).  Returns the exact lower median.
+    template <bool K4>
     __device__ float finish(const float *X8, int n, int npad, float *buf, uint32_t *hist, uint32_t *red)
     {
         const uint32_t M = (uint32_t)((long)n * (n - 1) / 2);
@@ -547,9 +565,8 @@ struct MedianTracker {
         float med = 0.f;
         bool done = false;
         if (active) {
-            const uint32_t bw = wave_sum(below);
             if (lane == 0) {
-                wbelow[wave] = bw;
+                wbelow[wave] = below;
                 wcnt[wave] = kept;
             }
             __syncthreads();
@@ -568,7 +585,7 @@ struct MedianTracker {
             }
             __syncthreads();
         }
-        if (!done) med = radix_median_mfma(X8, npad, rank, hist, red);
+        if (!done) med = radix_median_mfma<K4>(X8, npad, rank, hist, red);
         med = uniform(med);
         med2 = med1;
         med1 = med;
@@ -587,31 +604,34 @@ struct MedianTracker {
 // next call, so it never waits.  A wave ahead of its slowest mate yields:
 // priority 3 within 2 steps of it, 2 within 4, 1 within 8, else 0.
 struct ProgressBalance {
-    uint32_t *row, *own;  // the SIMD's four counts; this wave's count
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    // the words are addressed as LDS (ds instructions, no vector-memory wait)
+    typedef __attribute__((address_space(3))) volatile uint32_t lds_u32;
+    typedef __attribute__((address_space(3))) volatile u32x4_t lds_u32x4;
+    lds_u32x4 *row;       // the SIMD's four counts
+    lds_u32 *own;         // this wave's count
     uint32_t done;        // steps of this wave so far (all passes)
-    uint32_t s0, s1, s2, s3;
+    uint32_t mn;          // the least of the four counts at the last step
 
     // prog: 16 LDS words set to ~0 (absent waves never lag) before a barrier
     __device__ void init(uint32_t *prog, int wave)
     {
-        row = prog + (wave & 3) * 4;
-        own = row + (wave >> 2);
+        row = (lds_u32x4 *)(prog + (wave & 3) * 4);
+        own = (lds_u32 *)(prog + (wave & 3) * 4 + (wave >> 2));
         done = 0;
-        s0 = s1 = s2 = s3 = 0;
+        mn = 0;
     }
     __device__ void step()
     {
         done += 2;
-        const uint32_t mn = __builtin_amdgcn_readfirstlane(min(min(s0, s1), min(s2, s3)));
         const uint32_t ahead = done - min(mn, done);
         if (ahead <= 2) __builtin_amdgcn_s_setprio(3);
         else if (ahead <= 4) __builtin_amdgcn_s_setprio(2);
         else if (ahead <= 8) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
-        *(volatile uint32_t *)own = done;
-        typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-        const u32x4_t p = *(const volatile u32x4_t *)row;
-        s0 = p[0]; s1 = p[1]; s2 = p[2]; s3 = p[3];
+        *own = done;
+        const u32x4_t p = *row;
+        mn = __builtin_amdgcn_readfirstlane(min(min(p[0], p[1]), min(p[2], p[3])));
     }
 };
 
@@ -719,6 +739,9 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     static_assert(D <= 7, "K-column 7 carries the norms");
     extern __shared__ __align__(16) unsigned char smem[];
     static_assert(!COOP || SPLIT, "the multi-workgroup mode splits the sources");
+    // d <= 3: four K-rows per tile (coordinates and the norm or constant in
+    // row 3) and four rows of sums, one MFMA each where d <= 7 takes two
+    constexpr bool K4 = D <= 3;
     const int n = a.n, np = a.n_prev;
     const int G = COOP ? cx.G : 1, gi = COOP ? cx.gi : 0;
     const int npad0 = (n + 63) / 64 * 64;
@@ -888,7 +911,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         // the score pass, which leaves the particles unchanged
         const bool need_median = a.bw_mode == 0 || it == 0;
         if (need_median) tracker.plan(whist);
-        TileWalker walker;
+        TileWalker<K4> walker;
         if (tracker.active) {
             if (COOP)
                 walker.start(X8, npad, g, col, gi * nwaves + wave, G * nwaves);
@@ -916,7 +939,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 for (int q = 0; q < kTilesPerWave; ++q) {
                     const int kk = kbase + 16 * q + col;
                     const int kd0 = g, kd1 = 4 + g;
-                    bx0[q] = kd0 < D ? X8[(long)kk * 8 + kd0] * rs[kd0] : 0.f;
+                    bx0[q] = kd0 < D ? X8[(long)kk * 8 + kd0] * rs[kd0] : (K4 && kd0 == 3 ? 1.f : 0.f);
                     bx1[q] = kd1 < D ? X8[(long)kk * 8 + kd1] * rs[kd1] : (kd1 == 7 ? 1.f : 0.f);
                     cm[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
@@ -926,26 +949,32 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 // block b = l / 4 takes B = that register and A = table rows
                 // 4 ch + l % 4 of its source; lane l of O4[ch][q] accumulates
                 // rows 4 ch + i (register i) of particle kbase + 16 q + l % 16
-                // over the source quarter l / 16.
-                f32x4 O4[2][kTilesPerWave];
+                // over the source quarter l / 16.  With K4 one group holds
+                // rows 2 mh_0..2 and the 1 (table row 7) as its row 3.
+                constexpr int NGS = K4 ? 1 : 2;
+                f32x4 O4[NGS][kTilesPerWave];
 #pragma unroll
-                for (int ch = 0; ch < 2; ++ch)
+                for (int ch = 0; ch < NGS; ++ch)
 #pragma unroll
                     for (int q = 0; q < kTilesPerWave; ++q) O4[ch][q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 // four consecutive sources 4 (l / 16) + r of rows l % 4, 4 + l % 4
-                const float *vt0 = VT + (long)(lane & 3) * nppad + 4 * g;
+                const float *vt0 = VT + (long)(K4 && (lane & 3) == 3 ? 7 : (lane & 3)) * nppad + 4 * g;
                 const float *vt1 = VT + (long)(4 + (lane & 3)) * nppad + 4 * g;
                 // logit A operands: K-row g (2 mh), K-row 4 + g (row 7 of the
-                // table, the 1, becomes c'_j in K-row 7)
-                const float *am0p = VT + (long)g * nppad + col;
+                // table, the 1, becomes c'_j in K-row 7); with K4, c'_j in
+                // K-row 3 of the one chunk
+                const float *am0p = VT + (long)(K4 && g == 3 ? 8 : g) * nppad + col;
                 const float *am1p = VT + (long)(g == 3 ? 8 : 4 + g) * nppad + col;
                 // logits of tile jt relative to the column references
                 auto logits = [&](int jt, f32x4 (&Lo)[kTilesPerWave]) {
-                    const float am0 = am0p[jt * 16], am1 = am1p[jt * 16];
+                    const float am0 = am0p[jt * 16];
 #pragma unroll
                     for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am0, bx0[q], cm[q]);
+                    if (!K4) {
+                        const float am1 = am1p[jt * 16];
 #pragma unroll
-                    for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am1, bx1[q], Lo[q]);
+                        for (int q = 0; q < kTilesPerWave; ++q) Lo[q] = mfma16(am1, bx1[q], Lo[q]);
+                    }
                 };
                 // Raises the reference of the columns of a relative logit tile
                 // whose maximum lies more than 2^8 above it (all four lane
@@ -974,8 +1003,8 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
 #pragma unroll
                             for (int q = 0; q < kTilesPerWave; ++q) {
                                 const float sc = R::exp2_(-shq[q]);
-                                O4[0][q] *= sc;
-                                O4[1][q] *= sc;
+#pragma unroll
+                                for (int ch = 0; ch < NGS; ++ch) O4[ch][q] *= sc;
                             }
                         }
                     }
@@ -989,8 +1018,9 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                     auto body = [&](int jt, f32x4 (&T)[kTilesPerWave]) {
                         f32x4 W0, W1;
                         if (WALK) walker.issue(X8, g, col, W0, W1);
-                        const f32x4 va0 = *(const f32x4 *)(vt0 + jt * 16);
-                        const f32x4 va1 = *(const f32x4 *)(vt1 + jt * 16);
+                        f32x4 va[NGS];
+                        va[0] = *(const f32x4 *)(vt0 + jt * 16);
+                        if (!K4) va[NGS - 1] = *(const f32x4 *)(vt1 + jt * 16);
 #pragma unroll
                         for (int q = 0; q < kTilesPerWave; ++q)
 #pragma unroll
@@ -998,10 +1028,11 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
 #pragma unroll
-                            for (int q = 0; q < kTilesPerWave; ++q) {
-                                O4[0][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(va0[r], T[q][r], O4[0][q], 0, 0, 0);
-                                O4[1][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(va1[r], T[q][r], O4[1][q], 0, 0, 0);
-                            }
+                            for (int q = 0; q < kTilesPerWave; ++q)
+#pragma unroll
+                                for (int ch = 0; ch < NGS; ++ch)
+                                    O4[ch][q] = __builtin_amdgcn_mfma_f32_4x4x1f32(va[ch][r], T[q][r], O4[ch][q], 0,
+                                                                                   0, 0);
                         if (WALK && !walker.done()) {
                             tracker.visit(W0, false, wregion);
                             if (walker.second()) tracker.visit(W1, false, wregion);
@@ -1048,7 +1079,15 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     osum[i] = sum_quarters_scatter(O4[0][0][i], O4[0][1][i], O4[0][2][i], O4[0][3][i]);
-                    osum[4 + i] = sum_quarters_scatter(O4[1][0][i], O4[1][1][i], O4[1][2][i], O4[1][3][i]);
+                    if (!K4)
+                        osum[4 + i] = sum_quarters_scatter(O4[NGS - 1][0][i], O4[NGS - 1][1][i], O4[NGS - 1][2][i],
+                                                           O4[NGS - 1][3][i]);
+                }
+                if (K4) {
+                    // the sum of e sits in row 3; rows 3..6 carry nothing
+                    osum[7] = osum[3];
+#pragma unroll
+                    for (int i = 3; i < 7; ++i) osum[i] = 0.f;
                 }
                 const int qq = lane >> 4;
                 float cref = cm[0][0];
@@ -1175,9 +1214,8 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             // this workgroup's share of the window pass: counts, its kept
             // distances in wave order, its histogram
             if (need_median && tracker.active) {
-                const uint32_t bw = wave_sum(tracker.below);
                 if (lane == 0) {
-                    red[26 + wave] = bw;
+                    red[26 + wave] = tracker.below;
                     red[10 + wave] = tracker.kept;
                 }
                 __syncthreads();
@@ -1331,7 +1369,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                                 if (valid && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
                             }
                         };
-                        TileWalker rw;
+                        TileWalker<K4> rw;
                         rw.start(X8, npad, g, col, gi * nwaves + wave, G * nwaves);
                         while (!rw.done()) {
                             f32x4 D0, D1;
@@ -1384,7 +1422,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 h = uniform(bandwidth_from_median(med, n, a.bw_scale));
             }
         } else if (need_median) {
-            const float med = tracker.finish(X8, n, npad, WIN, hist, red);
+            const float med = tracker.finish<K4>(X8, n, npad, WIN, hist, red);
             h = uniform(bandwidth_from_median(med, n, a.bw_scale));
         }
         if (a.h_out && tid == 0 && gi == 0) a.h_out[(long)b * a.h_stride + it] = h;
@@ -1474,7 +1512,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
 #pragma unroll
             for (int q = 0; q < kTilesPerWave; ++q) {
                 const int ii = ibase + 16 * q + col;
-                bi0[q] = twob * X8[(long)ii * 8 + g];
+                bi0[q] = K4 && g == 3 ? -beta : twob * X8[(long)ii * 8 + g];
                 bi1[q] = g == 3 ? -beta : twob * X8[(long)ii * 8 + 4 + g];
                 const float nb = -beta * X8[(long)ii * 8 + 7];
                 cb[q] = f32x4{nb, nb, nb, nb};
@@ -1482,14 +1520,18 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 for (int gg = 0; gg < NG; ++gg) O4[gg][q] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
             const float *vbase = S8 + (long)(4 * g) * 8 + (lane & 3);
-            // Gram tiles: A rows (x_k, n_k in K-column 7)
+            // Gram tiles: A rows (x_k, n_k in the last K-row)
+            const int ka = gram_col<K4>(g);
             auto gram = [&](int kt, f32x4 (&Go)[kTilesPerWave]) {
                 const float *xr = X8 + (long)(kt * 16 + col) * 8;
-                const float ak0 = xr[g], ak1 = xr[4 + g];
+                const float ak0 = xr[ka];
 #pragma unroll
                 for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak0, bi0[q], cb[q]);
+                if (!K4) {
+                    const float ak1 = xr[4 + g];
 #pragma unroll
-                for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak1, bi1[q], Go[q]);
+                    for (int q = 0; q < kTilesPerWave; ++q) Go[q] = mfma16(ak1, bi1[q], Go[q]);
+                }
             };
             // one source tile: the Gram tiles of kt + 1 are issued before the
             // exponentials of tile kt (the last tile repeats, unused); the two

@@ -13,7 +13,7 @@
 //     logit_kj = 2 mh_j . xh_k + c_j - |mh_j|^2 (log2 units; the common
 //     -|xh_k|^2 drops out), as 16x16 logit tiles [xh_k, 1] . [2 mh_j, c'_j],
 //     a per-particle reference maximum raised only when a tile exceeds it by
-//     2^8, exp2 on the VALU, and the weighted sums sum_j e_kj [2 mh_j, 1]
+//     2^64, exp2 on the VALU, and the weighted sums sum_j e_kj [2 mh_j, 1]
 //     accumulated by MFMA;
 //   * Stein direction: Gram tiles give the kernel argument
 //     2 beta x_k . x_i - beta n_k (the norm rides in the free eighth
@@ -81,7 +81,10 @@ constexpr int kVtRows = 9;        // rows of the transition-mean table: 2 mh (7)
 constexpr int kWinCap = 8192;     // capacity of the median window buffer (floats)
 constexpr int kWinRegion = kWinCap / kMaxWaves; // per-wave share of the window buffer
 constexpr int kWinTarget = 512;   // aimed-for number of distances in the window
-constexpr float kRescaleGap = 8.f; // log2 headroom before the softmax reference moves
+// log2 headroom before the softmax reference moves: a tile's exponentials
+// stay at most 2^64 and a row's sums of up to 1024 of them far below the
+// FP32 range, while a column's reference seldom moves after its first tile
+constexpr float kRescaleGap = 64.f;
 constexpr int kProgSlot = 48;      // first of the 16 wave-progress words in the reduction slots
 constexpr int kPartStride = 9;     // floats per particle in a split's partial sums (8 rows + 1)
 
@@ -977,7 +980,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                     }
                 };
                 // Raises the reference of the columns of a relative logit tile
-                // whose maximum lies more than 2^8 above it (all four lane
+                // whose maximum lies more than 2^64 above it (all four lane
                 // groups of a column agree), rescaling the sums and the tile;
                 // with `first`, sets the references to the tile's maxima.  The
                 // test compares the bit patterns as integers: for a positive
@@ -1013,11 +1016,10 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                 // window pass ride along.
                 auto score_loop = [&](auto walk_tag) {
                     constexpr bool WALK = decltype(walk_tag)::value;
-                    // exponentials and sums of a relative logit tile; the
-                    // median walk's tiles ride along
-                    auto body = [&](int jt, f32x4 (&T)[kTilesPerWave]) {
-                        f32x4 W0, W1;
-                        if (WALK) walker.issue(X8, g, col, W0, W1);
+                    // exponentials and sums of a relative logit tile; with
+                    // WALK the median walk's two tiles W0, W1 (issued before
+                    // the logits are checked) are visited after the sums
+                    auto body = [&](int jt, f32x4 (&T)[kTilesPerWave], const f32x4 &W0, const f32x4 &W1) {
                         f32x4 va[NGS];
                         va[0] = *(const f32x4 *)(vt0 + jt * 16);
                         if (!K4) va[NGS - 1] = *(const f32x4 *)(vt1 + jt * 16);
@@ -1040,23 +1042,28 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         }
                     };
                     if (WALK) {
-                        // one buffer: the walk's registers leave no room for two
-                        f32x4 T[kTilesPerWave];
+                        // one buffer (the walk's registers leave no room for
+                        // two); the walk's MFMAs go between the logits and
+                        // their check, which waits for them
+                        f32x4 T[kTilesPerWave], W0, W1;
                         logits(j0, T);
+                        walker.issue(X8, g, col, W0, W1);
                         rebase(T, true);
-                        body(j0, T);
+                        body(j0, T, W0, W1);
                         for (int jt = j0 + 1; jt < j1; ++jt) {
                             if ((jt & 1) == 0) bal.step();
                             logits(jt, T);
+                            walker.issue(X8, g, col, W0, W1);
                             rebase(T, false);
-                            body(jt, T);
+                            body(jt, T, W0, W1);
                         }
                     } else {
                         // the logits of tile jt + 1 are issued (and checked)
                         // around the exponentials and sums of tile jt
+                        const f32x4 none = {0.f, 0.f, 0.f, 0.f};
                         auto tile = [&](int jt, f32x4 (&T)[kTilesPerWave], f32x4 (&Tn)[kTilesPerWave]) {
                             logits(min(jt + 1, j1 - 1), Tn);
-                            body(jt, T);
+                            body(jt, T, none, none);
                             rebase(Tn, false);
                         };
                         f32x4 TA[kTilesPerWave], TB[kTilesPerWave];

@@ -349,6 +349,9 @@ SVGD_CASES = [
     # iteration counts (one teacher-forced step)
     ("range2d", 256, 256, 50, 0.005),
     ("cv4d", 512, 512, 50, 0.005),
+    # d <= 3 with sixteen 64-particle tasks (one MFMA per tile, no source
+    # splits) and a ragged tail
+    ("range2d", 1000, 600, 10, 0.005),
 ]
 
 

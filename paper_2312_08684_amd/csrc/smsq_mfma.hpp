@@ -364,11 +364,13 @@ __device__ float window_select(const float *buf, const uint32_t *wcnt, int nregi
 // accumulator input.  The diagonal tiles of the wave's rows are visited by
 // diagonals().  In chunk mode (the multi-workgroup walk: more waves than
 // rows) virtual wave v of nv takes the v-th of nv equal contiguous runs of
-// the off-diagonal tiles listed row by row, and every nv-th diagonal tile.
-template <bool K4>
+// the off-diagonal tiles listed row by row, and every nv-th diagonal tile
+// (CHUNK: the mode is fixed per kernel, so neither walk carries the other's
+// state through its loops).
+template <bool K4, bool CHUNK>
 struct TileWalker {
+    static constexpr bool chunk = CHUNK;
     int nt16, nwaves, wave, rr, ib, kb, left;
-    bool chunk;
     float bi0, bi1;
     f32x4 cn;
 
@@ -384,7 +386,6 @@ struct TileWalker {
     __device__ void start(const float *X8, int npad, int g, int col, int vwave = -1, int nvwaves = 0)
     {
         nt16 = npad / 16;
-        chunk = nvwaves > 0;
         nwaves = chunk ? nvwaves : (int)(blockDim.x >> 6);
         wave = chunk ? vwave : wave_id();
         if (!chunk) {
@@ -914,7 +915,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
         // the score pass, which leaves the particles unchanged
         const bool need_median = a.bw_mode == 0 || it == 0;
         if (need_median) tracker.plan(whist);
-        TileWalker<K4> walker;
+        TileWalker<K4, COOP> walker;
         if (tracker.active) {
             if (COOP)
                 walker.start(X8, npad, g, col, gi * nwaves + wave, G * nwaves);
@@ -1376,7 +1377,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                                 if (valid && (key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
                             }
                         };
-                        TileWalker<K4> rw;
+                        TileWalker<K4, true> rw;
                         rw.start(X8, npad, g, col, gi * nwaves + wave, G * nwaves);
                         while (!rw.done()) {
                             f32x4 D0, D1;

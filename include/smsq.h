@@ -394,7 +394,12 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
  * each workgroup shape (16 waves, one 64-particle task per wave; 8 waves,
  * two tasks per wave) and grid size from the occupancy of that shape, times
  * the steps after the first with HIP events, and keeps the faster shape.
- * Synchronises the stream. (host) */
+ * Synchronises the stream.  The choice and its timings are remembered for
+ * the rest of the process per device architecture (name and compute units)
+ * and plan shape (every sequence's family, d, n, T, L and proposal switch
+ * in order, the learned-initialisation setting, the number of steps): a
+ * later plan of the same shape on the same kind of device takes them
+ * without running anything. (host) */
 smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t plan, int steps, hipStream_t stream);
 
 /* Runs every sequence end to end on `stream` (asynchronous).  use_graph:

@@ -9,6 +9,8 @@
 #include <mutex>
 #include <new>
 #include <algorithm>
+#include <map>
+#include <string>
 #include <vector>
 #include <type_traits>
 
@@ -1226,11 +1228,65 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     return SMSQ_OK;
 }
 
+namespace {
+
+// The tuner's choices for this process, keyed by the device architecture
+// (name and compute units) and the plan's shape: every sequence's family,
+// size, length, iteration count and proposal switch in plan order, the
+// learned-initialisation setting and the number of tuned steps.
+struct TuneRecord {
+    int waves;
+    double ms[2];
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneRecord> g_tune;
+
+std::string tune_key(const smsq_batch_plan_s *p, int steps)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the shape
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (const SeqDesc &q : p->host) {
+        mix((uint64_t)q.code);
+        mix((uint64_t)q.d);
+        mix((uint64_t)q.n);
+        mix((uint64_t)q.T);
+        mix((uint64_t)q.n_iter);
+        mix((uint64_t)q.use_proposal);
+    }
+    mix((uint64_t)(p->mlp != nullptr));
+    mix((uint64_t)steps);
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/%d/%d/%016llx", prop.gcnArchName, prop.multiProcessorCount, p->count,
+             (unsigned long long)h);
+    return std::string(buf);
+}
+
+} // namespace
+
 smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t p, int steps, hipStream_t stream)
 {
     if (!p || steps < 2) return SMSQ_ERR_INVALID;
     const int k = std::min(steps, p->T_max);
     if (k < 2) return SMSQ_OK;
+    const std::string key = tune_key(p, k);
+    if (!key.empty()) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            p->waves = it->second.waves;
+            p->tuned[0] = it->second.ms[0];
+            p->tuned[1] = it->second.ms[1];
+            return SMSQ_OK;
+        }
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return SMSQ_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1259,6 +1315,10 @@ smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t p, int steps, hipStream_t s
     (void)hipEventDestroy(e1);
     if (st != SMSQ_OK) return st;
     p->waves = p->tuned[1] < p->tuned[0] ? 8 : 16;
+    if (!key.empty()) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = TuneRecord{p->waves, {p->tuned[0], p->tuned[1]}};
+    }
     return SMSQ_OK;
 }
 

@@ -120,6 +120,25 @@ def test_batch_autotuner_and_8_wave_shape():
     _check_equal(plan, models, opts, seqs)
 
 
+def test_batch_autotuner_remembers_plan_shapes():
+    """A second plan of the same shape takes the first one's tuned shape
+    and timings without running the tuner again; another shape is timed."""
+    models, opts, seqs = _build(MIX[:5], base_seed=55)
+    first = smsq.BatchPlan(models, opts, seqs).tune(steps=3)
+    again = smsq.BatchPlan(models, opts, seqs).tune(steps=3)
+    print("tuner", first, again, flush=True)
+    assert again["tuned_ms"] == first["tuned_ms"] and again["waves"] == first["waves"]
+    other = list(MIX[:5])
+    other[1] = (other[1][0], other[1][1] - 64, other[1][2], other[1][3])
+    models2, opts2, seqs2 = _build(other, base_seed=55)
+    plan = smsq.BatchPlan(models2, opts2, seqs2)
+    info = plan.tune(steps=3)
+    assert info["tuned_ms"] != first["tuned_ms"]
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == smsq.OK
+
+
 def test_batch_graph_replays_match_eager():
     models, opts, seqs = _build(MIX[:6], base_seed=80)
     plan = smsq.BatchPlan(models, opts, seqs)

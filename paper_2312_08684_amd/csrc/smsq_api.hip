@@ -904,6 +904,49 @@ __global__ void k_status_out(const uint32_t *__restrict__ word, int32_t *__restr
 
 } // namespace
 
+namespace {
+
+// The tuner's choices for this process, keyed by the device architecture
+// (name and compute units) and the plan's shape: every sequence's family,
+// size, length, iteration count and proposal switch in plan order, the
+// learned-initialisation setting and the number of tuned steps.
+struct TuneRecord {
+    int waves;
+    double ms[2];
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneRecord> g_tune;
+
+std::string tune_key(const smsq_batch_plan_s *p, int steps)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the shape
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (const SeqDesc &q : p->host) {
+        mix((uint64_t)q.code);
+        mix((uint64_t)q.d);
+        mix((uint64_t)q.n);
+        mix((uint64_t)q.T);
+        mix((uint64_t)q.n_iter);
+        mix((uint64_t)q.use_proposal);
+    }
+    mix((uint64_t)(p->mlp != nullptr));
+    mix((uint64_t)steps);
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/%d/%d/%016llx", prop.gcnArchName, prop.multiProcessorCount, p->count,
+             (unsigned long long)h);
+    return std::string(buf);
+}
+
+} // namespace
+
 extern "C" {
 
 smsq_status_t smsq_model_create(const smsq_model_desc_t *desc, smsq_model_t *out)
@@ -1227,49 +1270,6 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
     *out = p;
     return SMSQ_OK;
 }
-
-namespace {
-
-// The tuner's choices for this process, keyed by the device architecture
-// (name and compute units) and the plan's shape: every sequence's family,
-// size, length, iteration count and proposal switch in plan order, the
-// learned-initialisation setting and the number of tuned steps.
-struct TuneRecord {
-    int waves;
-    double ms[2];
-};
-std::mutex g_tune_mu;
-std::map<std::string, TuneRecord> g_tune;
-
-std::string tune_key(const smsq_batch_plan_s *p, int steps)
-{
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over the shape
-    auto mix = [&](uint64_t v) {
-        for (int b = 0; b < 8; ++b) {
-            h ^= (v >> (8 * b)) & 0xffu;
-            h *= 1099511628211ull;
-        }
-    };
-    for (const SeqDesc &q : p->host) {
-        mix((uint64_t)q.code);
-        mix((uint64_t)q.d);
-        mix((uint64_t)q.n);
-        mix((uint64_t)q.T);
-        mix((uint64_t)q.n_iter);
-        mix((uint64_t)q.use_proposal);
-    }
-    mix((uint64_t)(p->mlp != nullptr));
-    mix((uint64_t)steps);
-    char buf[160];
-    snprintf(buf, sizeof buf, "%s/%d/%d/%016llx", prop.gcnArchName, prop.multiProcessorCount, p->count,
-             (unsigned long long)h);
-    return std::string(buf);
-}
-
-} // namespace
 
 smsq_status_t smsq_batch_plan_tune(smsq_batch_plan_t p, int steps, hipStream_t stream)
 {

@@ -787,8 +787,14 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
     const float inf = R::inf();
 
     for (int o = tid; o < 16; o += nt) red[kProgSlot + o] = 0xffffffffu;
+    // wave priorities by progress: with whole tasks per wave (the arm7
+    // shape: 64 tile steps per pass) the balancing pays (5%), and in the
+    // multi-workgroup step (2% at arm7 B = 1); one workgroup with sources
+    // split among waves runs short passes where it costs more than it saves
+    // (range2d 5%), so that kernel leaves it out
     ProgressBalance bal;
     bal.init(red + kProgSlot, wave);
+    constexpr bool kBalance = !SPLIT || COOP;
     for (int o = tid; o < m.obs_dim; o += nt) sz[o] = a.z[(long)b * a.z_stride + o];
     const uint8_t *mk = nullptr;
     if (a.mask) {
@@ -1052,7 +1058,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         rebase(T, true);
                         body(j0, T, W0, W1);
                         for (int jt = j0 + 1; jt < j1; ++jt) {
-                            if ((jt & 1) == 0) bal.step();
+                            if (kBalance && (jt & 1) == 0) bal.step();
                             logits(jt, T);
                             walker.issue(X8, g, col, W0, W1);
                             rebase(T, false);
@@ -1071,7 +1077,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
                         logits(j0, TA);
                         rebase(TA, true);
                         for (int jt = j0; jt < j1; jt += 2) {
-                            bal.step();
+                            if (kBalance) bal.step();
                             tile(jt, TA, TB);
                             if (jt + 1 < j1) tile(jt + 1, TB, TA);
                         }
@@ -1568,7 +1574,7 @@ __device__ __forceinline__ void step_mfma_body(const StepArgs<float> &a, const i
             f32x4 GA[kTilesPerWave], GB[kTilesPerWave];
             gram(k0, GA);
             for (int kt = k0; kt < k1; kt += 2) {
-                bal.step();
+                if (kBalance) bal.step();
                 tile(kt, GA, GB);
                 if (kt + 1 < k1) tile(kt + 1, GB, GA);
             }

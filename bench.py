@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--batched-seqs", type=int, default=4096, help="ragged-mix sequences (0: skip)")
     p.add_argument("--train-steps", type=int, default=4000)
     p.add_argument("--train-seqs", type=int, default=700, help="plain sequences whose steps train the proposal")
+    p.add_argument("--train-L", type=float, default=2.0,
+                   help="iterations of the plain training runs, as a multiple of each family's L")
     p.add_argument("--ablation-mc", type=int, default=50, help="sequences per kernel-ablation row (0: skip)")
     p.add_argument("--scenario-b-mc", type=int, default=10, help="pose-scenario sequences per row (0: skip)")
     p.add_argument("--scenario-d-mc", type=int, default=20, help="14-D arm sequences per row (0: skip)")
@@ -632,7 +634,7 @@ def sweep(torch, smsq):
     return out
 
 
-def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
+def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int, train_L: float = 2.0):
     """Ragged mix (family uniform over the four, N from {32..1024}, T in
     [50, 200]) as one batched plan per run, hipGraph replay, autotuned.  The
     plain method at the full iteration count gives the reference J of every
@@ -662,7 +664,7 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
     # family on a validation mix
     t0 = time.perf_counter()
     tspec = LI.mix(train_seqs, seed=1, T_lo=20, T_hi=40)
-    tplan, _, _, tmodels, tseqs = LI.run(tspec, 1.0, warm=False)
+    tplan, _, _, tmodels, tseqs = LI.run(tspec, train_L, warm=False)
     ex = LI.examples(tplan, tspec, tseqs)
     n_examples = len(ex)
     mlp = smsq.InitMLP(seed=5, max_batch=max(4096, count))
@@ -724,7 +726,8 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int):
                                     "frac_fp32_peak": flops_full / t_full / PEAK_FP32,
                                     "note": "whole plan wall time (graph replay), one run at the full L"},
             "proposal": {"train_sequences": len(tspec), "train_T": "20..40", "train_examples": n_examples,
-                         "train_steps": train_steps, "train_nll": losses, "gate_per_family": gain,
+                         "train_steps": train_steps, "train_L": train_L, "train_nll": losses,
+                         "gate_per_family": gain,
                          "setup_seconds": t_train},
             "match_rule": "J >= J_plain_full - 1e-3 max(|J_plain_full|, T)"}
 
@@ -882,7 +885,7 @@ def main():
     if args.latency:
         out["latency"] = latency(torch, smsq)
     if args.batched_seqs > 0:
-        out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs)
+        out["batched"] = batched_mix(torch, smsq, args.batched_seqs, args.train_steps, args.train_seqs, args.train_L)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(out), flush=True)

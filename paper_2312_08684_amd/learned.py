@@ -5,9 +5,11 @@ batched ragged runs (``smsq.BatchPlan``); every numerical step runs in the
 library's kernels.  The recipe:
 
 1. run the plain method (predictive initialisation) on a training mix of
-   sequences; every step t >= 2 of every sequence gives one example: the
-   previous step's particles and forward-recursion scores, the observation,
-   and the particles SVGD converged to (the proposal's target);
+   sequences, with more iterations than the runs it will serve (twice each
+   family's L in the benchmark, so the targets are nearer convergence);
+   every step t >= 2 of every sequence gives one example: the previous
+   step's particles and forward-recursion scores, the observation, and the
+   particles SVGD converged to (the proposal's target);
 2. train the network by Adam on the mixture NLL of those targets;
 3. on a validation mix, compare the MAP log-posterior J reached with a
    reduced iteration count from the proposal against the predictive

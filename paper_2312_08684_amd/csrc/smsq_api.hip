@@ -410,6 +410,91 @@ smsq_status_t launch_viterbi_wide(const smsq_model_desc_t &d, int t, int n, int 
     return SMSQ_ERR_INVALID;
 }
 
+// Rows per workgroup pass of the particle-mode forward recursion without tie
+// flags: the largest of 16, 8, 4 that still gives each compute unit a
+// workgroup (n / RP >= ~240), 4 below that
+inline int rows_pass(int n) { return n >= 16 * 240 ? 16 : n >= 8 * 240 ? 8 : 4; }
+// its LDS: D + 1 arrays of n_prev entries rounded up to rows_table_align(RP)
+inline int rows_npad(int n_prev, int rp)
+{
+    const int a = rows_table_align(rp);
+    return (n_prev + a - 1) / a * a;
+}
+template <typename T> long rows_lds_bytes(int n, int n_prev, int d)
+{
+    return (long)(d + 1) * rows_npad(n_prev, rows_pass(n)) * sizeof(T);
+}
+constexpr long kRowsStaticLds = 4096;   // row-merge slots and observation (FP64: 3360 bytes), rounded up
+
+// states for which the 16-rows kernel runs without register spills (its
+// eight-edge tiles); the others take the two-waves-per-row kernel
+template <typename T> constexpr bool rows_fits(int d) { return sizeof(T) == 4 ? d <= 8 : d <= 2; }
+
+template <typename T, int KIND, int D, int RP>
+smsq_status_t launch_viterbi_rows_rp(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                     const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                     void *phi, int32_t *psi, uint32_t *status, hipStream_t s)
+{
+    auto fn = &k_viterbi_particle_rows<T, KIND, D, RP>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] { attr_err = allow_big_lds(fn, kRowsStaticLds); });
+    if (attr_err != hipSuccess) return SMSQ_ERR_HIP;
+    const int npad = rows_npad(n_prev, RP);
+    const int grid = std::min((n + RP - 1) / RP, kWideMaxBlocks);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kRowsWaves * kWave), (size_t)rows_lds_bytes<T>(n, n_prev, D), s,
+                       make_dev_model<T>(d), t, n, n_prev, npad, (const T *)x_prev, (const T *)phi_prev,
+                       (const T *)z, mask, (const T *)x, (T *)phi, psi, status);
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+template <typename T, int KIND, int D>
+smsq_status_t launch_viterbi_rows_kd(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                     const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                     void *phi, int32_t *psi, uint32_t *status, hipStream_t s)
+{
+    if constexpr (!rows_fits<T>(D)) {
+        return SMSQ_ERR_UNSUPPORTED;
+    } else {
+        switch (rows_pass(n)) {
+        case 16:
+            return launch_viterbi_rows_rp<T, KIND, D, 16>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi,
+                                                          status, s);
+        case 8:
+            return launch_viterbi_rows_rp<T, KIND, D, 8>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi,
+                                                         status, s);
+        default:
+            return launch_viterbi_rows_rp<T, KIND, D, 4>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi,
+                                                         status, s);
+        }
+    }
+}
+
+template <typename T>
+smsq_status_t launch_viterbi_rows(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                  const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                  void *phi, int32_t *psi, uint32_t *status, hipStream_t s)
+{
+#define SMSQ_ROWS(K, DD) launch_viterbi_rows_kd<T, K, DD>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi, status, s)
+    switch (d.kind) {
+    case SMSQ_MODEL_GROWTH1D: return SMSQ_ROWS(GROWTH1D, 1);
+    case SMSQ_MODEL_RANGE2D: return SMSQ_ROWS(RANGE2D, 2);
+    case SMSQ_MODEL_CV4D: return SMSQ_ROWS(CV4D, 4);
+    case SMSQ_MODEL_ARM7: return SMSQ_ROWS(ARM7, 7);
+    case SMSQ_MODEL_SE2: return SMSQ_ROWS(SE2, 3);
+    case SMSQ_MODEL_ARM14: return SMSQ_ROWS(ARM14, 14);
+    case SMSQ_MODEL_LINGAUSS:
+        switch (d.d) {
+        case 1: return SMSQ_ROWS(LINGAUSS, 1);
+        case 2: return SMSQ_ROWS(LINGAUSS, 2);
+        case 3: return SMSQ_ROWS(LINGAUSS, 3);
+        case 4: return SMSQ_ROWS(LINGAUSS, 4);
+        }
+    }
+#undef SMSQ_ROWS
+    return SMSQ_ERR_INVALID;
+}
+
 bool opts_ok(const smsq_svgd_opts_t *o)
 {
     return o && o->n_iter >= 0 && std::isfinite(o->step) && finite_pos(o->bw_scale) &&
@@ -1024,8 +1109,19 @@ smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t, i
         return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
     }
     if (!model || t < 1 || !x_prev || !z_t || !x) return SMSQ_ERR_INVALID;
-    // particle mode: the chip-wide kernel, whose LDS holds the means table
+    // particle mode: chip-wide kernels whose LDS holds the means table; 4..16
+    // rows per workgroup pass without tie flags, two waves per row with them
     const smsq_model_desc_t &d = model->desc;
+    if (!tie_flags) {
+        if (dtype == SMSQ_F64 && rows_fits<double>(d.d) &&
+            rows_lds_bytes<double>(n, n_prev, d.d) <= kLdsLimit - kRowsStaticLds)
+            return launch_viterbi_rows<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi,
+                                               status_ptr(ws), stream);
+        if (dtype == SMSQ_F32 && rows_fits<float>(d.d) &&
+            rows_lds_bytes<float>(n, n_prev, d.d) <= kLdsLimit - kRowsStaticLds)
+            return launch_viterbi_rows<float>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi,
+                                              status_ptr(ws), stream);
+    }
     if (dtype == SMSQ_F64) {
         if (wide_lds_bytes<double>(n_prev, d.d) > kLdsLimit - kWideStaticLds) return SMSQ_ERR_UNSUPPORTED;
         return launch_viterbi_wide<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,

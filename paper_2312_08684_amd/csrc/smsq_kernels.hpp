@@ -873,6 +873,284 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
 }
 
 // ---------------------------------------------------------------------------
+// Particle-mode forward recursion without tie flags, rows in blocks of RP.
+// The edge score above is ranked in log2 units, in one fixed direct form:
+// c'_ij = s_j - |y_i - m_j|^2 with s_j = (log_z + phi_{t-1}(j)) log2 e, the
+// particles y_i and transition means m_j centred on f_t(x_{t-1}^0) and scaled
+// by sqrt(log2 e / (2 q)), so that c'_ij = c_ij log2 e; each squared
+// coordinate difference is one fused multiply-subtract, 2d instructions per
+// edge.  The winner's score is taken back to natural-log units (c = ln2 c').
+// LDS holds the workgroup's table tile by tile: for each run of kTile
+// consecutive indices, D + 1 arrays of kTile entries (the means coordinate
+// by coordinate, then s_j), so that one base address with constant offsets
+// serves a whole tile; npad is n_prev rounded
+// up to a multiple of rows_table_align(RP).  Tiles that start at or beyond
+// n_prev are skipped, and the last one is padded to its end with m = 0 and
+// score -inf, which never wins, so no edge needs a bounds check.  A
+// workgroup takes RP = 4, 8 or 16 rows at a time (the launch picks the
+// largest that still gives every compute unit a workgroup): lane l of wave w
+// takes row l % RP and, of the previous particles, the w-th sixteenth of the
+// table in tiles of 8 * 64 / RP indices, eight consecutive ones per lane
+// group l / RP.  Per tile a lane takes the maximum of its eight scores and
+// keeps the first tile that raised its running maximum; that tile's scores
+// are evaluated again at the end (the
+// same arithmetic, hence the same values) to find the lowest index reaching
+// it.  Lanes of a row merge by shuffles, the 16 waves through LDS, equal
+// scores always going to the lower index.  A non-finite scaled coordinate or
+// a NaN / +inf score offset (checked once per table entry and per row) is
+// the only way to a NaN score; then the workgroup walks its edges one by
+// one, skipping the padding and flagging NaN scores, as the kernel above
+// does.  Bound by the vector ALU: 2d instructions per edge and 7 per lane
+// and tile of eight.
+// ---------------------------------------------------------------------------
+constexpr int kRowsWaves = 16;       // waves per workgroup
+constexpr int kRowsPer = 8;          // consecutive edges per lane and tile
+__host__ __device__ constexpr int rows_tile(int rp) { return kRowsPer * (kWave / rp); }
+__host__ __device__ constexpr int rows_table_align(int rp) { return kRowsWaves * rows_tile(rp); }
+
+template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T> __device__ __forceinline__ T vmax_(T a, T b);
+template <> __device__ __forceinline__ float vmax_(float a, float b) { return __builtin_fmaxf(a, b); }
+template <> __device__ __forceinline__ double vmax_(double a, double b) { return __builtin_fmax(a, b); }
+
+typedef float lds_f4 __attribute__((ext_vector_type(4)));
+typedef double lds_d2 __attribute__((ext_vector_type(2)));
+
+// K consecutive table entries from a 16-byte aligned LDS address
+template <int K> __device__ __forceinline__ void lds_run(const float *p, float (&v)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; k += 4) {
+        const lds_f4 q = *(const lds_f4 *)(p + k);
+        v[k] = q[0]; v[k + 1] = q[1]; v[k + 2] = q[2]; v[k + 3] = q[3];
+    }
+}
+template <int K> __device__ __forceinline__ void lds_run(const double *p, double (&v)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; k += 2) {
+        const lds_d2 q = *(const lds_d2 *)(p + k);
+        v[k] = q[0]; v[k + 1] = q[1];
+    }
+}
+
+// keeps (v, j) or takes (vo, jo): the larger score, the lower index among
+// equal ones; NaN never taken (branch-free)
+template <typename T> __device__ __forceinline__ void take_better(T &v, int &j, T vo, int jo)
+{
+    const bool b = (vo > v) | ((vo == v) & (jo < j));
+    v = b ? vo : v;
+    j = b ? jo : j;
+}
+
+// log2-unit scores of K edges of row y: p points at the first of them in
+// the coordinate-0 array of a tile of TILE indices
+template <typename T, int D, int K, int TILE>
+__device__ __forceinline__ void row_edge_scores(const T *p, const T (&y)[D], T (&c)[K])
+{
+    lds_run<K>(p + D * TILE, c);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T mv[K];
+        lds_run<K>(p + a * TILE, mv);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T r = y[a] - mv[k];
+            c[k] = fma_(-r, r, c[k]);
+        }
+    }
+}
+
+template <typename T, int KIND, int D, int RP>
+__global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
+    DevModel<T> m, int t, int n, int n_prev, int npad, const T *__restrict__ x_prev, const T *__restrict__ phi_prev,
+    const T *__restrict__ z, const uint8_t *mask, const T *__restrict__ x, T *phi, int32_t *psi, uint32_t *status)
+{
+    using F = Family<T, KIND, D>;
+    using R = RealOps<T>;
+    constexpr int NT = kRowsWaves * kWave;
+    constexpr int kChunk = 4;                         // table entries per thread in flight
+    constexpr int kTile = rows_tile(RP);
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *tab = (T *)smem;                               // [npad / kTile][D + 1][kTile]
+    __shared__ T s_v[kRowsWaves][RP];
+    __shared__ int s_j[kRowsWaves][RP];
+    __shared__ T s_z[kMaxObs];
+    __shared__ uint8_t s_mask[kMaxObs];
+    __shared__ int s_bad[kRowsWaves];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = wave_id();
+    const int rl = lane & (RP - 1), grp = lane / RP;
+    const int nrb = (n + RP - 1) / RP;
+
+    // this workgroup's first rows and the centre, loaded before the table
+    T xn[D];
+    {
+        const int i = blockIdx.x * RP + rl;
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = i < n ? x[(long)i * D + a] : (T)0;
+    }
+    T xp0[D], cen[D], rs[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xp0[a] = x_prev[a];
+        rs[a] = m.rs[a];
+    }
+    // the observation, staged in LDS after the table loads are in flight
+    const T zr = tid < m.obs_dim ? z[tid] : (T)0;
+    const uint8_t mr = mask && tid < m.n_obs ? mask[tid] : (uint8_t)0;
+    const int span = npad / kRowsWaves;               // this wave's share, a multiple of kTile
+    const int nfill = (n_prev + kTile - 1) / kTile * kTile;   // entries the tiles read
+    bool bad = false;
+    for (int j0 = 0; j0 < nfill; j0 += kChunk * NT) {
+        T xv[kChunk][D], pv[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int j = j0 + u * NT + tid;
+            const bool real = j < n_prev;
+#pragma unroll
+            for (int a = 0; a < D; ++a) xv[u][a] = real ? x_prev[(long)j * D + a] : (T)0;
+            pv[u] = real ? phi_prev[j] : (T)0;
+        }
+        if (j0 == 0) F::mean(m, t, xp0, cen);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int j = j0 + u * NT + tid;
+            if (j >= nfill) break;
+            T mu[D];
+            T s = -R::inf();
+            if (j < n_prev) {
+                F::mean(m, t, xv[u], mu);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    mu[a] = (mu[a] - cen[a]) * rs[a];
+                    bad |= !R::finite(mu[a]);
+                }
+                s = (m.log_z + pv[u]) * (T)kLog2e;
+                bad |= (s != s) || s == R::inf();
+            } else {
+#pragma unroll
+                for (int a = 0; a < D; ++a) mu[a] = 0;
+            }
+            T *e = tab + (long)(j / kTile) * (D + 1) * kTile + (j % kTile);
+#pragma unroll
+            for (int a = 0; a < D; ++a) e[a * kTile] = mu[a];
+            e[D * kTile] = s;
+        }
+    }
+    if (tid < m.obs_dim) s_z[tid] = zr;
+    if (tid < m.n_obs) s_mask[tid] = mr;
+    {
+        const bool wbad = __any(bad);
+        if (lane == 0) s_bad[w] = wbad;
+        __syncthreads();
+        bad = false;
+#pragma unroll
+        for (int h = 0; h < kRowsWaves; ++h) bad |= s_bad[h] != 0;
+    }
+
+    const int jw0 = w * span;                         // this wave's first index
+    const int jw = jw0 + grp * kRowsPer;              // this lane's first index
+    // this lane's entries of the wave's first tile
+    const T *tw = tab + (long)(jw0 / kTile) * (D + 1) * kTile + grp * kRowsPer;
+    const uint8_t *mk = mask ? s_mask : nullptr;
+    bool nan_seen = false;
+    for (int rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+        const int i = rb * RP + rl;
+        const bool live = i < n;
+        T xi[D], y[D];
+        bool rbad = false;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            xi[a] = xn[a];
+            y[a] = live ? (xi[a] - cen[a]) * rs[a] : (T)0;
+            rbad |= !R::finite(y[a]);
+        }
+        {   // the next pass's rows, in flight during this pass
+            const int in = (rb + gridDim.x) * RP + rl;
+#pragma unroll
+            for (int a = 0; a < D; ++a) xn[a] = in < n ? x[(long)in * D + a] : (T)0;
+        }
+        // every wave holds the same rows, so this choice is the workgroup's
+        const bool exact = bad || __any(rbad);
+        T v = -R::inf();
+        int jb = 0x7fffffff;
+        if (!exact) {
+            T best = -R::inf();
+            int bt = -1;
+            for (int tt = 0; tt < span && jw0 + tt < n_prev; tt += kTile) {
+                T c[kRowsPer];
+                row_edge_scores<T, D, kRowsPer, kTile>(tw + (long)tt * (D + 1), y, c);
+                T mx = vmax_(vmax_(c[0], c[1]), c[2]);
+#pragma unroll
+                for (int k = 3; k + 1 < kRowsPer; k += 2) mx = vmax_(vmax_(mx, c[k]), c[k + 1]);
+                if (kRowsPer % 2 == 0) mx = vmax_(mx, c[kRowsPer - 1]);
+                const bool up = mx > best;
+                bt = up ? tt : bt;
+                best = up ? mx : best;
+            }
+            if (bt >= 0) {
+                T c[kRowsPer];
+                row_edge_scores<T, D, kRowsPer, kTile>(tw + (long)bt * (D + 1), y, c);
+#pragma unroll
+                for (int k = 0; k < kRowsPer; ++k) {
+                    const bool b = c[k] > v;
+                    v = b ? c[k] : v;
+                    jb = b ? jw + bt + k : jb;
+                }
+            }
+        } else {
+            for (int tt = 0; tt < span && jw + tt < n_prev; tt += kTile) {
+                T c[kRowsPer];
+                row_edge_scores<T, D, kRowsPer, kTile>(tw + (long)tt * (D + 1), y, c);
+#pragma unroll
+                for (int k = 0; k < kRowsPer; ++k) {
+                    const int j = jw + tt + k;
+                    if (j < n_prev) {
+                        nan_seen |= live && (c[k] != c[k]);
+                        const bool b = c[k] > v;
+                        v = b ? c[k] : v;
+                        jb = b ? j : jb;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int off = RP; off < kWave; off <<= 1) {
+            const T vo = __shfl_xor(v, off, kWave);
+            const int jo = __shfl_xor(jb, off, kWave);
+            take_better(v, jb, vo, jo);
+        }
+        if (lane < RP) {
+            s_v[w][lane] = v;
+            s_j[w][lane] = jb;
+        }
+        __syncthreads();
+        if (w == 0 && lane < RP && live) {
+            T vs[kRowsWaves];
+            int js[kRowsWaves];
+#pragma unroll
+            for (int h = 0; h < kRowsWaves; ++h) {
+                vs[h] = s_v[h][lane];
+                js[h] = s_j[h][lane];
+            }
+            T b = vs[0];
+            int arg = js[0];
+#pragma unroll
+            for (int h = 1; h < kRowsWaves; ++h) take_better(b, arg, vs[h], js[h]);
+            const T ell = F::loglik(m, s_z, mk, xi);
+            const T ph = b * (T)kLn2 + ell;
+            phi[i] = ph;
+            psi[i] = arg == 0x7fffffff ? 0 : arg;
+            nan_seen |= (ell != ell) || (ph != ph);
+        }
+        __syncthreads();
+    }
+    if (__any(nan_seen) && lane == 0) atomicOr(status, STATUS_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
 // Backtracking: one workgroup (one wave) per sequence.
 // ---------------------------------------------------------------------------
 template <typename T>

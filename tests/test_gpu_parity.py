@@ -154,8 +154,11 @@ def _particle_case(name, n, n_prev, seed):
 
 @pytest.mark.parametrize("name", ["growth1d", "range2d", "cv4d", "arm7", "lingauss", "scenario_b", "scenario_d"])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_viterbi_particle_mode(name, dt):
-    announce("viterbi particle", name, dt)
+@pytest.mark.parametrize("flags", [True, False])
+def test_viterbi_particle_mode(name, dt, flags):
+    """Particle mode per model, with tie flags (two waves per row) and without
+    (16 rows per workgroup pass, for the states that fit it)."""
+    announce("viterbi particle", name, dt, flags)
     n, n_prev = 150, 77
     wl, desc, xp, x = _particle_case(name, n, n_prev, 3)
     z = wl.z[0, 1]
@@ -174,7 +177,7 @@ def test_viterbi_particle_mode(name, dt):
     model = smsq.Model(desc)
     phi, psi, fl = smsq.viterbi_step(model, dt, 2, dev(phi_prev, td), x_prev=dev(xp, td), z_t=dev(z, td),
                                      z_mask=None if mask is None else dev(mask, torch.uint8),
-                                     x=dev(x, td), tie_tol=tol)
+                                     x=dev(x, td), tie_tol=tol, want_flags=flags)
     psi, phi = host(psi), host(phi).astype(np.float64)
     sure = fl_o == 0
     assert sure.mean() > 0.5
@@ -215,12 +218,16 @@ def test_backtrack_bit_exact(dt):
         assert np.array_equal(xmap[b, 1:], want.astype(np.float32) if dt == "f32" else want)
 
 
-@pytest.mark.parametrize("n,n_prev", [(4000, 4000), (1, 3000), (2500, 1), (777, 1025)])
+@pytest.mark.parametrize("n,n_prev", [(4000, 4000), (2000, 1999), (1, 3000), (2500, 1), (777, 1025),
+                                      (8200, 600), (33, 5000)])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_viterbi_particle_mode_large(n, n_prev, dt):
+@pytest.mark.parametrize("flags", [True, False])
+def test_viterbi_particle_mode_large(n, n_prev, dt, flags):
     """Particle mode at PF-MAP-Seq sizes (up to 4000 x 4000 edges of the
-    range-only model), with one row, one previous particle and ragged tails."""
-    announce("viterbi particle large", n, n_prev, dt)
+    range-only model), with one row, one previous particle, ragged tails,
+    more rows than one pass of the 16-rows kernel's grid covers and a table
+    of several load chunks."""
+    announce("viterbi particle large", n, n_prev, dt, flags)
     wl, desc, xp, x = _particle_case("range2d", n, n_prev, 4)
     z = wl.z[0, 1]
     rng = np.random.default_rng(6)
@@ -233,25 +240,72 @@ def test_viterbi_particle_mode_large(n, n_prev, dt):
     assert st == O.OK
     ws = smsq.workspace()
     phi, psi, fl = smsq.viterbi_step(smsq.Model(desc), dt, 2, dev(phi_prev, td), x_prev=dev(xp, td),
-                                     z_t=dev(z, td), x=dev(x, td), tie_tol=tol, ws=ws)
+                                     z_t=dev(z, td), x=dev(x, td), tie_tol=tol, ws=ws, want_flags=flags)
     assert smsq.device_status(ws) == smsq.OK
-    psi, phi, fl = host(psi), host(phi).astype(np.float64), host(fl)
+    psi, phi = host(psi), host(phi).astype(np.float64)
     sure = fl_o == 0
     assert np.array_equal(psi[sure], psi_o[sure])
     if n_prev == 1:
-        assert np.all(psi == 0) and np.all(fl == 0)
+        assert np.all(psi == 0)
+        if flags:
+            assert np.all(host(fl) == 0)
     err = np.abs(phi - phi_o) / np.maximum(1, np.abs(phi_o))
     print("phi rel err %.3e, sure rows %.3f" % (err.max(), sure.mean()))
+    # FP32: the range log-likelihood dominates (d ell / d r = e / r_var, up to
+    # ~8 per beacon, times the ~3e-6 rounding of ranges near 20), as in the
+    # per-model test above
+    assert err.max() <= (1e-4 if dt == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("flags", [True, False])
+@pytest.mark.parametrize("case", ["nan_score", "inf_row", "dead_block"])
+def test_viterbi_particle_nonfinite(case, dt, flags):
+    """Non-finite inputs in particle mode: a NaN previous score (every row
+    sees a NaN edge: status non-finite, NaN never the argmax), a row at
+    infinity (its scores are all -inf: index 0) and previous scores that are
+    -inf on a whole block of the table; each against the oracle."""
+    announce("viterbi particle nonfinite", case, dt, flags)
+    n, n_prev = 300, 700
+    wl, desc, xp, x = _particle_case("range2d", n, n_prev, 8)
+    z = wl.z[0, 1]
+    rng = np.random.default_rng(9)
+    phi_prev = rng.normal(size=n_prev) * 3
+    if case == "nan_score":
+        phi_prev[5] = np.nan
+    elif case == "inf_row":
+        x[17, 0] = np.inf
+    else:
+        phi_prev[:600] = -np.inf
+    td = tdt(dt)
+    if dt == "f32":
+        xp, x, phi_prev, z = (v.astype(np.float32).astype(np.float64) for v in (xp, x, phi_prev, z))
+    tol = 1e-5 if dt == "f32" else 1e-9
+    phi_o, psi_o, fl_o, st = O.viterbi_particle(desc, 2, xp, phi_prev, z, None, x, tie_tol=tol)
+    ws = smsq.workspace()
+    phi, psi, _ = smsq.viterbi_step(smsq.Model(desc), dt, 2, dev(phi_prev, td), x_prev=dev(xp, td),
+                                    z_t=dev(z, td), x=dev(x, td), tie_tol=tol, ws=ws, want_flags=flags)
+    status = smsq.device_status(ws)
+    assert (status == smsq.ERR_NONFINITE) == (st == O.NONFINITE), (status, st)
+    psi, phi = host(psi), host(phi).astype(np.float64)
+    sure = fl_o == 0
+    if case == "inf_row":
+        assert psi[17] == 0 and psi_o[17] == 0 and phi[17] == phi_o[17]
+    assert np.array_equal(psi[sure], psi_o[sure])
+    fin = np.isfinite(phi_o)
+    assert np.array_equal(np.isfinite(phi), fin)
+    err = np.abs(phi[fin] - phi_o[fin]) / np.maximum(1, np.abs(phi_o[fin]))
     assert err.max() <= (1e-5 if dt == "f32" else 1e-12)
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_pf_map_seq_forward_recursion(dt):
+@pytest.mark.parametrize("flags", [True, False])
+def test_pf_map_seq_forward_recursion(dt, flags):
     """The PF-MAP-Seq workload: forward recursion and backtrack over the
     particle sets of a bootstrap particle filter (1500 particles per step,
     12 steps of the range-only model), step by step against the oracle fed
     the same scores, then free-running to the MAP log-posterior."""
-    announce("pf-map-seq", dt)
+    announce("pf-map-seq", dt, flags)
     T, n = 12, 1500
     wl = S.make_workload("range2d", B=1, seed=1008, T=T)
     desc = wl.model
@@ -272,14 +326,15 @@ def test_pf_map_seq_forward_recursion(dt):
         assert st == O.OK
         # same scores on both sides for this step's comparison
         ph_t, ps_t, _ = smsq.viterbi_step(model, dt, t, dev(rnd(phi_o), td), x_prev=dev(xp, td),
-                                          z_t=dev(z[t - 1], td), x=dev(parts[t - 1], td), tie_tol=tol, ws=ws)
+                                          z_t=dev(z[t - 1], td), x=dev(parts[t - 1], td), tie_tol=tol, ws=ws,
+                                          want_flags=flags)
         sure = fl_o == 0
         assert np.array_equal(host(ps_t)[sure], ps_o[sure]), t
         err = np.abs(host(ph_t).astype(np.float64) - ph_o) / np.maximum(1, np.abs(ph_o))
         assert err.max() <= (1e-5 if dt == "f32" else 1e-12), (t, err.max())
         # free-running chain on the GPU's own scores
         phi_g, psi_g, _ = smsq.viterbi_step(model, dt, t, phi_g, x_prev=dev(xp, td), z_t=dev(z[t - 1], td),
-                                            x=dev(parts[t - 1], td), tie_tol=tol, ws=ws)
+                                            x=dev(parts[t - 1], td), tie_tol=tol, ws=ws, want_flags=flags)
         psi_all[t - 1] = psi_g
         psi_o_all[t - 1] = ps_o
         phi_o = ph_o

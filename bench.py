@@ -414,10 +414,13 @@ PAPER_SCENARIO_C_MS = {"pf_map_seq": {1000: 58.94, 2000: 162.01, 4000: 505.32},
 def pf_map_seq(torch, smsq):
     """The PF-MAP-Seq forward recursion as a workload of the particle-mode
     kernel: bootstrap-PF particle sets of the range-only model (T = 200, one
-    beacon visible in steps 80..120) at N = 1000, 2000, 4000, FP32.  Per step:
-    the kernel's time (HIP events around back-to-back launches on the launch
-    stream), the whole recursion + backtrack wall time per step, edges/s and
-    the counted vector-ALU rate (N N_p (2d + 4) flops per launch).  Beside it,
+    beacon visible in steps 80..120) at N = 1000, 2000, 4000, FP32.  Per N:
+    the kernel's time per launch (HIP events around a captured graph of 50
+    back-to-back launches of step 100, median of 5 replays), edges/s and the
+    counted vector-ALU rate (N N_p (2d + 4) flops per launch); the whole
+    recursion + backtrack wall time per step, run eagerly through the binding
+    and replayed from a captured graph (one launch per step: each step writes
+    its back-pointers into a row of the [T, N] array).  Beside it,
     Stein-MAP-Seq's own per-step time on one sequence at N = 20, 30, 40
     (L = 100, eps = 0.005)."""
     from paper_2312_08684_amd import scenarios as S
@@ -428,20 +431,44 @@ def pf_map_seq(torch, smsq):
     z = torch.tensor(wl.z[0], dtype=torch.float32, device="cuda")
     zm = torch.tensor(wl.mask[0], dtype=torch.uint8, device="cuda")
     x0 = torch.tensor(wl.x0[0][None, :], dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
     rows = []
+
+    def replayed(run, reps):
+        """Median wall time of one run() from 5 replays of a captured graph."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            out = run()
+        times = []
+        for _ in range(5):
+            e0, e1 = _events(torch)
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / reps)
+        del graph
+        return sorted(times)[2], out
+
     for n in (1000, 2000, 4000):
         parts = torch.tensor(S.bootstrap_pf_particles(wl.model, wl.x0[0], wl.z[0], wl.mask[0], n, seed=10),
                              dtype=torch.float32, device="cuda")
         psi_all = torch.empty((T, n), dtype=torch.int32, device="cuda")
+        phi_buf = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(2)]
+        phi0 = torch.zeros(1, dtype=torch.float32, device="cuda")
 
         def recursion():
-            phi = torch.zeros(1, dtype=torch.float32, device="cuda")
+            phi = phi0
             for t in range(1, T + 1):
-                phi, psi, _ = smsq.viterbi_step(model, "f32", t, phi, x_prev=x0 if t == 1 else parts[t - 2],
-                                                z_t=z[t - 1], z_mask=zm[t - 1], x=parts[t - 1],
-                                                want_flags=False, ws=ws)
-                psi_all[t - 1] = psi
+                phi, _, _ = smsq.viterbi_step(model, "f32", t, phi, x_prev=x0 if t == 1 else parts[t - 2],
+                                              z_t=z[t - 1], z_mask=zm[t - 1], x=parts[t - 1],
+                                              want_flags=False, ws=ws, phi_out=phi_buf[t % 2],
+                                              psi_out=psi_all[t - 1])
             return smsq.backtrack("f32", psi_all, phi, ws=ws)
 
         recursion()
@@ -450,49 +477,31 @@ def pf_map_seq(torch, smsq):
         _, J, _ = recursion()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        # the T + 1 launches captured once and replayed (wall per step = the
-        # kernels' time): every replay checked against the eager J
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            recursion()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            _, Jg, _ = recursion()
-        graph_ok = True
-        for _ in range(3):
-            graph.replay()
-            torch.cuda.synchronize()
-            graph_ok &= float(Jg.item()) == float(J.item())
-        t0 = time.perf_counter()
-        graph.replay()
-        torch.cuda.synchronize()
-        wall_graph = time.perf_counter() - t0
-        graph_ok &= float(Jg.item()) == float(J.item())
-        del graph
-        # kernel alone: one mid-sequence step launched back to back
+        J_eager = float(J.item())
+        # the T + 1 launches replayed (wall per step = the kernels' time); the
+        # replayed J must equal the eager one
+        ms_graph, (_, Jg, _) = replayed(recursion, T)
+        graph_ok = float(Jg.item()) == J_eager
+        # kernel alone: step T / 2 launched back to back from a graph
         tm = T // 2
         ph = torch.zeros(n, dtype=torch.float32, device="cuda")
+        psi_k = torch.empty(n, dtype=torch.int32, device="cuda")
+        phi_k = torch.empty(n, dtype=torch.float32, device="cuda")
         reps = 50
-        for _ in range(3):
-            smsq.viterbi_step(model, "f32", tm, ph, x_prev=parts[tm - 2], z_t=z[tm - 1], z_mask=zm[tm - 1],
-                              x=parts[tm - 1], want_flags=False, ws=ws)
-        e0, e1 = _events(torch)
-        e0.record(stream)
-        for _ in range(reps):
-            smsq.viterbi_step(model, "f32", tm, ph, x_prev=parts[tm - 2], z_t=z[tm - 1], z_mask=zm[tm - 1],
-                              x=parts[tm - 1], want_flags=False, ws=ws)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) / reps * 1e3
+
+        def steps():
+            for _ in range(reps):
+                smsq.viterbi_step(model, "f32", tm, ph, x_prev=parts[tm - 2], z_t=z[tm - 1], z_mask=zm[tm - 1],
+                                  x=parts[tm - 1], want_flags=False, ws=ws, phi_out=phi_k, psi_out=psi_k)
+
+        ms_kernel, _ = replayed(steps, reps)
+        us = ms_kernel * 1e3
         edges = n * n
         rows.append({"N": n, "kernel_us_per_step": us, "edges_per_s": edges / (us * 1e-6),
                      "counted_tflops": edges * (2 * d + 4) / (us * 1e-6) / 1e12,
                      "frac_fp32_peak": edges * (2 * d + 4) / (us * 1e-6) / PEAK_FP32,
-                     "wall_ms_per_step": wall / T * 1e3, "graph_wall_ms_per_step": wall_graph / T * 1e3,
-                     "graph_replays_match_eager": graph_ok, "J": float(J.item()),
+                     "wall_ms_per_step": wall / T * 1e3, "graph_wall_ms_per_step": ms_graph,
+                     "graph_replays_match_eager": graph_ok, "J": J_eager,
                      "paper_ms_per_step": PAPER_SCENARIO_C_MS["pf_map_seq"][n]})
     assert smsq.device_status(ws) == smsq.OK
     stein = []
@@ -511,7 +520,7 @@ def pf_map_seq(torch, smsq):
         stein.append({"N": n, "ms_per_step": (time.perf_counter() - t0) / w2.T * 1e3,
                       "paper_ms_per_step": PAPER_SCENARIO_C_MS["stein_map_seq"][n]})
     return {"model": "range2d (stand-in for Sec. V-C), FP32, T=200; PF particle sets from a bootstrap PF "
-                     "with stratified resampling", "kernel": "k_viterbi_particle_wide", "rows": rows,
+                     "with stratified resampling", "kernel": "k_viterbi_particle_rows", "rows": rows,
             "stein_map_seq_one_sequence": stein}
 
 

@@ -269,16 +269,25 @@ def svgd_step(model: Model, dtype, t: int, x_prev: torch.Tensor, log_w_prev: Opt
     return x
 
 
+def _out(t: torch.Tensor, dtype, n: int, name: str) -> torch.Tensor:
+    if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {n} elements")
+    return t
+
+
 def viterbi_step(model: Optional[Model], dtype, t: int, phi_prev: torch.Tensor, *, x_prev=None,
                  z_t=None, z_mask=None, x=None, lattice=None, loglik=None, tie_tol: float = 0.0,
-                 want_flags: bool = True, ws: Optional[torch.Tensor] = None, stream=None):
-    """Forward-recursion step (smsq_viterbi_step).  Returns (phi, psi, flags)."""
+                 want_flags: bool = True, ws: Optional[torch.Tensor] = None, stream=None,
+                 phi_out: Optional[torch.Tensor] = None, psi_out: Optional[torch.Tensor] = None):
+    """Forward-recursion step (smsq_viterbi_step).  Returns (phi, psi, flags);
+    phi_out / psi_out, when given, are contiguous [n] tensors written in place
+    (e.g. a row of a [T, n] back-pointer array)."""
     td = torch_dtype(dtype)
     n_prev = phi_prev.shape[0]
     n = lattice.shape[0] if lattice is not None else x.shape[0]
     dev = phi_prev.device
-    phi = torch.empty(n, dtype=td, device=dev)
-    psi = torch.empty(n, dtype=torch.int32, device=dev)
+    phi = torch.empty(n, dtype=td, device=dev) if phi_out is None else _out(phi_out, td, n, "phi_out")
+    psi = torch.empty(n, dtype=torch.int32, device=dev) if psi_out is None else _out(psi_out, torch.int32, n, "psi_out")
     flags = torch.empty(n, dtype=torch.uint8, device=dev) if want_flags else None
     ws = workspace(device=dev) if ws is None else ws
     st = load().smsq_viterbi_step(model.handle if model is not None else None, _dt(dtype), t, n_prev,

@@ -433,28 +433,6 @@ def pf_map_seq(torch, smsq):
     x0 = torch.tensor(wl.x0[0][None, :], dtype=torch.float32, device="cuda")
     rows = []
 
-    def replayed(run, reps):
-        """Median wall time of one run() from 5 replays of a captured graph."""
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            run()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            out = run()
-        times = []
-        for _ in range(5):
-            e0, e1 = _events(torch)
-            e0.record()
-            graph.replay()
-            e1.record()
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1) / reps)
-        del graph
-        return sorted(times)[2], out
-
     for n in (1000, 2000, 4000):
         parts = torch.tensor(S.bootstrap_pf_particles(wl.model, wl.x0[0], wl.z[0], wl.mask[0], n, seed=10),
                              dtype=torch.float32, device="cuda")
@@ -480,7 +458,7 @@ def pf_map_seq(torch, smsq):
         J_eager = float(J.item())
         # the T + 1 launches replayed (wall per step = the kernels' time); the
         # replayed J must equal the eager one
-        ms_graph, (_, Jg, _) = replayed(recursion, T)
+        ms_graph, (_, Jg, _) = _graph_ms(torch, recursion, T)
         graph_ok = float(Jg.item()) == J_eager
         # kernel alone: step T / 2 launched back to back from a graph
         tm = T // 2
@@ -494,7 +472,7 @@ def pf_map_seq(torch, smsq):
                 smsq.viterbi_step(model, "f32", tm, ph, x_prev=parts[tm - 2], z_t=z[tm - 1], z_mask=zm[tm - 1],
                                   x=parts[tm - 1], want_flags=False, ws=ws, phi_out=phi_k, psi_out=psi_k)
 
-        ms_kernel, _ = replayed(steps, reps)
+        ms_kernel, _ = _graph_ms(torch, steps, reps)
         us = ms_kernel * 1e3
         edges = n * n
         rows.append({"N": n, "kernel_us_per_step": us, "edges_per_s": edges / (us * 1e-6),
@@ -526,6 +504,31 @@ def pf_map_seq(torch, smsq):
 
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _graph_ms(torch, run, reps):
+    """run() (reps launches) captured once in a hipGraph after a warm-up on a
+    side stream, replayed 5 times: the median wall time per launch in ms from
+    HIP events around each replay, and run()'s return value."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = run()
+    times = []
+    for _ in range(5):
+        e0, e1 = _events(torch)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / reps)
+    del graph
+    return sorted(times)[2], out
 
 
 def sweep(torch, smsq):
@@ -576,16 +579,16 @@ def sweep(torch, smsq):
             ell = torch.randn(n, generator=gen, device="cuda", dtype=tdt)
             php = torch.randn(n, generator=gen, device="cuda", dtype=tdt)
             ws = smsq.workspace()
-            for A in As[:3]:
-                smsq.viterbi_step(None, dt, 2, php, lattice=A, loglik=ell, want_flags=False, ws=ws)
             reps = 48
-            e0, e1 = _events(torch)
-            e0.record()
-            for r in range(reps):
-                smsq.viterbi_step(None, dt, 2, php, lattice=As[r % nlat], loglik=ell, want_flags=False, ws=ws)
-            e1.record()
-            torch.cuda.synchronize()
-            sec = e0.elapsed_time(e1) / 1e3 / reps
+            phi_k = torch.empty(n, dtype=tdt, device="cuda")
+            psi_k = torch.empty(n, dtype=torch.int32, device="cuda")
+
+            def lattices():
+                for r in range(reps):
+                    smsq.viterbi_step(None, dt, 2, php, lattice=As[r % nlat], loglik=ell, want_flags=False, ws=ws,
+                                      phi_out=phi_k, psi_out=psi_k)
+
+            sec = _graph_ms(torch, lattices, reps)[0] / 1e3
             nbytes = n * n * es + 3 * n * es + 4 * n
             del As
             rows.append({"mode": "lattice", "dtype": dt, "N": n, "us_per_launch": sec * 1e6,
@@ -602,16 +605,16 @@ def sweep(torch, smsq):
         mk = torch.tensor(wl.mask[0, 1], dtype=torch.uint8, device="cuda") if wl.mask is not None else None
         php = torch.zeros(n, dtype=tdt, device="cuda")
         ws = smsq.workspace()
-        for _ in range(3):
-            smsq.viterbi_step(model, dt, 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
         reps = 50
-        e0, e1 = _events(torch)
-        e0.record()
-        for _ in range(reps):
-            smsq.viterbi_step(model, dt, 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3 / reps
+        phi_k = torch.empty(n, dtype=tdt, device="cuda")
+        psi_k = torch.empty(n, dtype=torch.int32, device="cuda")
+
+        def particles():
+            for _ in range(reps):
+                smsq.viterbi_step(model, dt, 2, php, x_prev=xp, z_t=z, z_mask=mk, x=x, want_flags=False, ws=ws,
+                                  phi_out=phi_k, psi_out=psi_k)
+
+        sec = _graph_ms(torch, particles, reps)[0] / 1e3
         rows.append({"mode": "particle (one sequence, rows over the chip)", "model": name, "dtype": dt, "N": n,
                      "us_per_launch": sec * 1e6, "edges_per_s": n * n / sec})
     out["viterbi_vs_n"] = rows

@@ -208,9 +208,14 @@ smsq_status_t smsq_svgd_step(smsq_model_t model, smsq_dtype_t dtype, int t,
  * ignored (may be NULL).  Particle mode (lattice == NULL): A and loglik are
  * computed from x_prev [n_prev, d], x [n, d] and z_t over the whole chip
  * (rows i spread over workgroups, each holding the n_prev transition means
- * in LDS); any n, and n_prev up to what fits one compute unit's LDS,
- * n_prev * (dpad(d) + 1) element slots with dpad(d) = 1, 2, 4, 8 or 16
- * (e.g. 13,000 previous particles in FP32 at d = 2), else
+ * in LDS).  Without tie flags, FP32 states of d <= 8 and FP64 of d <= 2
+ * take 4..16 rows per workgroup pass and rank c_ij in log2 units
+ * (c_ij log2 e, one fused multiply-subtract per coordinate; equal scores
+ * are equal in that form), in (d + 1) * n_prev element slots with n_prev
+ * rounded up to a multiple of 512, 1024 or 2048; the other cases, and these
+ * when that does not fit, take two waves per row in n_prev * (dpad(d) + 1)
+ * slots with dpad(d) = 1, 2, 4, 8 or 16.  Any n, and n_prev up to what fits one compute unit's
+ * LDS (e.g. 13,000 previous particles in FP32 at d = 2), else
  * SMSQ_ERR_UNSUPPORTED.
  *  phi_prev    [n_prev] accumulated scores of step t-1 (zeros for t = 1)
  *  phi, psi    [n] outputs; tie_flags [n] output or NULL: 1 where the best

@@ -895,8 +895,9 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
 // keeps the first tile that raised its running maximum; that tile's scores
 // are evaluated again at the end (the
 // same arithmetic, hence the same values) to find the lowest index reaching
-// it.  Lanes of a row merge by shuffles, the 16 waves through LDS, equal
-// scores always going to the lower index.  A non-finite scaled coordinate or
+// it.  Lanes of a row merge by shuffles, the 16 waves through LDS (read by
+// all of wave 0, then shuffles again), equal scores always going to the
+// lower index.  A non-finite scaled coordinate or
 // a NaN / +inf score offset (checked once per table entry and per row) is
 // the only way to a NaN score; then the workgroup walks its edges one by
 // one, skipping the padding and flagging NaN scores, as the kernel above
@@ -1007,11 +1008,11 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
         T xv[kChunk][D], pv[kChunk];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            const int j = j0 + u * NT + tid;
-            const bool real = j < n_prev;
+            // clamped, so that every load is unconditional; padding is chosen below
+            const int j = min(j0 + u * NT + tid, n_prev - 1);
 #pragma unroll
-            for (int a = 0; a < D; ++a) xv[u][a] = real ? x_prev[(long)j * D + a] : (T)0;
-            pv[u] = real ? phi_prev[j] : (T)0;
+            for (int a = 0; a < D; ++a) xv[u][a] = x_prev[(long)j * D + a];
+            pv[u] = phi_prev[j];
         }
         if (j0 == 0) F::mean(m, t, xp0, cen);
 #pragma unroll
@@ -1127,23 +1128,28 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
             s_j[w][lane] = jb;
         }
         __syncthreads();
-        if (w == 0 && lane < RP && live) {
-            T vs[kRowsWaves];
-            int js[kRowsWaves];
+        if (w == 0) {
+            // the 16 waves' results of row rl: lane group grp takes waves
+            // grp, grp + 64 / RP, ..., then the groups merge by shuffles
+            constexpr int kGroups = kWave / RP;
+            T b = s_v[grp][rl];
+            int arg = s_j[grp][rl];
 #pragma unroll
-            for (int h = 0; h < kRowsWaves; ++h) {
-                vs[h] = s_v[h][lane];
-                js[h] = s_j[h][lane];
+            for (int q = 1; q < kRowsWaves / kGroups; ++q)
+                take_better(b, arg, s_v[grp + q * kGroups][rl], s_j[grp + q * kGroups][rl]);
+#pragma unroll
+            for (int off = RP; off < kWave; off <<= 1) {
+                const T vo = __shfl_xor(b, off, kWave);
+                const int jo = __shfl_xor(arg, off, kWave);
+                take_better(b, arg, vo, jo);
             }
-            T b = vs[0];
-            int arg = js[0];
-#pragma unroll
-            for (int h = 1; h < kRowsWaves; ++h) take_better(b, arg, vs[h], js[h]);
-            const T ell = F::loglik(m, s_z, mk, xi);
-            const T ph = b * (T)kLn2 + ell;
-            phi[i] = ph;
-            psi[i] = arg == 0x7fffffff ? 0 : arg;
-            nan_seen |= (ell != ell) || (ph != ph);
+            if (lane < RP && live) {
+                const T ell = F::loglik(m, s_z, mk, xi);
+                const T ph = b * (T)kLn2 + ell;
+                phi[i] = ph;
+                psi[i] = arg == 0x7fffffff ? 0 : arg;
+                nan_seen |= (ell != ell) || (ph != ph);
+            }
         }
         __syncthreads();
     }

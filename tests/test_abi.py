@@ -62,3 +62,23 @@ def test_workspace_size_grows_with_batch():
     c = m.workspace_size("f64", 8, 50, 256)
     assert a < b < c
     assert b >= 8 * 50 * 256 * 2 * 4
+
+
+def test_viterbi_step_out_tensors_validated_host_only():
+    """phi_out / psi_out must be contiguous tensors of the step's dtype and n
+    elements; a mismatch is rejected before anything is launched."""
+    import torch
+    m = smsq.Model(S._model_for("range2d", 0))
+    phi_prev = torch.zeros(5)
+    x = torch.zeros((7, 2))
+    bad = [dict(phi_out=torch.empty(7, dtype=torch.float64)),
+           dict(phi_out=torch.empty(6)),
+           dict(psi_out=torch.empty(7, dtype=torch.int64)),
+           dict(psi_out=torch.empty((7, 2), dtype=torch.int32)[:, 0])]
+    for kw in bad:
+        try:
+            smsq.viterbi_step(m, "f32", 2, phi_prev, x_prev=torch.zeros((5, 2)), z_t=torch.zeros(3), x=x, **kw)
+            raise AssertionError("accepted %s" % list(kw))
+        except ValueError as e:
+            assert "_out" in str(e)
+    m.close()

@@ -258,6 +258,28 @@ def test_viterbi_particle_mode_large(n, n_prev, dt, flags):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_viterbi_step_out_tensors(dt):
+    """phi_out / psi_out (a row of a [T, n] back-pointer array) receive the
+    same values the step returns when it allocates its outputs."""
+    announce("viterbi out tensors", dt)
+    n, n_prev = 1200, 900
+    wl, desc, xp, x = _particle_case("range2d", n, n_prev, 12)
+    td = tdt(dt)
+    model = smsq.Model(desc)
+    ws = smsq.workspace()
+    phi_prev = dev(np.random.default_rng(3).normal(size=n_prev), td)
+    args = dict(x_prev=dev(xp, td), z_t=dev(wl.z[0, 1], td), x=dev(x, td), want_flags=False, ws=ws)
+    phi_a, psi_a, _ = smsq.viterbi_step(model, dt, 2, phi_prev, **args)
+    psi_all = torch.full((3, n), -7, dtype=torch.int32, device=DEV)
+    phi_o = torch.full((n,), 5.0, dtype=td, device=DEV)
+    phi_b, psi_b, _ = smsq.viterbi_step(model, dt, 2, phi_prev, phi_out=phi_o, psi_out=psi_all[1], **args)
+    assert phi_b.data_ptr() == phi_o.data_ptr() and psi_b.data_ptr() == psi_all[1].data_ptr()
+    assert torch.equal(phi_a, phi_o) and torch.equal(psi_a, psi_all[1])
+    assert torch.all(psi_all[0] == -7) and torch.all(psi_all[2] == -7)
+    assert smsq.device_status(ws) == smsq.OK
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("flags", [True, False])
 @pytest.mark.parametrize("case", ["nan_score", "inf_row", "dead_block"])
 def test_viterbi_particle_nonfinite(case, dt, flags):

@@ -93,3 +93,46 @@ def test_full_size_teacher_forced_step_against_oracle(name):
     print("rel X err %.3e" % rel)
     assert rel <= TOL_X
     print(check_move(xg, xo, x_init, L, "f32"))
+
+
+@pytest.mark.parametrize("n", [1000, 4000])
+def test_pf_map_seq_full_size_against_oracle(n):
+    """The PF-MAP-Seq workload at the bench's sizes: 200 steps of the
+    range-only model over bootstrap-PF sets of n particles (eq.
+    forward_recursion, Sec. IV-B).  The GPU recursion (FP32, without tie
+    flags, back-pointers written in place as the bench does) and backtrack
+    against the oracle's FP64 J (fixture); and the oracle's FP64 score of the
+    GPU's particle path against that J."""
+    import sys
+    if GOLDEN not in sys.path:
+        sys.path.insert(0, GOLDEN)
+    import make_fullsize_fixtures as MF
+    print("CASE pf-map-seq full size", n, flush=True)
+    f = np.load(os.path.join(GOLDEN, "pf_map_seq_%d.npz" % n), allow_pickle=False)
+    J_o, idx_o = float(f["J"]), f["idx"]
+    desc, x0, z, mask, parts = MF.pf_map_seq_inputs(n)
+    T = parts.shape[0]
+    model = smsq.Model(desc)
+    ws = smsq.workspace()
+    P = torch.tensor(parts, dtype=torch.float32, device=DEV)
+    X0 = torch.tensor(x0, dtype=torch.float32, device=DEV)
+    Z = torch.tensor(z, dtype=torch.float32, device=DEV)
+    M = torch.tensor(mask, dtype=torch.uint8, device=DEV)
+    psi_all = torch.empty((T, n), dtype=torch.int32, device=DEV)
+    phi_buf = [torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(2)]
+    phi = torch.zeros(1, dtype=torch.float32, device=DEV)
+    for t in range(1, T + 1):
+        phi, _, _ = smsq.viterbi_step(model, "f32", t, phi, x_prev=X0 if t == 1 else P[t - 2], z_t=Z[t - 1],
+                                      z_mask=M[t - 1], x=P[t - 1], want_flags=False, ws=ws,
+                                      phi_out=phi_buf[t % 2], psi_out=psi_all[t - 1])
+    idx, J, _ = smsq.backtrack("f32", psi_all, phi, ws=ws)
+    assert smsq.device_status(ws) == smsq.OK
+    J = float(J.cpu().reshape(-1)[0])
+    idx = idx.cpu().numpy().reshape(-1)
+    path = np.concatenate([x0, parts[np.arange(T), idx]])
+    J_path = O.path_score(desc, path, z, mask)
+    tol = TOL_J * max(abs(J_o), T)
+    print("J gpu %.6f oracle %.6f (rel %.2e); oracle score of the gpu path %.6f; path agreement %.3f"
+          % (J, J_o, abs(J - J_o) / max(abs(J_o), T), J_path, np.mean(idx == idx_o)), flush=True)
+    assert abs(J - J_o) <= tol
+    assert abs(J_path - J_o) <= tol

@@ -901,8 +901,9 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
 // a NaN / +inf score offset (checked once per table entry and per row) is
 // the only way to a NaN score; then the workgroup walks its edges one by
 // one, skipping the padding and flagging NaN scores, as the kernel above
-// does.  Bound by the vector ALU: 2d instructions per edge and 7 per lane
-// and tile of eight.
+// does.  Bound by the vector ALU: 2d instructions per edge, and 9 per lane
+// and tile of eight for its maximum, the compare, the two selects and the
+// tile index and address.
 // ---------------------------------------------------------------------------
 constexpr int kRowsWaves = 16;       // waves per workgroup
 constexpr int kRowsPer = 8;          // consecutive edges per lane and tile
@@ -1008,36 +1009,39 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
         T xv[kChunk][D], pv[kChunk];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            // clamped, so that every load is unconditional; padding is chosen below
+            // clamped, so that every load is unconditional; padding is chosen
+            // below (32-bit offsets: n_prev is bounded by the LDS)
             const int j = min(j0 + u * NT + tid, n_prev - 1);
 #pragma unroll
-            for (int a = 0; a < D; ++a) xv[u][a] = x_prev[(long)j * D + a];
+            for (int a = 0; a < D; ++a) xv[u][a] = x_prev[j * D + a];
             pv[u] = phi_prev[j];
         }
         if (j0 == 0) F::mean(m, t, xp0, cen);
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
+            // every entry computed (from a clamped, valid index), padding
+            // selected, only the store guarded: no divergent branches; the
+            // chunk's tail past the table is cut workgroup-uniformly
+            if (j0 + u * NT >= nfill) break;
             const int j = j0 + u * NT + tid;
-            if (j >= nfill) break;
+            const bool real = j < n_prev;
             T mu[D];
-            T s = -R::inf();
-            if (j < n_prev) {
-                F::mean(m, t, xv[u], mu);
+            F::mean(m, t, xv[u], mu);
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    mu[a] = (mu[a] - cen[a]) * rs[a];
-                    bad |= !R::finite(mu[a]);
-                }
-                s = (m.log_z + pv[u]) * (T)kLog2e;
-                bad |= (s != s) || s == R::inf();
-            } else {
-#pragma unroll
-                for (int a = 0; a < D; ++a) mu[a] = 0;
+            for (int a = 0; a < D; ++a) {
+                const T v = (mu[a] - cen[a]) * rs[a];
+                bad |= real & !R::finite(v);
+                mu[a] = real ? v : (T)0;
             }
-            T *e = tab + (long)(j / kTile) * (D + 1) * kTile + (j % kTile);
+            const T sv = (m.log_z + pv[u]) * (T)kLog2e;
+            bad |= real & ((sv != sv) | (sv == R::inf()));
+            const T s = real ? sv : -R::inf();
+            if (j < nfill) {
+                T *e = tab + (j / kTile) * (D + 1) * kTile + (j % kTile);
 #pragma unroll
-            for (int a = 0; a < D; ++a) e[a * kTile] = mu[a];
-            e[D * kTile] = s;
+                for (int a = 0; a < D; ++a) e[a * kTile] = mu[a];
+                e[D * kTile] = s;
+            }
         }
     }
     if (tid < m.obs_dim) s_z[tid] = zr;

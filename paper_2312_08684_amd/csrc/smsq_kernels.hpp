@@ -873,37 +873,34 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
 }
 
 // ---------------------------------------------------------------------------
-// Particle-mode forward recursion without tie flags, rows in blocks of RP.
-// The edge score above is ranked in log2 units, in one fixed direct form:
-// c'_ij = s_j - |y_i - m_j|^2 with s_j = (log_z + phi_{t-1}(j)) log2 e, the
-// particles y_i and transition means m_j centred on f_t(x_{t-1}^0) and scaled
-// by sqrt(log2 e / (2 q)), so that c'_ij = c_ij log2 e; each squared
-// coordinate difference is one fused multiply-subtract, 2d instructions per
-// edge.  The winner's score is taken back to natural-log units (c = ln2 c').
-// LDS holds the workgroup's table tile by tile: for each run of kTile
-// consecutive indices, D + 1 arrays of kTile entries (the means coordinate
-// by coordinate, then s_j), so that one base address with constant offsets
-// serves a whole tile; npad is n_prev rounded
-// up to a multiple of rows_table_align(RP).  Tiles that start at or beyond
-// n_prev are skipped, and the last one is padded to its end with m = 0 and
-// score -inf, which never wins, so no edge needs a bounds check.  A
-// workgroup takes RP = 4, 8 or 16 rows at a time (the launch picks the
-// largest that still gives every compute unit a workgroup): lane l of wave w
-// takes row l % RP and, of the previous particles, the w-th sixteenth of the
-// table in tiles of 8 * 64 / RP indices, eight consecutive ones per lane
-// group l / RP.  Per tile a lane takes the maximum of its eight scores and
-// keeps the first tile that raised its running maximum; that tile's scores
-// are evaluated again at the end (the
-// same arithmetic, hence the same values) to find the lowest index reaching
-// it.  Lanes of a row merge by shuffles, the 16 waves through LDS (read by
-// all of wave 0, then shuffles again), equal scores always going to the
-// lower index.  A non-finite scaled coordinate or
-// a NaN / +inf score offset (checked once per table entry and per row) is
-// the only way to a NaN score; then the workgroup walks its edges one by
-// one, skipping the padding and flagging NaN scores, as the kernel above
-// does.  Bound by the vector ALU: 2d instructions per edge, and 9 per lane
-// and tile of eight for its maximum, the compare, the two selects and the
-// tile index and address.
+// Particle-mode forward recursion without tie flags, rows in blocks of RP.  The
+// edge score above is ranked in log2 units, in one fixed direct form: c'_ij =
+// s_j - |y_i - m_j|^2 with s_j = (log_z + phi_{t-1}(j)) log2 e, the particles
+// y_i and transition means m_j centred on f_t(x_{t-1}^0) and scaled by
+// sqrt(log2 e / (2 q)), so that c'_ij = c_ij log2 e; each squared coordinate
+// difference is one fused multiply-subtract, 2d instructions per edge.  The
+// winner's score is taken back to natural-log units (c = ln2 c').  LDS holds
+// the workgroup's table tile by tile: for each run of kTile consecutive
+// indices, D + 1 arrays of kTile entries (the means coordinate by coordinate,
+// then s_j), so that one base address with constant offsets serves a whole
+// tile; npad is n_prev rounded up to a multiple of rows_table_align(RP).  Tiles
+// that start at or beyond n_prev are skipped, and the last one is padded to its
+// end with m = 0 and score -inf, which never wins, so no edge needs a bounds
+// check.  A workgroup takes RP = 4, 8 or 16 rows at a time (the launch picks
+// the largest that still gives every compute unit a workgroup): lane l of wave
+// w takes row l % RP and, of the previous particles, the w-th sixteenth of the
+// table in tiles of 8 * 64 / RP indices, eight consecutive ones per lane group
+// l / RP.  Per tile a lane takes the maximum of its eight scores and keeps the
+// first tile that raised its running maximum; that tile's scores are evaluated
+// again at the end (the same arithmetic, hence the same values) to find the
+// lowest index reaching it.  Lanes of a row merge by shuffles, the 16 waves
+// through LDS (read by all of wave 0, then shuffles again), equal scores always
+// going to the lower index.  A non-finite scaled coordinate or a NaN / +inf
+// score offset (checked once per table entry and per row) is the only way to a
+// NaN score; then the workgroup walks its edges one by one, skipping the
+// padding and flagging NaN scores, as the kernel above does.  Bound by the
+// vector ALU: 2d instructions per edge, and 9 per lane and tile of eight for
+// its maximum, the compare, the two selects and the tile index and address.
 // ---------------------------------------------------------------------------
 constexpr int kRowsWaves = 16;       // waves per workgroup
 constexpr int kRowsPer = 8;          // consecutive edges per lane and tile

@@ -186,12 +186,67 @@ def test_viterbi_particle_mode(name, dt, flags):
     c = A + phi_prev[None, :]
     best = c.max(1)
     assert np.all(c[np.arange(n), psi] >= best - 4 * tol * np.maximum(1, np.abs(best)))
+    if flags:
+        # tie flags wherever the runner-up gap is clearly on one side of
+        # tie_tol max(1, |best|)
+        c2 = c.copy()
+        c2[np.arange(n), c.argmax(1)] = -np.inf
+        gap = best - c2.max(1)
+        thr = tol * np.maximum(1.0, np.abs(best))
+        clear0, clear1 = gap > 1.5 * thr, gap < 0.5 * thr
+        fl = host(fl)
+        print("tie flags: %d clear 0, %d clear 1" % (clear0.sum(), clear1.sum()))
+        assert clear0.sum() > 0
+        assert np.all(fl[clear0] == 0) and np.all(fl[clear1] == 1)
+        assert np.array_equal(fl[clear0 | clear1], fl_o[clear0 | clear1])
     err = np.abs(phi - phi_o) / np.maximum(1, np.abs(phi_o))
     print("phi rel err", err.max())
     # FP32 evaluation of the log-densities (e.g. the arm's forward kinematics,
     # d ell / d p ~ |z - p| / r ~ 500 times a ~1e-7 position rounding) bounds
     # the FP32 error near 1e-4 relative
     assert err.max() <= (1e-4 if dt == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("name", ["range2d", "cv4d", "arm7"])
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_viterbi_particle_tie_flags(name, dt):
+    """Tie flags of particle mode (eq. forward_recursion; runner-up within
+    tie_tol max(1, |best|)) against the oracle's, on every row whose gap is
+    clearly on one side of the threshold.  Exact duplicates of the previous
+    particles with the highest scores (as resampling makes) give exact ties;
+    the others give clear gaps."""
+    announce("viterbi particle tie flags", name, dt)
+    n, n_prev = 400, 300
+    wl, desc, xp, x = _particle_case(name, n, n_prev, 21)
+    z = wl.z[0, 1]
+    mask = None if wl.mask is None else wl.mask[0, 1]
+    phi_prev = np.random.default_rng(22).normal(size=n_prev) * 3
+    top = np.argsort(phi_prev[:n_prev - 4])[-4:]
+    xp[n_prev - 4:] = xp[top]
+    phi_prev[n_prev - 4:] = phi_prev[top]
+    td = tdt(dt)
+    if dt == "f32":
+        xp, x, phi_prev, z = (v.astype(np.float32).astype(np.float64) for v in (xp, x, phi_prev, z))
+    tol = 1e-5 if dt == "f32" else 1e-9
+    phi_o, psi_o, fl_o, st = O.viterbi_particle(desc, 2, xp, phi_prev, z, mask, x, tie_tol=tol)
+    assert st == O.OK
+    ws = smsq.workspace()
+    _, _, fl = smsq.viterbi_step(smsq.Model(desc), dt, 2, dev(phi_prev, td), x_prev=dev(xp, td), z_t=dev(z, td),
+                                 z_mask=None if mask is None else dev(mask, torch.uint8), x=dev(x, td),
+                                 tie_tol=tol, ws=ws)
+    assert smsq.device_status(ws) == smsq.OK
+    A, _ = O.particle_lattice(desc, 2, xp, z, mask, x)
+    c = A + phi_prev[None, :]
+    best = c.max(1)
+    c[np.arange(n), c.argmax(1)] = -np.inf
+    gap = best - c.max(1)
+    thr = tol * np.maximum(1.0, np.abs(best))
+    clear0, clear1 = gap > 1.5 * thr, gap < 0.5 * thr
+    fl = host(fl)
+    print("tie flags: %d clear 0, %d clear 1, %d between" % (clear0.sum(), clear1.sum(), n - clear0.sum() - clear1.sum()))
+    assert clear0.sum() > 0 and clear1.sum() > 0
+    assert np.array_equal(fl_o[clear0 | clear1], clear1[clear0 | clear1].astype(np.uint8))
+    assert np.all(fl[clear0] == 0) and np.all(fl[clear1] == 1)
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
@@ -342,16 +397,33 @@ def test_pf_map_seq_forward_recursion(dt, flags):
     phi_g = torch.zeros(1, dtype=td, device=DEV)
     psi_all = torch.zeros((T, n), dtype=torch.int32, device=DEV)
     psi_o_all = np.zeros((T, n), dtype=np.int32)
+    flag_counts = [0, 0]
     for t in range(1, T + 1):
         xp = x0 if t == 1 else parts[t - 2]
         ph_o, ps_o, fl_o, st = O.viterbi_particle(desc, t, xp, phi_o, z[t - 1], None, parts[t - 1], tie_tol=tol)
         assert st == O.OK
         # same scores on both sides for this step's comparison
-        ph_t, ps_t, _ = smsq.viterbi_step(model, dt, t, dev(rnd(phi_o), td), x_prev=dev(xp, td),
-                                          z_t=dev(z[t - 1], td), x=dev(parts[t - 1], td), tie_tol=tol, ws=ws,
-                                          want_flags=flags)
+        ph_t, ps_t, fl_t = smsq.viterbi_step(model, dt, t, dev(rnd(phi_o), td), x_prev=dev(xp, td),
+                                             z_t=dev(z[t - 1], td), x=dev(parts[t - 1], td), tie_tol=tol, ws=ws,
+                                             want_flags=flags)
         sure = fl_o == 0
         assert np.array_equal(host(ps_t)[sure], ps_o[sure]), t
+        if flags:
+            # tie flags against the oracle's scores wherever the runner-up gap
+            # is clearly on one side of tie_tol max(1, |best|)
+            A, _ = O.particle_lattice(desc, t, xp, z[t - 1], None, parts[t - 1])
+            c = A + rnd(phi_o)[None, :]
+            top = c.argmax(1)
+            best = c[np.arange(n), top]
+            c[np.arange(n), top] = -np.inf
+            gap = best - c.max(1)
+            thr = tol * np.maximum(1.0, np.abs(best))
+            clear0, clear1 = gap > 1.5 * thr, gap < 0.5 * thr
+            fl_t = host(fl_t)
+            assert np.all(fl_t[clear0] == 0) and np.all(fl_t[clear1] == 1), t
+            assert np.array_equal(fl_o[clear0 | clear1], fl_t[clear0 | clear1]), t
+            flag_counts[0] += int(clear0.sum())
+            flag_counts[1] += int(clear1.sum())
         err = np.abs(host(ph_t).astype(np.float64) - ph_o) / np.maximum(1, np.abs(ph_o))
         assert err.max() <= (1e-5 if dt == "f32" else 1e-12), (t, err.max())
         # free-running chain on the GPU's own scores
@@ -370,6 +442,9 @@ def test_pf_map_seq_forward_recursion(dt, flags):
     assert dJ <= (1e-5 if dt == "f32" else 1e-12)
     if dt == "f64":
         assert np.array_equal(host(idx).reshape(-1), idx_o)
+    if flags:
+        print("tie flags compared: %d clear 0, %d clear 1" % tuple(flag_counts))
+        assert flag_counts[0] > 0
 
 
 # ---------------------------------------------------------------------------

@@ -424,18 +424,19 @@ template <typename T> long rows_lds_bytes(int n, int n_prev, int d)
 {
     return (long)(d + 1) * rows_npad(n_prev, rows_pass(n)) * sizeof(T);
 }
-constexpr long kRowsStaticLds = 4096;   // row-merge slots and observation (FP64: 3360 bytes), rounded up
+constexpr long kRowsStaticLds = 6144;   // row-merge slots, runner-ups, observation (FP64: 5472 bytes), rounded up
 
 // states for which the 16-rows kernel runs without register spills (its
 // eight-edge tiles); the others take the two-waves-per-row kernel
 template <typename T> constexpr bool rows_fits(int d) { return sizeof(T) == 4 ? d <= 8 : d <= 2; }
 
-template <typename T, int KIND, int D, int RP>
+template <typename T, int KIND, int D, int RP, bool FLAGS>
 smsq_status_t launch_viterbi_rows_rp(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
                                      const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
-                                     void *phi, int32_t *psi, uint32_t *status, hipStream_t s)
+                                     void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                     hipStream_t s)
 {
-    auto fn = &k_viterbi_particle_rows<T, KIND, D, RP>;
+    auto fn = &k_viterbi_particle_rows<T, KIND, D, RP, FLAGS>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] { attr_err = allow_big_lds(fn, kRowsStaticLds); });
@@ -444,38 +445,51 @@ smsq_status_t launch_viterbi_rows_rp(const smsq_model_desc_t &d, int t, int n, i
     const int grid = std::min((n + RP - 1) / RP, kWideMaxBlocks);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kRowsWaves * kWave), (size_t)rows_lds_bytes<T>(n, n_prev, D), s,
                        make_dev_model<T>(d), t, n, n_prev, npad, (const T *)x_prev, (const T *)phi_prev,
-                       (const T *)z, mask, (const T *)x, (T *)phi, psi, status);
+                       (const T *)z, mask, (const T *)x, (T *)phi, psi, flags, (T)tie_tol, status);
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
+template <typename T, int KIND, int D, bool FLAGS>
+smsq_status_t launch_viterbi_rows_flags(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
+                                        const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
+                                        void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                        hipStream_t s)
+{
+#define SMSQ_ROWS_RP(RP) \
+    launch_viterbi_rows_rp<T, KIND, D, RP, FLAGS>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi, flags, \
+                                                  tie_tol, status, s)
+    switch (rows_pass(n)) {
+    case 16: return SMSQ_ROWS_RP(16);
+    case 8: return SMSQ_ROWS_RP(8);
+    default: return SMSQ_ROWS_RP(4);
+    }
+#undef SMSQ_ROWS_RP
 }
 
 template <typename T, int KIND, int D>
 smsq_status_t launch_viterbi_rows_kd(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
                                      const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
-                                     void *phi, int32_t *psi, uint32_t *status, hipStream_t s)
+                                     void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                     hipStream_t s)
 {
     if constexpr (!rows_fits<T>(D)) {
         return SMSQ_ERR_UNSUPPORTED;
     } else {
-        switch (rows_pass(n)) {
-        case 16:
-            return launch_viterbi_rows_rp<T, KIND, D, 16>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi,
-                                                          status, s);
-        case 8:
-            return launch_viterbi_rows_rp<T, KIND, D, 8>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi,
-                                                         status, s);
-        default:
-            return launch_viterbi_rows_rp<T, KIND, D, 4>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi,
-                                                         status, s);
-        }
+        return flags ? launch_viterbi_rows_flags<T, KIND, D, true>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x,
+                                                                   phi, psi, flags, tie_tol, status, s)
+                     : launch_viterbi_rows_flags<T, KIND, D, false>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x,
+                                                                    phi, psi, flags, tie_tol, status, s);
     }
 }
 
 template <typename T>
 smsq_status_t launch_viterbi_rows(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,
                                   const void *phi_prev, const void *z, const uint8_t *mask, const void *x,
-                                  void *phi, int32_t *psi, uint32_t *status, hipStream_t s)
+                                  void *phi, int32_t *psi, uint8_t *flags, double tie_tol, uint32_t *status,
+                                  hipStream_t s)
 {
-#define SMSQ_ROWS(K, DD) launch_viterbi_rows_kd<T, K, DD>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi, status, s)
+#define SMSQ_ROWS(K, DD) \
+    launch_viterbi_rows_kd<T, K, DD>(d, t, n, n_prev, x_prev, phi_prev, z, mask, x, phi, psi, flags, tie_tol, status, s)
     switch (d.kind) {
     case SMSQ_MODEL_GROWTH1D: return SMSQ_ROWS(GROWTH1D, 1);
     case SMSQ_MODEL_RANGE2D: return SMSQ_ROWS(RANGE2D, 2);
@@ -1110,18 +1124,17 @@ smsq_status_t smsq_viterbi_step(smsq_model_t model, smsq_dtype_t dtype, int t, i
     }
     if (!model || t < 1 || !x_prev || !z_t || !x) return SMSQ_ERR_INVALID;
     // particle mode: chip-wide kernels whose LDS holds the means table; 4..16
-    // rows per workgroup pass without tie flags, two waves per row with them
+    // rows per workgroup pass for the states that fit it, two waves per row
+    // for the others
     const smsq_model_desc_t &d = model->desc;
-    if (!tie_flags) {
-        if (dtype == SMSQ_F64 && rows_fits<double>(d.d) &&
-            rows_lds_bytes<double>(n, n_prev, d.d) <= kLdsLimit - kRowsStaticLds)
-            return launch_viterbi_rows<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi,
-                                               status_ptr(ws), stream);
-        if (dtype == SMSQ_F32 && rows_fits<float>(d.d) &&
-            rows_lds_bytes<float>(n, n_prev, d.d) <= kLdsLimit - kRowsStaticLds)
-            return launch_viterbi_rows<float>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi,
-                                              status_ptr(ws), stream);
-    }
+    if (dtype == SMSQ_F64 && rows_fits<double>(d.d) &&
+        rows_lds_bytes<double>(n, n_prev, d.d) <= kLdsLimit - kRowsStaticLds)
+        return launch_viterbi_rows<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,
+                                           tie_tol, status_ptr(ws), stream);
+    if (dtype == SMSQ_F32 && rows_fits<float>(d.d) &&
+        rows_lds_bytes<float>(n, n_prev, d.d) <= kLdsLimit - kRowsStaticLds)
+        return launch_viterbi_rows<float>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,
+                                          tie_tol, status_ptr(ws), stream);
     if (dtype == SMSQ_F64) {
         if (wide_lds_bytes<double>(n_prev, d.d) > kLdsLimit - kWideStaticLds) return SMSQ_ERR_UNSUPPORTED;
         return launch_viterbi_wide<double>(d, t, n, n_prev, x_prev, phi_prev, z_t, z_mask, x, phi, psi, tie_flags,

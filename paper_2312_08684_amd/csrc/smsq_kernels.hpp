@@ -873,7 +873,7 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
 }
 
 // ---------------------------------------------------------------------------
-// Particle-mode forward recursion without tie flags, rows in blocks of RP.  The
+// Particle-mode forward recursion, rows in blocks of RP.  The
 // edge score above is ranked in log2 units, in one fixed direct form: c'_ij =
 // s_j - |y_i - m_j|^2 with s_j = (log_z + phi_{t-1}(j)) log2 e, the particles
 // y_i and transition means m_j centred on f_t(x_{t-1}^0) and scaled by
@@ -898,7 +898,11 @@ __global__ __launch_bounds__(NT) void k_viterbi_particle_wide(DevModel<T> m, int
 // going to the lower index.  A non-finite scaled coordinate or a NaN / +inf
 // score offset (checked once per table entry and per row) is the only way to a
 // NaN score; then the workgroup walks its edges one by one, skipping the
-// padding and flagging NaN scores, as the kernel above does.  Bound by the
+// padding and flagging NaN scores, as the kernel above does.  FLAGS: each
+// lane also keeps the best of its other tiles' maxima and, at the end, of
+// the winning tile's other scores (its runner-up over all its indices but
+// the winner); merges keep the better of the winner's runner-up and the
+// loser's best; the tie test runs in log2 units.  Bound by the
 // vector ALU: 2d instructions per edge, and 9 per lane and tile of eight for
 // its maximum, the compare, the two selects and the tile index and address.
 // ---------------------------------------------------------------------------
@@ -944,6 +948,18 @@ template <typename T> __device__ __forceinline__ void take_better(T &v, int &j, 
     j = b ? jo : j;
 }
 
+// the same with runner-ups (the best score over the other indices): the
+// winner keeps the better of its runner-up and the loser's best
+template <typename T> __device__ __forceinline__ void take_better(T &v, int &j, T &r, T vo, int jo, T ro)
+{
+    const bool b = (vo > v) | ((vo == v) & (jo < j));
+    const T lose = b ? v : vo;
+    const T keep = b ? ro : r;
+    v = b ? vo : v;
+    j = b ? jo : j;
+    r = vmax_(keep, lose);
+}
+
 // log2-unit scores of K edges of row y: p points at the first of them in
 // the coordinate-0 array of a tile of TILE indices
 template <typename T, int D, int K, int TILE>
@@ -962,10 +978,11 @@ __device__ __forceinline__ void row_edge_scores(const T *p, const T (&y)[D], T (
     }
 }
 
-template <typename T, int KIND, int D, int RP>
+template <typename T, int KIND, int D, int RP, bool FLAGS>
 __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
     DevModel<T> m, int t, int n, int n_prev, int npad, const T *__restrict__ x_prev, const T *__restrict__ phi_prev,
-    const T *__restrict__ z, const uint8_t *mask, const T *__restrict__ x, T *phi, int32_t *psi, uint32_t *status)
+    const T *__restrict__ z, const uint8_t *mask, const T *__restrict__ x, T *phi, int32_t *psi, uint8_t *flags,
+    T tie_tol, uint32_t *status)
 {
     using F = Family<T, KIND, D>;
     using R = RealOps<T>;
@@ -976,6 +993,7 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
     T *tab = (T *)smem;                               // [npad / kTile][D + 1][kTile]
     __shared__ T s_v[kRowsWaves][RP];
     __shared__ int s_j[kRowsWaves][RP];
+    __shared__ T s_r[FLAGS ? kRowsWaves : 1][RP];       // runner-ups (tie flags)
     __shared__ T s_z[kMaxObs];
     __shared__ uint8_t s_mask[kMaxObs];
     __shared__ int s_bad[kRowsWaves];
@@ -1076,10 +1094,10 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
         }
         // every wave holds the same rows, so this choice is the workgroup's
         const bool exact = bad || __any(rbad);
-        T v = -R::inf();
+        T v = -R::inf(), rv = -R::inf();   // best and (FLAGS) runner-up
         int jb = 0x7fffffff;
         if (!exact) {
-            T best = -R::inf();
+            T best = -R::inf(), other = -R::inf();   // other: the other tiles' maxima
             int bt = -1;
             for (int tt = 0; tt < span && jw0 + tt < n_prev; tt += kTile) {
                 T c[kRowsPer];
@@ -1089,9 +1107,11 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
                 for (int k = 3; k + 1 < kRowsPer; k += 2) mx = vmax_(vmax_(mx, c[k]), c[k + 1]);
                 if (kRowsPer % 2 == 0) mx = vmax_(mx, c[kRowsPer - 1]);
                 const bool up = mx > best;
+                if (FLAGS) other = up ? best : vmax_(other, mx);
                 bt = up ? tt : bt;
                 best = up ? mx : best;
             }
+            rv = other;
             if (bt >= 0) {
                 T c[kRowsPer];
                 row_edge_scores<T, D, kRowsPer, kTile>(tw + (long)bt * (D + 1), y, c);
@@ -1100,6 +1120,10 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
                     const bool b = c[k] > v;
                     v = b ? c[k] : v;
                     jb = b ? jw + bt + k : jb;
+                }
+                if (FLAGS) {
+#pragma unroll
+                    for (int k = 0; k < kRowsPer; ++k) rv = jw + bt + k == jb ? rv : vmax_(rv, c[k]);
                 }
             }
         } else {
@@ -1112,6 +1136,7 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
                     if (j < n_prev) {
                         nan_seen |= live && (c[k] != c[k]);
                         const bool b = c[k] > v;
+                        if (FLAGS) rv = b ? v : (c[k] > rv ? c[k] : rv);
                         v = b ? c[k] : v;
                         jb = b ? j : jb;
                     }
@@ -1122,11 +1147,13 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
         for (int off = RP; off < kWave; off <<= 1) {
             const T vo = __shfl_xor(v, off, kWave);
             const int jo = __shfl_xor(jb, off, kWave);
-            take_better(v, jb, vo, jo);
+            if (FLAGS) take_better(v, jb, rv, vo, jo, __shfl_xor(rv, off, kWave));
+            else take_better(v, jb, vo, jo);
         }
         if (lane < RP) {
             s_v[w][lane] = v;
             s_j[w][lane] = jb;
+            if (FLAGS) s_r[FLAGS ? w : 0][lane] = rv;
         }
         __syncthreads();
         if (w == 0) {
@@ -1135,20 +1162,31 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
             constexpr int kGroups = kWave / RP;
             T b = s_v[grp][rl];
             int arg = s_j[grp][rl];
+            T r = FLAGS ? s_r[FLAGS ? grp : 0][rl] : (T)0;
 #pragma unroll
-            for (int q = 1; q < kRowsWaves / kGroups; ++q)
-                take_better(b, arg, s_v[grp + q * kGroups][rl], s_j[grp + q * kGroups][rl]);
+            for (int q = 1; q < kRowsWaves / kGroups; ++q) {
+                const int h = grp + q * kGroups;
+                if (FLAGS) take_better(b, arg, r, s_v[h][rl], s_j[h][rl], s_r[FLAGS ? h : 0][rl]);
+                else take_better(b, arg, s_v[h][rl], s_j[h][rl]);
+            }
 #pragma unroll
             for (int off = RP; off < kWave; off <<= 1) {
                 const T vo = __shfl_xor(b, off, kWave);
                 const int jo = __shfl_xor(arg, off, kWave);
-                take_better(b, arg, vo, jo);
+                if (FLAGS) take_better(b, arg, r, vo, jo, __shfl_xor(r, off, kWave));
+                else take_better(b, arg, vo, jo);
             }
             if (lane < RP && live) {
                 const T ell = F::loglik(m, s_z, mk, xi);
                 const T ph = b * (T)kLn2 + ell;
                 phi[i] = ph;
                 psi[i] = arg == 0x7fffffff ? 0 : arg;
+                if (FLAGS) {
+                    // runner-up within tie_tol max(1, |best|), in log2 units
+                    const T mag = b < 0 ? -b : b;
+                    const T sc = mag > (T)kLog2e ? mag : (T)kLog2e;
+                    flags[i] = (n_prev > 1 && r >= b - tie_tol * sc) ? 1 : 0;
+                }
                 nan_seen |= (ell != ell) || (ph != ph);
             }
         }

@@ -156,8 +156,9 @@ def _particle_case(name, n, n_prev, seed):
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("flags", [True, False])
 def test_viterbi_particle_mode(name, dt, flags):
-    """Particle mode per model, with tie flags (two waves per row) and without
-    (16 rows per workgroup pass, for the states that fit it)."""
+    """Particle mode per model, with and without tie flags (rows in blocks
+    of 4..16 per workgroup pass for the states that fit it, two waves per row
+    for the others)."""
     announce("viterbi particle", name, dt, flags)
     n, n_prev = 150, 77
     wl, desc, xp, x = _particle_case(name, n, n_prev, 3)
@@ -280,7 +281,7 @@ def test_backtrack_bit_exact(dt):
 def test_viterbi_particle_mode_large(n, n_prev, dt, flags):
     """Particle mode at PF-MAP-Seq sizes (up to 4000 x 4000 edges of the
     range-only model), with one row, one previous particle, ragged tails,
-    more rows than one pass of the 16-rows kernel's grid covers and a table
+    more rows than one pass of the rows kernel's grid covers and a table
     of several load chunks."""
     announce("viterbi particle large", n, n_prev, dt, flags)
     wl, desc, xp, x = _particle_case("range2d", n, n_prev, 4)

@@ -348,7 +348,9 @@ smsq_status_t smsq_run_sequence_noalloc(smsq_model_t model, smsq_dtype_t dtype, 
  * persistent launch over all sequences with T >= t (one workgroup per
  * sequence step, taken longest first from an atomic queue), followed at the
  * end by one backtrack launch over all sequences.  FP32, matrix-core step
- * kernel; families GROWTH1D, RANGE2D, CV4D and ARM7.
+ * kernel, RBF kernel; families GROWTH1D, RANGE2D, CV4D, ARM7, SE2 and
+ * LINGAUSS at d = 2 (ARM14 and the other linear-Gaussian sizes run through
+ * smsq_run_batch / smsq_run_sequence).
  *
  * The plan owns its device storage (every step's particles, forward-
  * recursion scores and backpointers of every sequence), allocated at
@@ -507,7 +509,9 @@ smsq_status_t smsq_init_mlp_sample(smsq_init_mlp_t mlp, smsq_init_set_t set, int
  * everywhere).  Per step the plan then also runs the features, the forward
  * pass and the sampler; a sequence whose proposal is not finite falls back
  * to the predictive initialisation for that step.
- * max_batch of the network must cover the plan's sequences. (host) */
+ * max_batch of the network must cover the plan's sequences.  The proposal's
+ * features cover GROWTH1D, RANGE2D, CV4D and ARM7: a plan holding another
+ * family gets SMSQ_ERR_UNSUPPORTED for a non-NULL mlp. (host) */
 smsq_status_t smsq_batch_plan_set_init(smsq_batch_plan_t plan, smsq_init_mlp_t mlp);
 
 /* Reads the workspace status word (synchronous device-to-host copy; call

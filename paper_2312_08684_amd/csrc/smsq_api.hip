@@ -830,6 +830,7 @@ smsq_status_t init_propose(smsq_init_mlp_s *m, const InitExample *ex, int count,
 
 struct smsq_batch_plan_s {
     int count = 0, T_max = 0, max_active = 0, max_n = 0;
+    bool proposal_ok = true;              // every sequence of a proposal family
     std::vector<int> list_off, list_cnt;  // per step t - 1
     std::vector<SeqDesc> host;            // per sequence
     SeqDesc *seqs = nullptr;
@@ -910,7 +911,17 @@ struct smsq_batch_plan_s {
 
 namespace {
 
+// the families of the learned proposal (and their plan dispatch codes)
 bool batch_family(int kind) { return kind >= SMSQ_MODEL_GROWTH1D && kind <= SMSQ_MODEL_ARM7; }
+
+// a plan's dispatch code of a model, or -1 when plans do not carry it
+int batch_code(const smsq_model_desc_t &d)
+{
+    if (batch_family(d.kind)) return d.kind;
+    if (d.kind == SMSQ_MODEL_SE2) return kCodeSE2;
+    if (d.kind == SMSQ_MODEL_LINGAUSS && d.d == 2) return kCodeLinGauss2;
+    return -1;
+}
 
 // Algorithm 2 for `batch` sequences in the scratch memory `ws` (ws_bytes
 // bytes, laid out by run_layout): the body of smsq_run_batch, shared with the
@@ -1283,7 +1294,7 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
             !q.logpost_out || (q.use_proposal != 0 && q.use_proposal != 1))
             return SMSQ_ERR_INVALID;
         const smsq_model_desc_t &d = models[q.model]->desc;
-        if (!batch_family(d.kind)) return SMSQ_ERR_UNSUPPORTED;
+        if (batch_code(d) < 0) return SMSQ_ERR_UNSUPPORTED;
         const MfmaLds L1(q.n, q.n), L2(q.n, 1);
         if (L1.npad > kMaxParticles || L1.total > kLdsLimit - kBatchStaticLds ||
             L2.total > kLdsLimit - kBatchStaticLds)
@@ -1356,7 +1367,8 @@ smsq_status_t smsq_batch_plan_create(const smsq_model_t *models, const smsq_svgd
         sd.n = q.n;
         sd.T = q.T;
         sd.d = d.d;
-        sd.code = d.kind;
+        sd.code = batch_code(d);
+        p->proposal_ok &= batch_family(d.kind);
         sd.n_iter = o.n_iter;
         sd.bw_mode = o.bw_mode;
         sd.trans_mode = o.trans_mode;
@@ -1713,6 +1725,7 @@ smsq_status_t smsq_init_mlp_sample(smsq_init_mlp_t m, smsq_init_set_t st, int fi
 smsq_status_t smsq_batch_plan_set_init(smsq_batch_plan_t p, smsq_init_mlp_t m)
 {
     if (!p) return SMSQ_ERR_INVALID;
+    if (m && !p->proposal_ok) return SMSQ_ERR_UNSUPPORTED;   // the proposal's features cover four families
     if (m && m->max_batch < p->max_active) return SMSQ_ERR_INVALID;
     if (m && !p->init_ex) {
         size_t total = 0;

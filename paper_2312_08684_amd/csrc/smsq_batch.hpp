@@ -15,8 +15,12 @@
 
 namespace smsq {
 
-// Model families the batched kernel carries (dispatch code = family).
-constexpr int kBatchFamilies = 4;  // GROWTH1D (d 1), RANGE2D (2), CV4D (4), ARM7 (7)
+// Model families the batched kernel carries, by dispatch code: the first
+// four codes equal the model kinds (GROWTH1D d 1, RANGE2D 2, CV4D 4, ARM7 7,
+// the families of the learned proposal), then the pose family (d 3) and the
+// linear-Gaussian family at d = 2.
+constexpr int kCodeSE2 = 4, kCodeLinGauss2 = 5;
+constexpr int kBatchFamilies = 6;
 
 struct SeqDesc {
     DevModel<float> m;
@@ -98,9 +102,13 @@ __device__ __forceinline__ void batch_step_loop(const StepArgs<float> *__restric
         case RANGE2D: step_mfma_body<RANGE2D, 2, TS, false>(a, 0); break;
         case CV4D: step_mfma_body<CV4D, 4, TS, false>(a, 0); break;
         case ARM7: step_mfma_body<ARM7, 7, TS, false>(a, 0); break;
+        case kCodeSE2: step_mfma_body<SE2, 3, TS, false>(a, 0); break;
+        case kCodeLinGauss2: step_mfma_body<LINGAUSS, 2, TS, false>(a, 0); break;
         case kBatchFamilies + GROWTH1D: step_mfma_body<GROWTH1D, 1, TS, true>(a, 0); break;
         case kBatchFamilies + RANGE2D: step_mfma_body<RANGE2D, 2, TS, true>(a, 0); break;
         case kBatchFamilies + CV4D: step_mfma_body<CV4D, 4, TS, true>(a, 0); break;
+        case kBatchFamilies + kCodeSE2: step_mfma_body<SE2, 3, TS, true>(a, 0); break;
+        case kBatchFamilies + kCodeLinGauss2: step_mfma_body<LINGAUSS, 2, TS, true>(a, 0); break;
         default: step_mfma_body<ARM7, 7, TS, true>(a, 0); break;
         }
         __syncthreads();  // LDS is reused by the next item

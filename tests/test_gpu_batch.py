@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from paper_2312_08684_amd import scenarios as S
 from paper_2312_08684_amd import smsq
 
@@ -172,19 +173,14 @@ def test_batch_plan_argument_errors():
     big = [dict(seqs[0], n=1025)]
     with pytest.raises(smsq.SmsqError):
         smsq.BatchPlan(models, opts, big)
-    wl = S.make_workload("lingauss", B=1, seed=0, T=3)
-    lg = [smsq.Model(wl.model)]
-    q = {"model": 0, "n": 32, "seed": 1, "x0": torch.zeros(wl.model.d, device="cuda"),
-         "z": torch.zeros((3, wl.model.obs_dim), device="cuda"), "z_mask": None}
+    # the linear-Gaussian family runs in plans at d = 2 only
+    lg3 = S.lingauss_model(np.eye(3) * 0.9, np.eye(3)[:1], [0.05, 0.05, 0.05], [0.1])
+    q = {"model": 0, "n": 32, "seed": 1, "x0": torch.zeros(3, device="cuda"),
+         "z": torch.zeros((3, lg3.obs_dim), device="cuda"), "z_mask": None}
     with pytest.raises(smsq.SmsqError) as e:
-        smsq.BatchPlan(lg, [smsq.opts_from(wl.opts)], [q])
+        smsq.BatchPlan([smsq.Model(lg3)], [smsq.opts(10, 0.01)], [q])
     assert e.value.status == smsq.ERR_UNSUPPORTED
-    se2 = S.make_workload("scenario_b", B=1, seed=0, T=3)     # the pose family runs outside plans
-    q2 = dict(q, x0=torch.zeros(3, device="cuda"), z=torch.zeros((3, 2), device="cuda"))
-    with pytest.raises(smsq.SmsqError) as e:
-        smsq.BatchPlan([smsq.Model(se2.model)], [smsq.opts_from(se2.opts)], [q2])
-    assert e.value.status == smsq.ERR_UNSUPPORTED
-    arm = S.make_workload("scenario_d", B=1, seed=0, T=3)     # and so does the 14-D manipulator
+    arm = S.make_workload("scenario_d", B=1, seed=0, T=3)     # the 14-D manipulator runs outside plans
     q3 = dict(q, x0=torch.zeros(14, device="cuda"), z=torch.zeros((3, 3), device="cuda"))
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan([smsq.Model(arm.model)], [smsq.opts_from(arm.opts)], [q3])
@@ -192,6 +188,44 @@ def test_batch_plan_argument_errors():
     imq = [smsq.opts(o.n_iter, o.step, o.bw_scale, kernel="imq") for o in opts]   # plans run the RBF kernel
     with pytest.raises(smsq.SmsqError) as e:
         smsq.BatchPlan(models, imq, seqs)
+    assert e.value.status == smsq.ERR_UNSUPPORTED
+
+
+POSE_MIX = [
+    ("scenario_b", 20, 6, 10),
+    ("lingauss", 64, 7, 10),
+    ("range2d", 100, 4, 10),
+    ("scenario_b", 130, 5, 10),
+    ("lingauss", 300, 3, 10),
+    ("arm7", 64, 4, 12),
+]
+
+
+def test_batch_pose_and_linear_gaussian_families():
+    """The pose family (Sec. V-B, d = 3, unknown association) and the
+    linear-Gaussian family at d = 2 in a plan, beside other families: every
+    sequence matches the single-sequence path; a proposal network cannot be
+    attached to such a plan (its features cover the other four families)."""
+    models, opts, seqs = _build(POSE_MIX, base_seed=300)
+    plan = smsq.BatchPlan(models, opts, seqs)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == smsq.OK
+    _check_equal(plan, models, opts, seqs, POSE_MIX)
+    # and the new families against the FP64 oracle (Algorithm 2, same keys)
+    for i, (name, n, T, L) in enumerate(POSE_MIX):
+        if name not in ("scenario_b", "lingauss"):
+            continue
+        wl = S.make_workload(name, B=1, seed=300 + i, n=n, T=T, n_iter=L)
+        o = wl.opts
+        res = O.run_sequence(wl.model, T, n, wl.x0[0], wl.z[0], None if wl.mask is None else wl.mask[0],
+                             seqs[i]["seed"], 0, o.n_iter, o.step, o.bw_scale, o.bw_mode, o.trans_mode)
+        assert res["status"] == O.OK
+        J = plan.J[i].item()
+        print("oracle %s n=%d: J plan %.6f oracle %.6f" % (name, n, J, res["J"]), flush=True)
+        assert abs(J - res["J"]) <= 1e-3 * max(abs(res["J"]), T)
+    with pytest.raises(smsq.SmsqError) as e:
+        plan.set_init(smsq.InitMLP(seed=0, max_batch=len(seqs)))
     assert e.value.status == smsq.ERR_UNSUPPORTED
 
 

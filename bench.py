@@ -31,6 +31,8 @@ import json
 import math
 import os
 import platform
+import re
+import subprocess
 import sys
 import time
 
@@ -115,6 +117,30 @@ def measured_traffic(name: str, B: int, n: int, dt: str):
         return float(fields["HBM bytes per launch"])
     except (KeyError, ValueError):
         return None
+
+
+def device_info(torch) -> dict:
+    """The GPU the line was measured on: torch's device properties and, from
+    rocminfo, the first GPU agent's compute units and maximum clock, with the
+    FP32 matrix-core peak they imply (256 flops per clock per compute unit)."""
+    p = torch.cuda.get_device_properties(0)
+    info = {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "compute_units": p.multi_processor_count,
+            "hbm_bytes": p.total_memory}
+    try:
+        txt = subprocess.run(["rocminfo"], capture_output=True, text=True, timeout=60).stdout
+    except (OSError, subprocess.SubprocessError):
+        return info
+    for block in txt.split("\nAgent ")[1:]:
+        if not re.search(r"Device Type:\s+GPU", block):
+            continue
+        cu = re.search(r"Compute Unit:\s+(\d+)", block)
+        mhz = re.search(r"Max Clock Freq\. \(MHz\):\s+(\d+)", block)
+        if cu and mhz:
+            info["rocminfo_compute_units"] = int(cu.group(1))
+            info["rocminfo_max_clock_mhz"] = int(mhz.group(1))
+            info["fp32_matrix_peak_tflops"] = int(cu.group(1)) * int(mhz.group(1)) * 1e6 * 256 / 1e12
+        break
+    return info
 
 
 def cpu_model() -> str:
@@ -885,6 +911,7 @@ def main():
                      + ", " + launch_kind,
                      "kernel_avg_ms": k_avg_ms, "flops_per_launch": flops_launch},
         "viterbi_lattice": lat,
+        "device": device_info(torch),
     }
     if args.ablation_mc > 0:
         out["kernel_ablation"] = kernel_ablation(torch, smsq, args.ablation_mc)

@@ -688,6 +688,7 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int, trai
     flops_full = sum(S.PRESETS[f][2] * (flops_per_iteration(n, 1, dims[f], f) +
                                         (T - 1) * flops_per_iteration(n, n, dims[f], f)) for (f, n, T, _) in spec)
     plan, Jfull, t_full, _, _ = LI.run(mx, 1.0, tune=True)
+    print("batched: plain at L, %.2f s" % t_full, file=sys.stderr, flush=True)
     info = plan.info()
     del plan
     fracs = (0.25, 0.5, 0.75)
@@ -695,6 +696,7 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int, trai
     for f in fracs:
         _, J, t, _, _ = LI.run(mx, f, warm=False)
         plain[f] = (J, t)
+        print("batched: plain at %g L, %.2f s" % (f, t), file=sys.stderr, flush=True)
     # the converged reference: the plain method at twice the iterations
     _, J2, t2, _, _ = LI.run(mx, 2.0, warm=False)
     plain[2.0] = (J2, t2)
@@ -707,6 +709,7 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int, trai
     n_examples = len(ex)
     mlp = smsq.InitMLP(seed=5, max_batch=max(4096, count))
     losses = LI.train(mlp, tmodels, ex, steps=train_steps, batch=512, lr=1e-3, log_every=train_steps // 4)
+    print("batched: proposal trained, NLL %.3f" % losses[-1], file=sys.stderr, flush=True)
     del tplan, ex
     gain = LI.choose_gate(mlp, LI.mix(64, seed=3, T_lo=50, T_hi=200), 0.5)
     gate = {f: g["use"] for f, g in gain.items()}
@@ -715,6 +718,7 @@ def batched_mix(torch, smsq, count: int, train_steps: int, train_seqs: int, trai
     for f in fracs + (1.0,):
         _, J, t, _, _ = LI.run(mx, f, mlp=mlp, gate=gate, warm=False)
         learned[f] = (J, t)
+        print("batched: learned at %g L, %.2f s" % (f, t), file=sys.stderr, flush=True)
     Lp = LI.iterations_to_match({f: v[0] for f, v in plain.items() if f <= 1.0}, Jfull, spec)
     Ll = LI.iterations_to_match({f: v[0] for f, v in learned.items()}, Jfull, spec)
     # against the converged reference (plain at 2 L); a sequence that no run

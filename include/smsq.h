@@ -252,6 +252,22 @@ smsq_status_t smsq_backtrack(smsq_dtype_t dtype, int batch, int T, int n, int d,
                              void *logpost_out, const void *particles, const void *x0,
                              void *xmap_out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Backtracking (Sec. IV-B; Algorithm 2, step 4) of one sequence whose
+ * particle count changes from step to step.  n_t (host) [T+1]: n_t[0] = 1
+ * (the known x_0), 1 <= n_t[t] <= n_max for t = 1..T.  psi [T, n_max]
+ * (device, int32): entries 0..n_t[t]-1 of row t-1 hold psi_t, indices into
+ * step t-1's n_t[t-1] particles (row 0 is never read).  phi_T [n_t[T]]
+ * (device).  Outputs idx_out [T] (device; entry t-1 is i_t, i_T = the lowest
+ * argmax of phi_T) and logpost_out [1] = phi_T(i_T).  A back-pointer outside
+ * [0, n_t[t-1]) or a non-finite J sets SMSQ_ERR_NONFINITE in the workspace
+ * status (the walk goes on from index 0).  The counts are copied into the
+ * workspace, which needs 256 + 4 (T + 1) bytes; n_t may be freed when the
+ * call returns (not for stream capture: the copy is from pageable memory).
+ * Errors: SMSQ_ERR_INVALID (sizes, counts or pointers), SMSQ_ERR_WORKSPACE. */
+smsq_status_t smsq_backtrack_steps(smsq_dtype_t dtype, int T, const int *n_t, int n_max, const int32_t *psi,
+                                   const void *phi_T, int32_t *idx_out, void *logpost_out, void *ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
 /* One step of Algorithm 2 for `batch` independent sequences that share a
  * model and sizes, in one launch: initial particles, n_iter SVGD iterations
  * and the forward recursion.

@@ -1201,6 +1201,29 @@ smsq_status_t smsq_backtrack(smsq_dtype_t dtype, int batch, int T, int n, int d,
     return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
 }
 
+smsq_status_t smsq_backtrack_steps(smsq_dtype_t dtype, int T, const int *n_t, int n_max, const int32_t *psi,
+                                   const void *phi_T, int32_t *idx_out, void *logpost_out, void *ws,
+                                   size_t ws_bytes, hipStream_t stream)
+{
+    if (!dtype_ok(dtype) || T < 1 || n_max < 1 || !n_t || !psi || !phi_T || !idx_out || !logpost_out)
+        return SMSQ_ERR_INVALID;
+    if (n_t[0] != 1) return SMSQ_ERR_INVALID;
+    for (int t = 1; t <= T; ++t)
+        if (n_t[t] < 1 || n_t[t] > n_max) return SMSQ_ERR_INVALID;
+    const size_t need = kHeader + sizeof(int) * ((size_t)T + 1);
+    if (!ws || ws_bytes < need) return SMSQ_ERR_WORKSPACE;
+    int *cnt = reinterpret_cast<int *>(static_cast<unsigned char *>(ws) + kHeader);
+    if (hipMemcpyAsync(cnt, n_t, sizeof(int) * ((size_t)T + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SMSQ_ERR_HIP;
+    if (dtype == SMSQ_F64)
+        hipLaunchKernelGGL(k_backtrack_steps<double>, dim3(1), dim3(kWave), 0, stream, T, cnt, n_max, psi,
+                           (const double *)phi_T, idx_out, (double *)logpost_out, status_ptr(ws));
+    else
+        hipLaunchKernelGGL(k_backtrack_steps<float>, dim3(1), dim3(kWave), 0, stream, T, cnt, n_max, psi,
+                           (const float *)phi_T, idx_out, (float *)logpost_out, status_ptr(ws));
+    return hipGetLastError() == hipSuccess ? SMSQ_OK : SMSQ_ERR_HIP;
+}
+
 smsq_status_t smsq_batch_step(smsq_model_t model, smsq_dtype_t dtype, int batch, int t, int n_prev,
                               const void *x_prev, long x_prev_stride, const void *phi_prev, const void *z,
                               long z_stride, const uint8_t *z_mask, long mask_stride, int n, void *x,

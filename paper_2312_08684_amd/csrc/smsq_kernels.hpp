@@ -1198,6 +1198,38 @@ __global__ __launch_bounds__(kRowsWaves * kWave) void k_viterbi_particle_rows(
 // ---------------------------------------------------------------------------
 // Backtracking: one workgroup (one wave) per sequence.
 // ---------------------------------------------------------------------------
+// One sequence with a particle count per step: cnt [T + 1] (cnt[0] = 1),
+// psi rows of stride n_max; i_T = lowest argmax of phi_T over cnt[T].
+template <typename T>
+__global__ __launch_bounds__(64) void k_backtrack_steps(int T_, const int *__restrict__ cnt, int n_max,
+                                                        const int32_t *__restrict__ psi,
+                                                        const T *__restrict__ phi_T, int32_t *idx,
+                                                        T *logpost, uint32_t *status)
+{
+    using R = RealOps<T>;
+    const int lane = threadIdx.x;
+    const int n = cnt[T_];
+    ArgBest<T> ab{-R::inf(), -R::inf(), 0x7fffffff};   // the same reduction as k_backtrack
+    for (int i = lane; i < n; i += kWave) {
+        const T v = phi_T[i];
+        if (i == lane) { ab.best = v; ab.arg = i; }
+        else argbest_push(ab, v, i);
+    }
+    ab = wave_argbest(ab);
+    if (lane != 0) return;
+    const T best = ab.best;
+    int cur = ab.arg;
+    idx[T_ - 1] = cur;
+    for (int t = T_; t >= 2; --t) {
+        int prev = psi[(long)(t - 1) * n_max + cur];
+        if (prev < 0 || prev >= cnt[t - 1]) { atomicOr(status, STATUS_NONFINITE); prev = 0; }
+        idx[t - 2] = prev;
+        cur = prev;
+    }
+    logpost[0] = best;
+    if (!R::finite(best)) atomicOr(status, STATUS_NONFINITE);
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_backtrack(int T_, int n, int d, const int32_t *__restrict__ psi,
                                                   long psi_bstride, const T *__restrict__ phi_T,

@@ -31,6 +31,7 @@ SYMBOLS = [
     "smsq_init_set_create", "smsq_init_set_destroy", "smsq_init_features", "smsq_init_mlp_forward",
     "smsq_init_mlp_backward", "smsq_init_mixture_nll", "smsq_init_mlp_train_step", "smsq_init_mlp_sample",
     "smsq_batch_plan_set_init", "smsq_run_sequence_noalloc", "smsq_viterbi_lattice_batch",
+    "smsq_backtrack_steps",
 ]
 
 
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
                                  vp, vp, C.c_size_t, vp]
     L.smsq_viterbi_step.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
                                     dbl, vp, C.c_size_t, vp]
+    L.smsq_backtrack_steps.argtypes = [i32, i32, C.POINTER(C.c_int), i32, vp, vp, vp, vp, vp, C.c_size_t, vp]
     L.smsq_backtrack.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
                                  C.c_size_t, vp]
     L.smsq_batch_step.argtypes = [vp, i32, i32, i32, i32, vp, i64, vp, vp, i64, vp, i64, i32, vp,
@@ -345,6 +347,28 @@ def backtrack(dtype, psi: torch.Tensor, phi_T: torch.Tensor, particles=None, x0=
                                _stream(stream))
     _check(st, "smsq_backtrack")
     return idx, J, xmap
+
+
+def backtrack_steps(dtype, psi: torch.Tensor, phi_T: torch.Tensor, n_t, ws: Optional[torch.Tensor] = None,
+                    stream=None):
+    """Backtracking of one sequence whose particle count changes by step:
+    psi [T, n_max] int32 (row t-1: psi_t in its first n_t[t] entries), phi_T
+    [n_t[T]], n_t the T + 1 counts (n_t[0] = 1).  Returns (idx [T], J [1])."""
+    td = torch_dtype(dtype)
+    T, n_max = psi.shape
+    counts = [int(c) for c in n_t]
+    if len(counts) != T + 1:
+        raise ValueError("n_t needs T + 1 = %d counts, got %d" % (T + 1, len(counts)))
+    dev = psi.device
+    idx = torch.empty(T, dtype=torch.int32, device=dev)
+    J = torch.empty(1, dtype=td, device=dev)
+    ws = workspace(HEADER_BYTES + 4 * (T + 1), device=dev) if ws is None else ws
+    arr = (C.c_int * (T + 1))(*counts)
+    st = load().smsq_backtrack_steps(_dt(dtype), T, arr, n_max, _ptr(psi, torch.int32, "psi"),
+                                     _ptr(phi_T, td, "phi_T"), _ptr(idx), _ptr(J), _ptr(ws, torch.uint8, "ws"),
+                                     ws.numel(), _stream(stream))
+    _check(st, "smsq_backtrack_steps")
+    return idx, J
 
 
 def _batched(t: Optional[torch.Tensor], dtype: Optional[torch.dtype], name: str):

@@ -82,3 +82,25 @@ def test_viterbi_step_out_tensors_validated_host_only():
         except ValueError as e:
             assert "_out" in str(e)
     m.close()
+
+
+def test_backtrack_steps_validates_counts_host_only():
+    """smsq_backtrack_steps checks its sizes, counts (n_t[0] = 1, 1..n_max)
+    and workspace size before any device work; the stand-in addresses below
+    are never dereferenced."""
+    L = smsq.load()
+    fake = C.c_void_p(0x1000)
+
+    def call(counts, n_max=8, T=None, ws_bytes=None):
+        T = len(counts) - 1 if T is None else T
+        arr = (C.c_int * max(1, len(counts)))(*counts)
+        wb = smsq.HEADER_BYTES + 4 * (T + 1) if ws_bytes is None else ws_bytes
+        return L.smsq_backtrack_steps(smsq.F32, T, arr, n_max, fake, fake, fake, fake, fake, wb, None)
+
+    assert call([1, 3, 8, 2], T=0) == smsq.ERR_INVALID          # T >= 1
+    assert call([2, 3, 8, 2]) == smsq.ERR_INVALID              # n_0 = 1
+    assert call([1, 3, 9, 2]) == smsq.ERR_INVALID              # above n_max
+    assert call([1, 3, 0, 2]) == smsq.ERR_INVALID              # at least one particle
+    assert call([1, 3, 8, 2], n_max=0) == smsq.ERR_INVALID
+    assert call([1, 3, 8, 2], ws_bytes=smsq.HEADER_BYTES + 15) == smsq.ERR_WORKSPACE
+    assert L.smsq_backtrack_steps(smsq.F32, 3, None, 8, fake, fake, fake, fake, fake, 512, None) == smsq.ERR_INVALID

@@ -274,6 +274,67 @@ def test_backtrack_bit_exact(dt):
         assert np.array_equal(xmap[b, 1:], want.astype(np.float32) if dt == "f32" else want)
 
 
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("case", ["ragged", "ties", "all_neg_inf", "one_step", "uniform"])
+def test_backtrack_steps_bit_exact(dt, case):
+    """Backtracking with a particle count per step (n_t[0] = 1).  The walk
+    reads only entries i < n_t[t] of row t-1, so the oracle's uniform
+    backtrack over rows padded to n_max (padding phi_T with -inf, psi with 0)
+    gives the same path; padding entries of the device psi hold indices out
+    of range, which a walk that strayed into them would flag."""
+    announce("backtrack_steps", dt, case)
+    rng = np.random.default_rng({"ragged": 21, "ties": 22, "all_neg_inf": 23, "one_step": 24, "uniform": 25}[case])
+    T = 1 if case == "one_step" else 37
+    n_max = 300
+    if case == "uniform":
+        counts = [1] + [n_max] * T
+    else:
+        counts = [1] + [int(c) for c in rng.integers(1, n_max + 1, size=T)]
+        counts[-1] = max(counts[-1], 5)
+    psi = np.full((T, n_max), n_max + 7, dtype=np.int32)        # padding: out of range
+    for t in range(1, T + 1):
+        psi[t - 1, :counts[t]] = rng.integers(0, counts[t - 1], size=counts[t])
+    nT = counts[T]
+    phi_T = rng.normal(size=nT)
+    if case == "ties":
+        phi_T[[1, 4]] = phi_T.max() + 1.0
+    if case == "all_neg_inf":
+        phi_T[:] = -np.inf
+    if dt == "f32":
+        phi_T = phi_T.astype(np.float32).astype(np.float64)
+    td = tdt(dt)
+    ws = smsq.workspace(smsq.HEADER_BYTES + 4 * (T + 1))
+    idx, J = smsq.backtrack_steps(dt, dev(psi, torch.int32), dev(phi_T, td), counts, ws=ws)
+    idx, J = host(idx), host(J)
+    pad_psi = np.where(psi >= n_max, 0, psi).astype(np.int32)
+    pad_phi = np.concatenate([phi_T, np.full(n_max - nT, -np.inf)])
+    ii, jj, st = O.backtrack(pad_psi, pad_phi)
+    assert np.array_equal(idx, ii), case
+    assert J[0] == (np.float32(jj) if dt == "f32" else jj)
+    for t in range(1, T + 1):
+        assert 0 <= idx[t - 1] < counts[t]
+    want = smsq.ERR_NONFINITE if case == "all_neg_inf" else smsq.OK
+    assert smsq.device_status(ws) == want
+    if case == "uniform":   # equal counts: the same path as the uniform entry point
+        i2, J2, _ = smsq.backtrack(dt, dev(psi, torch.int32), dev(phi_T, td))
+        assert np.array_equal(host(i2)[0], idx) and host(J2)[0] == J[0]
+
+
+def test_backtrack_steps_flags_out_of_range_pointer():
+    """A back-pointer at or beyond the previous step's count (but inside the
+    row) is reported through the workspace status; the walk goes on from 0."""
+    announce("backtrack_steps", "f64", "bad pointer")
+    T, n_max = 4, 16
+    counts = [1, 3, 8, 5, 6]
+    psi = np.zeros((T, n_max), dtype=np.int32)
+    psi[3, :6] = 7            # step 4 points at index 7 of step 3, which holds 5 particles
+    phi_T = np.arange(6, dtype=np.float64)
+    ws = smsq.workspace(smsq.HEADER_BYTES + 4 * (T + 1))
+    idx, J = smsq.backtrack_steps("f64", dev(psi, torch.int32), dev(phi_T, torch.float64), counts, ws=ws)
+    assert smsq.device_status(ws) == smsq.ERR_NONFINITE
+    assert host(idx).tolist() == [0, 0, 0, 5] and host(J)[0] == 5.0
+
+
 @pytest.mark.parametrize("n,n_prev", [(4000, 4000), (2000, 1999), (1, 3000), (2500, 1), (777, 1025),
                                       (8200, 600), (33, 5000)])
 @pytest.mark.parametrize("dt", ["f32", "f64"])

@@ -208,7 +208,7 @@ smsq_status_t smsq_svgd_step(smsq_model_t model, smsq_dtype_t dtype, int t,
  * ignored (may be NULL).  Particle mode (lattice == NULL): A and loglik are
  * computed from x_prev [n_prev, d], x [n, d] and z_t over the whole chip
  * (rows i spread over workgroups, each holding the n_prev transition means
- * in LDS).  FP32 states of d <= 8 and FP64 of d <= 2 take 4..16 rows per
+ * in LDS).  FP32 states of d <= 8 and FP64 of d <= 4 take 4..16 rows per
  * workgroup pass (with or without tie flags) and rank c_ij in log2 units
  * (c_ij log2 e, one fused multiply-subtract per coordinate; equal scores
  * are equal in that form), in (d + 1) * n_prev element slots with n_prev

@@ -426,9 +426,12 @@ template <typename T> long rows_lds_bytes(int n, int n_prev, int d)
 }
 constexpr long kRowsStaticLds = 6144;   // row-merge slots, runner-ups, observation (FP64: 5472 bytes), rounded up
 
-// states for which the 16-rows kernel runs without register spills (its
-// eight-edge tiles); the others take the two-waves-per-row kernel
-template <typename T> constexpr bool rows_fits(int d) { return sizeof(T) == 4 ? d <= 8 : d <= 2; }
+// states the rows kernel takes: FP32 up to 8 dimensions (no register
+// spills); FP64 up to 4, where it still beats the two-waves-per-row kernel
+// although from d = 3 it spills (measured, back-to-back launches: clutter
+// model N = 512 15.9 against 21.9 us, pose model N = 1000 20.0 against 20.7;
+// the 7-D arm at N = 1024 29.8 against 25.5, so d > 4 keeps the other kernel)
+template <typename T> constexpr bool rows_fits(int d) { return sizeof(T) == 4 ? d <= 8 : d <= 4; }
 
 template <typename T, int KIND, int D, int RP, bool FLAGS>
 smsq_status_t launch_viterbi_rows_rp(const smsq_model_desc_t &d, int t, int n, int n_prev, const void *x_prev,

@@ -374,6 +374,39 @@ def test_viterbi_particle_mode_large(n, n_prev, dt, flags):
     assert err.max() <= (1e-4 if dt == "f32" else 1e-12)
 
 
+@pytest.mark.parametrize("name,n,n_prev", [("cv4d", 2000, 1999), ("cv4d", 777, 1025), ("scenario_b", 1000, 1000),
+                                           ("cv4d", 33, 2040)])
+@pytest.mark.parametrize("flags", [True, False])
+def test_viterbi_particle_f64_rows_wider_states(name, n, n_prev, flags):
+    """FP64 states of 3 and 4 dimensions on the rows kernel at sizes that
+    span several row passes, table chunks and a ragged last tile: psi equal
+    on every row the oracle does not flag as a near tie, phi to 1e-12."""
+    announce("viterbi particle f64 rows", name, n, n_prev, flags)
+    wl, desc, xp, x = _particle_case(name, n, n_prev, 8)
+    assert desc.d in (3, 4)
+    z = wl.z[0, 1]
+    mask = None if wl.mask is None else wl.mask[0, 1]
+    phi_prev = np.random.default_rng(9).normal(size=n_prev) * 3
+    tol = 1e-9
+    phi_o, psi_o, fl_o, st = O.viterbi_particle(desc, 2, xp, phi_prev, z, mask, x, tie_tol=tol)
+    assert st == O.OK
+    ws = smsq.workspace()
+    phi, psi, fl = smsq.viterbi_step(smsq.Model(desc), "f64", 2, dev(phi_prev, torch.float64),
+                                     x_prev=dev(xp, torch.float64), z_t=dev(z, torch.float64),
+                                     z_mask=None if mask is None else dev(mask, torch.uint8),
+                                     x=dev(x, torch.float64), tie_tol=tol, ws=ws, want_flags=flags)
+    assert smsq.device_status(ws) == smsq.OK
+    psi, phi = host(psi), host(phi)
+    sure = fl_o == 0
+    assert np.array_equal(psi[sure], psi_o[sure])
+    err = np.abs(phi - phi_o) / np.maximum(1, np.abs(phi_o))
+    print("d %d phi rel err %.3e, sure rows %.3f" % (desc.d, err.max(), sure.mean()))
+    assert err.max() <= 1e-12
+    if flags:
+        clear = np.abs(host(fl).astype(int) - fl_o.astype(int)) == 0
+        assert clear.mean() > 0.99
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_viterbi_step_out_tensors(dt):
     """phi_out / psi_out (a row of a [T, n] back-pointer array) receive the
